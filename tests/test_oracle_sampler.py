@@ -1,0 +1,153 @@
+"""Pins of the oracle's MLS^2MC sampler (Sec. 4) against closed forms.
+
+* Linear-Gaussian model G_l(theta) = (A + 2^{-2l} E) theta with a N(0, I)
+  prior: the posterior on the finest level is Gaussian with covariance
+  (I + A^T A / s^2)^{-1} and the evidence has a closed form (Sec. 2.1).
+* The number of forward evaluations per level follows the cost model of
+  Prop. 4.4, adapted to n pCN steps per stage and the J_tilde look-ahead
+  evaluations of Sec. 4.4.
+* With l_min = l_max the sampler is single-level SMC (Example 4.1).
+* A PDE model with K = 1 has a posterior computable by quadrature.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests import inputs
+
+
+def _lin_problem(K=3, nobs=4, s=0.2, seed=0):
+    g = inputs.rng(seed)
+    A = g.standard_normal((nobs, K))
+    E = g.standard_normal((nobs, K))
+    th = g.standard_normal(K)
+    y = A @ th + s * g.standard_normal(nobs)
+    return A, E, y
+
+
+def _lin_posterior(A, y, s):
+    K = A.shape[1]
+    P = np.eye(K) + A.T @ A / s ** 2
+    C = np.linalg.inv(P)
+    m = C @ A.T @ y / s ** 2
+    G = s ** 2 * np.eye(len(y)) + A @ A.T
+    logZ = -0.5 * np.linalg.slogdet(P)[1] - 0.5 * y @ np.linalg.solve(G, y)
+    return m, C, logZ
+
+
+def _expected_solves(r, J, Jt, n_mcmc, l_min):
+    ex = np.zeros(16, dtype=np.int64)
+    ex[l_min] += J
+    for typ, lev, z in zip(r["stage_type"], r["stage_level"], r["stage_zeta"]):
+        if typ in (0, 1):
+            ex[lev] += n_mcmc * J
+            if typ == 1:
+                ex[lev + 1] += Jt
+        else:
+            if typ in (2, 3):
+                ex[lev] += J  # first evaluation of all particles on the finer level
+            ex[lev] += n_mcmc * J
+            if z < 1.0:
+                ex[lev - 1] += n_mcmc * J
+    return ex
+
+
+@pytest.mark.slow
+def test_linear_gaussian_single_level_posterior_and_evidence():
+    s = 0.2
+    A, E, y = _lin_problem(s=s)
+    m, C, logZ = _lin_posterior(A + 2.0 ** -6 * E, y, s)
+    R, J = 8, 2000
+    means, vars_, lz = [], [], []
+    for seed in range(R):
+        r = oracle.run_sampler(y, model="linear", l_min=3, l_max=3, K=3, nobs=4, sigma_n=s, J=J,
+                               seed=seed, lin_A=A, lin_E=E, n_mcmc=5)
+        assert np.all(r["stage_type"] == 0)  # single-level SMC
+        means.append(r["theta"].mean(0))
+        vars_.append(r["theta"].var(0))
+        lz.append(r["log_Z"])
+    means, vars_, lz = map(np.array, (means, vars_, lz))
+    se = means.std(0, ddof=1) / np.sqrt(R)
+    assert np.all(np.abs(means.mean(0) - m) < 4 * se + 0.02 * np.sqrt(np.diag(C))), (means.mean(0), m)
+    np.testing.assert_allclose(vars_.mean(0), np.diag(C), rtol=0.1)
+    assert abs(lz.mean() - logZ) < 4 * lz.std(ddof=1) / np.sqrt(R) + 0.05, (lz.mean(), logZ)
+
+
+@pytest.mark.slow
+def test_linear_gaussian_multilevel_posterior():
+    s = 0.15
+    A, E, y = _lin_problem(K=2, nobs=3, s=s, seed=3)
+    E = 30.0 * E  # strong level dependence: coarse levels are poor models
+    m, C, logZ = _lin_posterior(A + 2.0 ** -10 * E, y, s)
+    R, J = 8, 2000
+    means, lz = [], []
+    kinds = set()
+    for seed in range(R):
+        r = oracle.run_sampler(y, model="linear", l_min=2, l_max=5, K=2, nobs=3, sigma_n=s, J=J,
+                               J_tilde=100, seed=100 + seed, lin_A=A, lin_E=E)
+        assert r["final_level"] == 5 and r["final_beta"] == 1.0
+        kinds |= set(r["stage_type"].tolist())
+        means.append(r["theta"].mean(0))
+        lz.append(r["log_Z"])
+        ex = _expected_solves(r, J, 100, 5, 2)
+        np.testing.assert_array_equal(np.array(r["solves"]), ex)
+    # bridging path (posterior at level 5 is A + 2^-10 E)
+    means, lz = np.array(means), np.array(lz)
+    se = means.std(0, ddof=1) / np.sqrt(R)
+    assert np.all(np.abs(means.mean(0) - m) < 4 * se + 0.03 * np.sqrt(np.diag(C))), (means.mean(0), m)
+    assert abs(lz.mean() - logZ) < 4 * lz.std(ddof=1) / np.sqrt(R) + 0.1
+    assert 0 in kinds and (2 in kinds or 3 in kinds)
+
+
+def test_first_update_is_tempering_and_levels_monotone():
+    s = 0.3
+    A, E, y = _lin_problem(seed=5)
+    r = oracle.run_sampler(y, model="linear", l_min=1, l_max=4, K=3, nobs=4, sigma_n=s, J=300,
+                           J_tilde=50, seed=1, lin_A=A, lin_E=10 * E)
+    assert r["stage_type"][0] == 0 and r["stage_level"][0] == 1
+    assert np.all(np.diff(r["stage_level"]) >= 0)
+    b = r["stage_beta"]
+    assert np.all(np.diff(b) >= 0) and b[-1] == 1.0
+    # every tempering update right after a level update is taken without a look-ahead
+    t = r["stage_type"]
+    for i in range(1, len(t)):
+        if t[i] in (0, 1) and t[i - 1] in (2, 3, 4):
+            assert t[i] == 0
+    np.testing.assert_array_equal(np.array(r["solves"]), _expected_solves(r, 300, 50, 5, 1))
+
+
+def test_deterministic_replay():
+    A, E, y = _lin_problem(seed=6)
+    kw = dict(model="linear", l_min=1, l_max=3, K=3, nobs=4, sigma_n=0.3, J=200, J_tilde=40,
+              seed=9, lin_A=A, lin_E=E)
+    r1 = oracle.run_sampler(y, **kw)
+    r2 = oracle.run_sampler(y, **kw)
+    np.testing.assert_array_equal(r1["theta"], r2["theta"])
+    assert r1["log_Z"] == r2["log_Z"]
+
+
+@pytest.mark.slow
+def test_pde_brute_force_posterior_k1():
+    # K = 1 on the real PDE at h = 1/8: posterior mean and variance by
+    # quadrature on a fine grid against the SMC estimate
+    l, K, m, sn = 3, 1, 3, 0.02
+    th_true = np.array([[0.8]])
+    y = oracle.forward(l, K, 1.0, 0.3, m, th_true)[0] + sn * inputs.rng(0).standard_normal(m * m)
+    grid = np.linspace(-6, 6, 4001)
+    G = oracle.forward(l, K, 1.0, 0.3, m, grid[:, None])
+    phi = 0.5 * (((G - y) / sn) ** 2).sum(1)
+    lp = -phi - 0.5 * grid ** 2
+    wq = np.exp(lp - lp.max())
+    wq /= wq.sum()
+    mq = (wq * grid).sum()
+    vq = (wq * (grid - mq) ** 2).sum()
+    R, J = 6, 1500
+    ms, vs = [], []
+    for seed in range(R):
+        r = oracle.run_sampler(y, l_min=l, l_max=l, K=K, m=m, sigma_n=sn, J=J, seed=seed)
+        ms.append(r["theta"].mean())
+        vs.append(r["theta"].var())
+    ms = np.array(ms)
+    se = ms.std(ddof=1) / np.sqrt(R)
+    assert abs(ms.mean() - mq) < 4 * se + 0.02 * np.sqrt(vq), (ms.mean(), mq, se)
+    assert abs(np.mean(vs) / vq - 1) < 0.15, (np.mean(vs), vq)
