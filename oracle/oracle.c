@@ -163,7 +163,7 @@ int orc_kl_modes_2d(int K, double sigma2, double corr_len, double* lambda, int* 
         for (int i = 0; i < nm; ++i)
             for (int j = 0; j < nm; ++j) {
                 orc_mode* md = &all[(size_t)i * nm + j];
-                md->lam = sigma2 * mu[i] * mu[j];
+                md->lam = sigma2 * (mu[i] * mu[j]); /* exact (i,j)/(j,i) ties */
                 md->i = i; md->j = j;
             }
         qsort(all, (size_t)nm * nm, sizeof(orc_mode), orc_mode_cmp);

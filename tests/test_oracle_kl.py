@@ -87,15 +87,18 @@ def test_2d_modes_order_and_products():
     lam, ix, iy, ox, oy = oracle.kl_modes_2d(K, s2, corr)
     om, mu = oracle.kl_roots_1d(K, corr)
     assert np.all(np.diff(lam) <= 0)
-    np.testing.assert_array_equal(lam, s2 * mu[ix] * mu[iy])
+    np.testing.assert_array_equal(lam, s2 * (mu[ix] * mu[iy]))
     np.testing.assert_array_equal(ox, om[ix])
     # the K largest products of all pairs, as a multiset
-    allp = np.sort((s2 * mu[:, None] * mu[None, :]).ravel())[::-1][:K]
+    allp = np.sort((s2 * (mu[:, None] * mu[None, :])).ravel())[::-1][:K]
     np.testing.assert_array_equal(np.sort(lam)[::-1], allp)
     # exact ties (i,j)/(j,i): smaller i first
+    ties = 0
     for k in range(K - 1):
         if lam[k] == lam[k + 1]:
             assert ix[k] < ix[k + 1]
+            ties += 1
+    assert ties >= K // 3  # the (i,j)/(j,i) pairs tie exactly
     assert ix[0] == 0 and iy[0] == 0
 
 
