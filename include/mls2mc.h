@@ -1,0 +1,243 @@
+/*
+ * mls2mc.h - C ABI of the MI355X (gfx950) library for the hot path of
+ * Multilevel Sequential^2 Monte Carlo (Latz, Papaioannou, Ullmann,
+ * "Multilevel Sequential^2 Monte Carlo for Bayesian Inverse Problems",
+ * J. Comp. Phys.).
+ *
+ * The forward model is the one of the paper's Sec. 5: the log-permeability
+ * theta(x) is a truncated Karhunen-Loeve expansion with N(0,1) coefficients,
+ * kappa = exp(theta), and -div(kappa grad p) = f on (0,1)^2 with p = 0 on the
+ * boundary and f = 1, discretised by P1 elements on the uniform mesh with
+ * 2 n^2 triangles, n = 2^l; the observations are point values of p.  The
+ * sampler pieces are those of Secs. 2-4: the Gaussian potential, the
+ * ESS-adaptive tempering / bridging step, resampling and the Markov move
+ * (here pCN).
+ *
+ * Conventions for every call:
+ *  - Return value: MLS2MC_OK (0) or a positive status code below.  On error
+ *    mls2mc_last_error() returns a message (thread-local, valid until the
+ *    next call on the same thread).  No C++ exception crosses the ABI.
+ *  - Array arguments are DEVICE pointers (memory of the context's GPU, e.g.
+ *    from hipMalloc or a torch CUDA tensor) unless marked "host".  They are
+ *    owned by the caller, contiguous, row-major and particle-major, and must
+ *    stay valid until the work on `stream` has completed.  The library never
+ *    frees caller memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work on it and return without waiting, except where stated.  Device
+ *    scratch owned by the context is reused across calls, so calls on one
+ *    context must not run concurrently on different streams.
+ *  - Random numbers are inputs (normals, uniforms), except in mls2mc_run,
+ *    which draws them with Philox4x32-10 keyed by the seed.
+ *
+ * Element ordering on level l (n = 2^l): cell (i,j), 0 <= i,j < n, is cut by
+ * the diagonal from node (i,j) to (i+1,j+1); element 2(j n + i) is the lower
+ * triangle {(i,j),(i+1,j),(i+1,j+1)}, element 2(j n + i)+1 the upper
+ * triangle {(i,j),(i+1,j+1),(i,j+1)}; n_e(l) = 2 n^2.  Interior unknowns
+ * (i,j), 1 <= i,j <= n-1, are ordered (j-1)(n-1)+(i-1); M(l) = (n-1)^2.
+ * Observation o = (b-1) m + (a-1) is the point (a/(m+1), b/(m+1)).
+ */
+#ifndef MLS2MC_H
+#define MLS2MC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define MLS2MC_OK 0
+#define MLS2MC_EINVAL 1    /* bad shape, pointer, level or value           */
+#define MLS2MC_ENOMEM 2    /* device or host allocation failed             */
+#define MLS2MC_EDEVICE 3   /* a HIP runtime call failed                    */
+#define MLS2MC_ENOTCONV 4  /* a solve did not converge or was non-finite   */
+#define MLS2MC_ESINGULAR 5 /* all weights vanished / ESS collapse          */
+
+/* ---- precision forms ---- */
+#define MLS2MC_FP64 0  /* FP64 KL GEMM (MFMA), FP64 multigrid-PCG        */
+#define MLS2MC_MIXED 1 /* BF16 KL GEMM (MFMA, FP32 accumulation), FP32
+                          stencil/smoothing/inner PCG, FP64 residual and
+                          iterative refinement, FP64 coarsest solve       */
+
+/* ---- kinds of mls2mc_kl_field output ---- */
+#define MLS2MC_FIELD_LOG_F64 0   /* a = theta B (double)                   */
+#define MLS2MC_FIELD_KAPPA_F64 1 /* kappa = exp(a) (double)                */
+#define MLS2MC_FIELD_KAPPA_F32 2 /* kappa = exp(a), BF16 GEMM (float)      */
+
+typedef struct mls2mc_ctx mls2mc_ctx;
+
+typedef struct {
+    int l_min, l_max;  /* levels used, 1 <= l_min <= l_max <= 10 (h = 2^-l)  */
+    int K;             /* KL terms, 1 <= K <= 512                            */
+    double sigma2;     /* prior field variance (> 0)                         */
+    double corr_len;   /* correlation length of the separable exponential
+                          covariance sigma2 exp(-|dx1|/c) exp(-|dx2|/c)      */
+    int m;             /* observation grid side, N_obs = m*m, 1 <= m <= 32   */
+    double sigma_n;    /* noise standard deviation, Gamma = sigma_n^2 I (> 0)*/
+    int precision;     /* MLS2MC_FP64 or MLS2MC_MIXED                        */
+    double rtol;       /* relative solver tolerance on the preconditioned
+                          residual norm; 0 selects 1e-11 (FP64) / 1e-10
+                          (MIXED, after refinement)                         */
+    int max_iters;     /* PCG iteration cap; 0 selects 200                   */
+} mls2mc_problem;
+
+/* Create a context on the current HIP device: builds the KL modes (roots of
+ * the 1-D eigen-equation, Sec. 5 truncated KL expansion), the basis tables
+ * B_l[k, e] = sqrt(lambda_k) phi_k(centroid_e) for l_min..l_max on the GPU,
+ * and the observation tables.  *out receives the context.  Synchronous.    */
+int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out);
+/* Free the context and all its device memory.  Synchronous.  NULL is OK.   */
+int mls2mc_destroy(mls2mc_ctx* ctx);
+const char* mls2mc_last_error(void);
+/* library version string, e.g. "mls2mc 1.0 gfx950"                         */
+const char* mls2mc_version(void);
+
+/* Observation count and level sizes (host queries).                        */
+int mls2mc_n_obs(const mls2mc_ctx* ctx);
+int64_t mls2mc_n_elem(int l);     /* 2 * 4^l                              */
+int64_t mls2mc_n_unknowns(int l); /* (2^l - 1)^2                          */
+
+/* KL field (Sec. 5, truncated KL expansion; Sec. 2.2 discretisation):
+ * out[q, e] = sum_k theta[q, k] B_l[k, e] for q < N, e < n_e(l), evaluated
+ * at the element centroids, as a GEMM on the matrix cores.  theta: N x K
+ * double.  kind selects the output: the log-field (double), kappa = exp(a)
+ * (double), or kappa from the BF16 GEMM with FP32 accumulation (float).
+ * Returns EINVAL for l outside [l_min, l_max], N < 0 or NULL pointers with
+ * N > 0.                                                                   */
+int mls2mc_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void* out,
+                    int kind, void* stream);
+
+/* Forward response G_l(theta) = O(p) (Sec. 2.1 forward response operator;
+ * Sec. 5 model): KL field, kappa = exp(a), solve A_l(kappa) p = b with
+ * multigrid-preconditioned CG, observe p at the N_obs points.
+ * theta: N x K double; G_out: N x N_obs double.
+ * status_out (N int8, may be NULL): 0 converged, 1 not converged within
+ * max_iters, 2 non-finite.  iters_out (N int32, may be NULL): PCG
+ * iterations (MIXED: inner iterations summed over refinement sweeps).
+ * Returns EINVAL on bad arguments; non-convergence is reported only through
+ * status_out (the call itself returns OK).                                 */
+int mls2mc_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G_out,
+                   int8_t* status_out, int32_t* iters_out, void* stream);
+
+/* Forward response from a given coefficient batch (skips the KL field):
+ * kappa: N x n_e(l) double, one positive value per element; G_out as above;
+ * p_out (N x M(l) double, may be NULL) receives the nodal solution.        */
+int mls2mc_forward_field(mls2mc_ctx* ctx, int l, int64_t N, const double* kappa,
+                         double* G_out, double* p_out, int8_t* status_out,
+                         int32_t* iters_out, void* stream);
+
+/* Potential (Sec. 2.1): phi_out[q] = 1/2 sum_o ((y_o - G[q,o]) / sigma_n)^2.
+ * G: N x N_obs, y: N_obs, phi_out: N (all double, device).                 */
+int mls2mc_loglik(mls2mc_ctx* ctx, int64_t N, const double* G, const double* y,
+                  double* phi_out, void* stream);
+
+/* Adaptive step (Sec. 3.4, the argmin of (ESS - tau_ESS)^2 over the next
+ * inverse temperature; tempering Sec. 3.1, bridging Sec. 3.2 and 4.1).
+ * Incremental log-weights lw_j(t) = -t * scale * d_j with t = next - cur:
+ * tempering: d = Phi_l, scale = 1, cur = beta; bridging: d = Phi_{l+1} -
+ * Phi_l, scale = beta, cur = zeta.  ESS(t) = (sum e^lw)^2 / sum e^{2 lw}.
+ * The chosen t is 1 - cur if ESS(1 - cur) >= tau_ess, else min(eps, 1-cur)
+ * if ESS there is <= tau_ess, else the result of 64 bisection steps keeping
+ * ESS(lo) >= tau_ess > ESS(hi) (lo returned).
+ * Outputs (device): out3 = {next, dlogZ, ess} (3 doubles; next is exactly
+ * 1.0 at the right end; dlogZ = LSE(lw) - log N); logw_out (N, may be NULL);
+ * w_out (N, normalised weights exp(lw - LSE), may be NULL).
+ * d: N doubles, finite (a non-finite entry gives next = NaN in out3).
+ * Requires 0 <= cur < 1, eps > 0, 1 <= N <= 2^26.                          */
+int mls2mc_next_step(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, double cur,
+                     double tau_ess, double eps, double* out3, double* logw_out,
+                     double* w_out, void* stream);
+
+/* Multinomial resampling (Sec. 2.4) with an exact integer CDF: weights are
+ * scaled by the power of two that brings max w into [1/2,1), quantised to
+ * q_j = floor(w_j 2^(62 - ceil(log2 N))), prefix-summed in uint64; for each
+ * uniform u_i, t_i = floor(u_i 2^53 * C_N / 2^53) and anc[i] = min{j :
+ * C_j > t_i}.  Bit-exact for given (w, u).  w: N doubles >= 0, not all
+ * zero, any scale; u: N doubles in [0,1), multiples of 2^-53; anc_out: N
+ * int32.  1 <= N <= 2^26.  Invalid weights give anc = -1 for every i.       */
+int mls2mc_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u,
+                    int32_t* anc_out, void* stream);
+
+/* Gather rows by ancestor: dst[i, :] = src[anc[i], :] for i < N, ncols
+ * doubles per row; src has n_src rows; an ancestor outside [0, n_src) gives
+ * a row of NaN.  src and dst must not overlap.                             */
+int mls2mc_gather(mls2mc_ctx* ctx, int64_t N, int64_t ncols, const int32_t* anc,
+                  int64_t n_src, const double* src, double* dst, void* stream);
+
+/* One pCN Metropolis-Hastings step (Markov move of Sec. 2.4; pCN as cited in
+ * Secs. 1 and 5) for the target exp(-Psi) times the N(0, I) prior,
+ * Psi = beta [(1 - zeta) Phi_{l_lo} + zeta Phi_{l_hi}].  Tempering: l_lo ==
+ * l_hi (zeta ignored).  Bridging: l_hi = l_lo + 1; the coarse level is
+ * evaluated only while zeta < 1.
+ * theta' = sqrt(1 - s^2) theta + s xi;  accept iff log u < -(Psi' - Psi).
+ * In/out state (device, double): theta N x K, G_lo / G_hi N x N_obs,
+ * phi_lo / phi_hi N (caches of the current state; G_hi/phi_hi may be NULL
+ * for tempering).  y: N_obs data.  xi: N x K normals; u: N uniforms in
+ * (0,1).  accepted_out: N uint8 (may be NULL).  A proposal whose solve
+ * fails (status != 0) is rejected.                                         */
+typedef struct {
+    int l_lo, l_hi;
+    double beta, zeta;
+    double s;          /* pCN step size, 0 < s <= 1 */
+} mls2mc_stage;
+
+int mls2mc_pcn_step(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, double* theta,
+                    double* G_lo, double* G_hi, double* phi_lo, double* phi_hi,
+                    const double* y, const double* xi, const double* u,
+                    uint8_t* accepted_out, void* stream);
+
+/* ---- the whole MLS^2MC sampler (Sec. 4, update scheme of Sec. 4.4) ---- */
+typedef struct {
+    int64_t J;          /* particles, 1 <= J <= 2^26                        */
+    int64_t J_tilde;    /* look-ahead particles for cv^LU, 1..J (0 = min(100,J)) */
+    double tau_star;    /* target cv: tau_ESS = J / (1 + tau_star^2)         */
+    double tau_lu;      /* level-update threshold (0 = tau_star)             */
+    double eps;         /* minimum temperature increment (0 = 1e-6)          */
+    int n_mcmc;         /* pCN steps per stage                              */
+    double s_pcn;       /* pCN step size                                    */
+    uint64_t seed;      /* Philox key                                       */
+    int max_stages;     /* safety cap (0 = 4000)                            */
+} mls2mc_run_config;
+
+typedef struct {
+    int n_stages;
+    int final_level;
+    double final_beta;
+    double log_Z;          /* sum over reweightings of LSE(lw) - log J       */
+    int64_t solves[16];    /* forward solves per level                       */
+    int64_t accepted, proposed;
+    int64_t iters_total;   /* PCG iterations summed over all solves          */
+    int64_t not_converged; /* solves reported with status != 0               */
+    double seconds;        /* wall time of the run (host clock)              */
+    /* optional per-stage log (host arrays of max_stage_log entries, or NULL).
+     * stage types: 0 tempering, 1 tempering after a discarded look-ahead,
+     * 2 first bridging sub-step of a level update chosen by the look-ahead,
+     * 3 first bridging sub-step of a level update forced at beta = 1,
+     * 4 later bridging sub-step                                             */
+    int max_stage_log;
+    int* stage_type;
+    int* stage_level;
+    double* stage_beta;
+    double* stage_zeta;
+    double* stage_ess;
+    double* stage_acc_rate;
+} mls2mc_run_result;
+
+/* Run MLS^2MC from the prior to beta = 1 on level l_max.  y: N_obs data
+ * (device).  theta_out: J x K final particles (device, equally weighted).
+ * Synchronous (returns when done).  Random streams (Philox4x32-10, counter
+ * = {index, sub-step, stage, stream}, key = seed): 0 prior draw, 3
+ * resampling uniforms, 4 pCN normals, 5 pCN uniforms.                      */
+int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const double* y,
+               double* theta_out, mls2mc_run_result* res, void* stream);
+
+/* Philox4x32-10 uniforms/normals on the device, the same streams mls2mc_run
+ * uses: out[i] for idx = i, counter {idx, sub, stage, stream}.  normal = 0:
+ * uniform in [0,1) (multiple of 2^-53); normal = 1: Box-Muller normal.      */
+int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint32_t stage,
+                       uint32_t sub, int64_t n, int normal, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

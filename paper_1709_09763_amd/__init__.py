@@ -1,0 +1,16 @@
+"""MI355X (gfx950) implementation of the hot path of Multilevel Sequential^2
+Monte Carlo (Latz, Papaioannou, Ullmann, J. Comp. Phys.).
+
+The compute lives in the HIP library ``libmls2mc.so`` (C ABI declared in
+``include/mls2mc.h``).  This package is a thin ctypes binding with the same
+names: it checks tensor shapes and dtypes, passes device pointers and the
+current HIP stream, and raises on a non-zero status.  PyTorch provides device
+memory and streams only.
+"""
+from ._lib import (  # noqa: F401
+    FIELD_KAPPA_F32, FIELD_KAPPA_F64, FIELD_LOG_F64, FP64, MIXED, Context, Mls2mcError,
+    Problem, RunConfig, lib, library_path, mls2mc_create, mls2mc_destroy, mls2mc_forward,
+    mls2mc_forward_field, mls2mc_gather, mls2mc_kl_field, mls2mc_last_error, mls2mc_loglik,
+    mls2mc_n_elem, mls2mc_n_obs, mls2mc_n_unknowns, mls2mc_next_step, mls2mc_pcn_step,
+    mls2mc_philox_fill, mls2mc_resample, mls2mc_run, mls2mc_version,
+)

@@ -1,0 +1,334 @@
+"""ctypes binding of libmls2mc.so.  Argument marshalling only."""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libmls2mc.so")
+
+FP64, MIXED = 0, 1
+FIELD_LOG_F64, FIELD_KAPPA_F64, FIELD_KAPPA_F32 = 0, 1, 2
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV", 5: "ESINGULAR"}
+
+
+class Mls2mcError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__(f"{where}: {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("l_min", C.c_int), ("l_max", C.c_int), ("K", C.c_int), ("sigma2", C.c_double),
+                ("corr_len", C.c_double), ("m", C.c_int), ("sigma_n", C.c_double),
+                ("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int)]
+
+
+class Stage(C.Structure):
+    _fields_ = [("l_lo", C.c_int), ("l_hi", C.c_int), ("beta", C.c_double), ("zeta", C.c_double),
+                ("s", C.c_double)]
+
+
+class RunConfig(C.Structure):
+    _fields_ = [("J", C.c_int64), ("J_tilde", C.c_int64), ("tau_star", C.c_double),
+                ("tau_lu", C.c_double), ("eps", C.c_double), ("n_mcmc", C.c_int),
+                ("s_pcn", C.c_double), ("seed", C.c_uint64), ("max_stages", C.c_int)]
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class RunResult(C.Structure):
+    _fields_ = [("n_stages", C.c_int), ("final_level", C.c_int), ("final_beta", C.c_double),
+                ("log_Z", C.c_double), ("solves", C.c_int64 * 16), ("accepted", C.c_int64),
+                ("proposed", C.c_int64), ("iters_total", C.c_int64), ("not_converged", C.c_int64),
+                ("seconds", C.c_double), ("max_stage_log", C.c_int), ("stage_type", _ip),
+                ("stage_level", _ip), ("stage_beta", _dp), ("stage_zeta", _dp),
+                ("stage_ess", _dp), ("stage_acc_rate", _dp)]
+
+
+_lib = None
+_vp = C.c_void_p
+
+
+def lib():
+    """Load libmls2mc.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise ImportError(f"{library_path} is missing: build the HIP library first "
+                              "(python paper_1709_09763_amd/build.py or __graft_entry__.build())")
+        L = C.CDLL(library_path)
+        L.mls2mc_last_error.restype = C.c_char_p
+        L.mls2mc_version.restype = C.c_char_p
+        L.mls2mc_n_elem.restype = C.c_int64
+        L.mls2mc_n_elem.argtypes = [C.c_int]
+        L.mls2mc_n_unknowns.restype = C.c_int64
+        L.mls2mc_n_unknowns.argtypes = [C.c_int]
+        L.mls2mc_n_obs.argtypes = [_vp]
+        L.mls2mc_create.argtypes = [C.POINTER(Problem), C.POINTER(_vp)]
+        L.mls2mc_destroy.argtypes = [_vp]
+        L.mls2mc_kl_field.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp, C.c_int, _vp]
+        L.mls2mc_forward.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+        L.mls2mc_forward_field.argtypes = [_vp, C.c_int, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.mls2mc_loglik.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp]
+        L.mls2mc_next_step.argtypes = [_vp, C.c_int64, _vp, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, _vp, _vp, _vp, _vp]
+        L.mls2mc_resample.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp]
+        L.mls2mc_gather.argtypes = [_vp, C.c_int64, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp]
+        L.mls2mc_pcn_step.argtypes = [_vp, C.POINTER(Stage), C.c_int64, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, _vp, _vp]
+        L.mls2mc_run.argtypes = [_vp, C.POINTER(RunConfig), _vp, _vp, C.POINTER(RunResult), _vp]
+        L.mls2mc_philox_fill.argtypes = [_vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                         C.c_int64, C.c_int, _vp, _vp]
+        _lib = L
+    return _lib
+
+
+def mls2mc_last_error():
+    return lib().mls2mc_last_error().decode()
+
+
+def mls2mc_version():
+    return lib().mls2mc_version().decode()
+
+
+def mls2mc_n_elem(l):
+    return lib().mls2mc_n_elem(l)
+
+
+def mls2mc_n_unknowns(l):
+    return lib().mls2mc_n_unknowns(l)
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise Mls2mcError(rc, where, mls2mc_last_error())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="tensor", optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def mls2mc_create(problem: Problem):
+    h = C.c_void_p()
+    _check(lib().mls2mc_create(C.byref(problem), C.byref(h)), "mls2mc_create")
+    return h
+
+
+def mls2mc_destroy(h):
+    _check(lib().mls2mc_destroy(h), "mls2mc_destroy")
+
+
+def mls2mc_n_obs(h):
+    return lib().mls2mc_n_obs(h)
+
+
+def mls2mc_kl_field(h, l, theta, out, kind):
+    N = theta.shape[0]
+    dt = torch.float32 if kind == FIELD_KAPPA_F32 else torch.float64
+    _check(lib().mls2mc_kl_field(h, l, N, _ptr(theta, torch.float64, name="theta"),
+                                 _ptr(out, dt, (N, mls2mc_n_elem(l)), "out"), kind, _stream()),
+           "mls2mc_kl_field")
+
+
+def mls2mc_forward(h, l, theta, G_out, status_out=None, iters_out=None):
+    N = theta.shape[0]
+    _check(lib().mls2mc_forward(h, l, N, _ptr(theta, torch.float64, name="theta"),
+                                _ptr(G_out, torch.float64, (N, mls2mc_n_obs(h)), "G_out"),
+                                _ptr(status_out, torch.int8, (N,), "status_out", True),
+                                _ptr(iters_out, torch.int32, (N,), "iters_out", True), _stream()),
+           "mls2mc_forward")
+
+
+def mls2mc_forward_field(h, l, kappa, G_out, p_out=None, status_out=None, iters_out=None):
+    N = kappa.shape[0]
+    _check(lib().mls2mc_forward_field(
+        h, l, N, _ptr(kappa, torch.float64, (N, mls2mc_n_elem(l)), "kappa"),
+        _ptr(G_out, torch.float64, (N, mls2mc_n_obs(h)), "G_out"),
+        _ptr(p_out, torch.float64, (N, mls2mc_n_unknowns(l)), "p_out", True),
+        _ptr(status_out, torch.int8, (N,), "status_out", True),
+        _ptr(iters_out, torch.int32, (N,), "iters_out", True), _stream()), "mls2mc_forward_field")
+
+
+def mls2mc_loglik(h, G, y, phi_out):
+    N = G.shape[0]
+    _check(lib().mls2mc_loglik(h, N, _ptr(G, torch.float64, name="G"),
+                               _ptr(y, torch.float64, (mls2mc_n_obs(h),), "y"),
+                               _ptr(phi_out, torch.float64, (N,), "phi_out"), _stream()),
+           "mls2mc_loglik")
+
+
+def mls2mc_next_step(h, d, scale, cur, tau_ess, eps, out3, logw_out=None, w_out=None):
+    N = d.shape[0]
+    _check(lib().mls2mc_next_step(h, N, _ptr(d, torch.float64, (N,), "d"), scale, cur, tau_ess,
+                                  eps, _ptr(out3, torch.float64, (3,), "out3"),
+                                  _ptr(logw_out, torch.float64, (N,), "logw_out", True),
+                                  _ptr(w_out, torch.float64, (N,), "w_out", True), _stream()),
+           "mls2mc_next_step")
+
+
+def mls2mc_resample(h, w, u, anc_out):
+    N = w.shape[0]
+    _check(lib().mls2mc_resample(h, N, _ptr(w, torch.float64, (N,), "w"),
+                                 _ptr(u, torch.float64, (N,), "u"),
+                                 _ptr(anc_out, torch.int32, (N,), "anc_out"), _stream()),
+           "mls2mc_resample")
+
+
+def mls2mc_gather(h, anc, src, dst):
+    N = anc.shape[0]
+    ncols = src.shape[1] if src.dim() == 2 else 1
+    _check(lib().mls2mc_gather(h, N, ncols, _ptr(anc, torch.int32, (N,), "anc"), src.shape[0],
+                               _ptr(src, torch.float64, name="src"),
+                               _ptr(dst, torch.float64, name="dst"), _stream()), "mls2mc_gather")
+
+
+def mls2mc_philox_fill(h, seed, stream_id, stage, sub, out, normal):
+    _check(lib().mls2mc_philox_fill(h, seed, stream_id, stage, sub, out.numel(), int(normal),
+                                    _ptr(out, torch.float64, name="out"), _stream()),
+           "mls2mc_philox_fill")
+
+
+def mls2mc_pcn_step(h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u,
+                    accepted_out=None):
+    N = theta.shape[0]
+    st = Stage(l_lo, l_hi, beta, zeta, s)
+    f64 = torch.float64
+    _check(lib().mls2mc_pcn_step(
+        h, C.byref(st), N, _ptr(theta, f64, name="theta"), _ptr(G_lo, f64, name="G_lo", optional=True),
+        _ptr(G_hi, f64, name="G_hi", optional=True), _ptr(phi_lo, f64, name="phi_lo", optional=True),
+        _ptr(phi_hi, f64, name="phi_hi", optional=True), _ptr(y, f64, name="y"),
+        _ptr(xi, f64, name="xi"), _ptr(u, f64, name="u"),
+        _ptr(accepted_out, torch.uint8, (N,), "accepted_out", True), _stream()), "mls2mc_pcn_step")
+
+
+def mls2mc_run(h, cfg: RunConfig, y, theta_out, max_stage_log=4000):
+    import numpy as np
+    res = RunResult()
+    ms = max_stage_log
+    arrs = dict(stage_type=np.zeros(ms, np.int32), stage_level=np.zeros(ms, np.int32),
+                stage_beta=np.zeros(ms), stage_zeta=np.zeros(ms), stage_ess=np.zeros(ms),
+                stage_acc_rate=np.zeros(ms))
+    res.max_stage_log = ms
+    res.stage_type = arrs["stage_type"].ctypes.data_as(_ip)
+    res.stage_level = arrs["stage_level"].ctypes.data_as(_ip)
+    for k in ("stage_beta", "stage_zeta", "stage_ess", "stage_acc_rate"):
+        setattr(res, k, arrs[k].ctypes.data_as(_dp))
+    _check(lib().mls2mc_run(h, C.byref(cfg), _ptr(y, torch.float64, name="y"),
+                            _ptr(theta_out, torch.float64, name="theta_out"), C.byref(res),
+                            _stream()), "mls2mc_run")
+    n = min(res.n_stages, ms)
+    out = dict(n_stages=res.n_stages, final_level=res.final_level, final_beta=res.final_beta,
+               log_Z=res.log_Z, solves=list(res.solves), accepted=res.accepted,
+               proposed=res.proposed, iters_total=res.iters_total,
+               not_converged=res.not_converged, seconds=res.seconds)
+    for k, v in arrs.items():
+        out[k] = v[:n].copy()
+    return out
+
+
+class Context:
+    """Owns one library context; methods mirror the C entry points."""
+
+    def __init__(self, l_min, l_max, K, sigma2=1.0, corr_len=0.3, m=3, sigma_n=0.01,
+                 precision=FP64, rtol=0.0, max_iters=0):
+        self.problem = Problem(l_min, l_max, K, sigma2, corr_len, m, sigma_n, precision, rtol,
+                               max_iters)
+        self.K = K
+        self.h = mls2mc_create(self.problem)
+        self.nobs = mls2mc_n_obs(self.h)
+
+    def close(self):
+        if self.h is not None:
+            mls2mc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def kl_field(self, l, theta, kind=FIELD_LOG_F64):
+        dt = torch.float32 if kind == FIELD_KAPPA_F32 else torch.float64
+        out = torch.empty((theta.shape[0], mls2mc_n_elem(l)), dtype=dt, device=theta.device)
+        mls2mc_kl_field(self.h, l, theta, out, kind)
+        return out
+
+    def forward(self, l, theta, with_stats=False):
+        N = theta.shape[0]
+        G = torch.empty((N, self.nobs), dtype=torch.float64, device=theta.device)
+        st = torch.empty(N, dtype=torch.int8, device=theta.device)
+        it = torch.empty(N, dtype=torch.int32, device=theta.device)
+        mls2mc_forward(self.h, l, theta, G, st, it)
+        return (G, st, it) if with_stats else G
+
+    def forward_field(self, l, kappa, want_p=False):
+        N = kappa.shape[0]
+        dev = kappa.device
+        G = torch.empty((N, self.nobs), dtype=torch.float64, device=dev)
+        p = torch.empty((N, mls2mc_n_unknowns(l)), dtype=torch.float64, device=dev) if want_p else None
+        st = torch.empty(N, dtype=torch.int8, device=dev)
+        it = torch.empty(N, dtype=torch.int32, device=dev)
+        mls2mc_forward_field(self.h, l, kappa, G, p, st, it)
+        return G, p, st, it
+
+    def loglik(self, G, y):
+        phi = torch.empty(G.shape[0], dtype=torch.float64, device=G.device)
+        mls2mc_loglik(self.h, G, y, phi)
+        return phi
+
+    def next_step(self, d, scale, cur, tau_ess, eps=1e-6):
+        N = d.shape[0]
+        out3 = torch.empty(3, dtype=torch.float64, device=d.device)
+        logw = torch.empty(N, dtype=torch.float64, device=d.device)
+        w = torch.empty(N, dtype=torch.float64, device=d.device)
+        mls2mc_next_step(self.h, d, scale, cur, tau_ess, eps, out3, logw, w)
+        return out3, logw, w
+
+    def resample(self, w, u):
+        anc = torch.empty(w.shape[0], dtype=torch.int32, device=w.device)
+        mls2mc_resample(self.h, w, u, anc)
+        return anc
+
+    def gather(self, anc, src):
+        dst = torch.empty((anc.shape[0],) + tuple(src.shape[1:]), dtype=src.dtype, device=src.device)
+        mls2mc_gather(self.h, anc, src, dst)
+        return dst
+
+    def philox(self, seed, stream_id, stage, sub, n, normal, device="cuda"):
+        out = torch.empty(n, dtype=torch.float64, device=device)
+        mls2mc_philox_fill(self.h, seed, stream_id, stage, sub, out, normal)
+        return out
+
+    def pcn_step(self, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u):
+        acc = torch.empty(theta.shape[0], dtype=torch.uint8, device=theta.device)
+        mls2mc_pcn_step(self.h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y,
+                        xi, u, acc)
+        return acc
+
+    def run(self, y, J, J_tilde=0, tau_star=1.0, tau_lu=0.0, eps=0.0, n_mcmc=5, s_pcn=0.5, seed=0,
+            max_stages=0):
+        cfg = RunConfig(J, J_tilde, tau_star, tau_lu, eps, n_mcmc, s_pcn, seed, max_stages)
+        theta = torch.empty((J, self.K), dtype=torch.float64, device=y.device)
+        out = mls2mc_run(self.h, cfg, y, theta)
+        out["theta"] = theta
+        return out

@@ -1,0 +1,282 @@
+// Truncated Karhunen-Loeve field of the prior (Sec. 5, truncated KL
+// expansion; Sec. 2.2, parameter discretisation) for the separable
+// exponential covariance sigma2 exp(-|dx1|/c) exp(-|dx2|/c), evaluated at the
+// element centroids as a GEMM  A[N x n_e] = Theta[N x K] B_l[K x n_e]  on the
+// CDNA4 matrix cores.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "common.h"
+
+namespace mls {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- modes --
+// 1-D eigenpairs on [0,1] of exp(-|s-t|/corr): with c = 1/corr the
+// eigenfunctions are (w/c) cos(wt) + sin(wt) where w solves
+// (w^2 - c^2) sin w = 2 c w cos w, one root in each ((n-1) pi, n pi), and the
+// eigenvalue is 2c / (w^2 + c^2).  Roots by safeguarded Newton.
+static double kl_root(int n, double c)
+{
+    auto g = [c](double w) { return (w * w - c * c) * std::sin(w) - 2.0 * c * w * std::cos(w); };
+    auto dg = [c](double w) {
+        return (2.0 * w + 2.0 * c * w) * std::sin(w) + (w * w - c * c - 2.0 * c) * std::cos(w);
+    };
+    double lo = (n - 1) * M_PI, hi = n * M_PI;
+    double glo = (n == 1) ? -1.0 : g(lo);  // g < 0 just above 0
+    double w = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double gw = g(w);
+        if (gw == 0.0) break;
+        if ((gw < 0) == (glo < 0)) lo = w; else hi = w;
+        double step = gw / dg(w);
+        double wn = w - step;
+        if (!(wn > lo && wn < hi)) wn = 0.5 * (lo + hi);
+        if (std::fabs(wn - w) <= 4e-16 * w) { w = wn; break; }
+        w = wn;
+    }
+    return w;
+}
+
+// Gauss-Legendre nodes/weights on [-1,1] by Newton on P_n.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wt)
+{
+    x.resize(n);
+    wt.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                x[i] = z;
+                wt[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                break;
+            }
+        }
+    }
+}
+
+// L2(0,1) norm of (a cos wt + sin wt) by composite Gauss-Legendre.
+static double l2_norm_1d(double w, double a, const std::vector<double>& gx,
+                         const std::vector<double>& gw)
+{
+    int nsub = 4 + (int)std::ceil(w / 2.0);
+    double h = 1.0 / nsub, s = 0.0;
+    for (int q = 0; q < nsub; ++q)
+        for (size_t i = 0; i < gx.size(); ++i) {
+            double t = (q + 0.5 * (gx[i] + 1.0)) * h;
+            double v = a * std::cos(w * t) + std::sin(w * t);
+            s += 0.5 * h * gw[i] * v * v;
+        }
+    return std::sqrt(s);
+}
+
+__global__ void kl_basis_kernel(const double* __restrict__ modes, int K, int l, int64_t ne,
+                                double* __restrict__ B, __hip_bfloat16* __restrict__ Bt16,
+                                int Kp)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (e >= ne) return;
+    const int n = 1 << l;
+    const int64_t cell = e >> 1;
+    const int i = (int)(cell & (n - 1)), j = (int)(cell >> l);
+    double x, y;
+    if ((e & 1) == 0) {
+        x = (double)(3 * i + 2) / (double)(3 * n);
+        y = (double)(3 * j + 1) / (double)(3 * n);
+    } else {
+        x = (double)(3 * i + 1) / (double)(3 * n);
+        y = (double)(3 * j + 2) / (double)(3 * n);
+    }
+    const double* m = modes + 7 * k;  // sqrt_lam, wx, wy, ax, ay, ix, iy
+    double fx = (m[3] * cos(m[1] * x) + sin(m[1] * x)) * m[5];
+    double fy = (m[4] * cos(m[2] * y) + sin(m[2] * y)) * m[6];
+    double v = m[0] * fx * fy;
+    B[(int64_t)k * ne + e] = v;
+    if (Bt16) Bt16[e * Kp + k] = __float2bfloat16((float)v);
+}
+
+int build_kl_tables(mls2mc_ctx* ctx)
+{
+    const mls2mc_problem& p = ctx->prob;
+    const int K = p.K;
+    const double c = 1.0 / p.corr_len;
+    const int nm = K;  // 1-D modes needed at most
+    std::vector<double> om(nm), mu(nm);
+    for (int n = 1; n <= nm; ++n) {
+        om[n - 1] = kl_root(n, c);
+        mu[n - 1] = 2.0 * c / (om[n - 1] * om[n - 1] + c * c);
+    }
+    // first K products, descending; exact (i,j)/(j,i) ties -> smaller i first
+    struct Pair { double v; int i, j; };
+    std::vector<Pair> all;
+    all.reserve((size_t)nm * nm);
+    for (int i = 0; i < nm; ++i)
+        for (int j = 0; j < nm; ++j) all.push_back({mu[i] * mu[j], i, j});
+    std::partial_sort(all.begin(), all.begin() + K, all.end(), [](const Pair& a, const Pair& b) {
+        if (a.v != b.v) return a.v > b.v;
+        if (a.i != b.i) return a.i < b.i;
+        return a.j < b.j;
+    });
+    std::vector<double> gx, gw;
+    gauss_legendre(24, gx, gw);
+    std::vector<double> inv(nm);
+    for (int n = 0; n < nm; ++n) inv[n] = 1.0 / l2_norm_1d(om[n], om[n] / c, gx, gw);
+    ctx->sqrt_lam.resize(K);
+    ctx->om_x.resize(K); ctx->om_y.resize(K);
+    ctx->amp_x.resize(K); ctx->amp_y.resize(K);
+    ctx->inv_x.resize(K); ctx->inv_y.resize(K);
+    std::vector<double> modes(7 * (size_t)K);
+    for (int k = 0; k < K; ++k) {
+        const Pair& q = all[k];
+        ctx->sqrt_lam[k] = std::sqrt(p.sigma2 * q.v);
+        ctx->om_x[k] = om[q.i]; ctx->om_y[k] = om[q.j];
+        ctx->amp_x[k] = om[q.i] / c; ctx->amp_y[k] = om[q.j] / c;
+        ctx->inv_x[k] = inv[q.i]; ctx->inv_y[k] = inv[q.j];
+        double* m = &modes[7 * (size_t)k];
+        m[0] = ctx->sqrt_lam[k]; m[1] = ctx->om_x[k]; m[2] = ctx->om_y[k];
+        m[3] = ctx->amp_x[k]; m[4] = ctx->amp_y[k]; m[5] = ctx->inv_x[k]; m[6] = ctx->inv_y[k];
+    }
+    MLS_CHECK_HIP(hipMalloc(&ctx->d_modes, sizeof(double) * modes.size()));
+    MLS_CHECK_HIP(hipMemcpy(ctx->d_modes, modes.data(), sizeof(double) * modes.size(),
+                            hipMemcpyHostToDevice));
+    const int Kp = (K + 31) / 32 * 32;
+    for (int l = p.l_min; l <= p.l_max; ++l) {
+        const int64_t ne = n_elem(l);
+        MLS_CHECK_HIP(hipMalloc(&ctx->d_B[l], sizeof(double) * (size_t)K * ne));
+        if (p.precision == MLS2MC_MIXED) {
+            MLS_CHECK_HIP(hipMalloc(&ctx->d_B16[l], sizeof(__hip_bfloat16) * (size_t)Kp * ne));
+            MLS_CHECK_HIP(hipMemset(ctx->d_B16[l], 0, sizeof(__hip_bfloat16) * (size_t)Kp * ne));
+        }
+        dim3 grid((unsigned)((ne + 255) / 256), (unsigned)K);
+        kl_basis_kernel<<<grid, 256>>>(ctx->d_modes, K, l, ne, ctx->d_B[l], ctx->d_B16[l], Kp);
+        MLS_CHECK_HIP(hipGetLastError());
+    }
+    MLS_CHECK_HIP(hipDeviceSynchronize());
+    return MLS2MC_OK;
+}
+
+// ----------------------------------------------------------------- GEMM --
+// FP64 on the matrix cores: v_mfma_f64_16x16x4f64.  A workgroup of four
+// waves computes a 64 (particles) x 64 (elements) tile; wave w owns rows
+// 16w..16w+15 and four 16x16 accumulators.  Operand lanes: A[i][k] with
+// i = lane%16, k = lane/16; B[k][j] with j = lane%16, k = lane/16.  Result:
+// lane holds D[lane/16 + 4v][lane%16], v = 0..3 (FP64 accumulator layout).
+template <bool EXP>
+__global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ theta,
+                                                   const double* __restrict__ B,
+                                                   double* __restrict__ out, int64_t N, int K,
+                                                   int64_t ne)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, kq = lane >> 4;
+    const int64_t e0 = (int64_t)blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.y * 64 + wv * 16;
+    const int64_t prow = p0 + r;
+    dbl4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + kq;
+        const double a = (prow < N && k < K) ? theta[prow * K + k] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t e = e0 + c * 16 + r;
+            const double b = (k < K && e < ne) ? B[(int64_t)k * ne + e] : 0.0;
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = p0 + kq + 4 * v, col = e0 + c * 16 + r;
+            if (row < N && col < ne) out[row * ne + col] = EXP ? exp(acc[c][v]) : acc[c][v];
+        }
+}
+
+// BF16 on the matrix cores with FP32 accumulation: v_mfma_f32_16x16x32_bf16.
+// Operand lanes: A[i][8*(lane/16) + 0..7] with i = lane%16 (theta rows,
+// rounded to BF16 here); B^T[j][8*(lane/16) + 0..7] with j = lane%16 (the
+// basis is stored transposed, n_e x Kp, K padded to 32 with zeros).
+// Output kappa = expf(a) in FP32.  Tile 64 x 64 as above.
+__global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ theta,
+                                                    const __hip_bfloat16* __restrict__ Bt,
+                                                    float* __restrict__ out, int64_t N, int K,
+                                                    int Kp, int64_t ne)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = lane & 15, kq = lane >> 4;
+    const int64_t e0 = (int64_t)blockIdx.x * 64;
+    const int64_t p0 = (int64_t)blockIdx.y * 64 + wv * 16;
+    const int64_t prow = p0 + r;
+    flt4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Kp; k0 += 32) {
+        bf16x8 a;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int k = k0 + 8 * kq + t;
+            const float v = (prow < N && k < K) ? (float)theta[prow * K + k] : 0.f;
+            a[t] = (__bf16)v;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t e = e0 + c * 16 + r;
+            bf16x8 b;
+            if (e < ne) {
+                b = *reinterpret_cast<const bf16x8*>(Bt + e * Kp + k0 + 8 * kq);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) b[t] = (__bf16)0.f;
+            }
+            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = p0 + 4 * kq + v, col = e0 + c * 16 + r;
+            if (row < N && col < ne) out[row * ne + col] = expf(acc[c][v]);
+        }
+}
+
+int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void* out, int kind,
+                    hipStream_t s)
+{
+    if (N == 0) return MLS2MC_OK;
+    const int64_t ne = n_elem(l);
+    const int K = ctx->prob.K;
+    MLS_REQUIRE((N + 63) / 64 <= 65535, "kl_field: N too large for one launch");
+    dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((N + 63) / 64));
+    if (kind == MLS2MC_FIELD_LOG_F64) {
+        kl_gemm_f64<false><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne);
+    } else if (kind == MLS2MC_FIELD_KAPPA_F64) {
+        kl_gemm_f64<true><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne);
+    } else if (kind == MLS2MC_FIELD_KAPPA_F32) {
+        MLS_REQUIRE(ctx->d_B16[l] != nullptr, "kl_field: BF16 basis needs precision MIXED");
+        const int Kp = (K + 31) / 32 * 32;
+        kl_gemm_bf16<<<grid, 256, 0, s>>>(theta, ctx->d_B16[l], (float*)out, N, K, Kp, ne);
+    } else {
+        MLS_REQUIRE(false, "kl_field: unknown output kind");
+    }
+    MLS_CHECK_HIP(hipGetLastError());
+    return MLS2MC_OK;
+}
+
+}  // namespace mls

@@ -1,0 +1,191 @@
+"""GPU parity of the sampler pieces (Secs. 2.1, 2.4, 3.1-3.4, 4.1, 4.4)
+against the CPU oracle on the same inputs: potential, adaptive next step,
+integer-CDF resampling (bit-exact), gather, Philox, pCN, and whole runs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1709_09763_amd as P
+from tests import inputs
+from tests.gpu_util import case, device, host, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    device()
+    c = P.Context(3, 5, 10, 1.0, 0.3, 3, 0.01)
+    yield c
+    c.close()
+
+
+def test_loglik_parity(ctx):
+    case("loglik N=333")
+    G = inputs.theta_batch(1, 333, 9)
+    y = inputs.theta_batch(2, 1, 9)[0]
+    phi = host(ctx.loglik(to_dev(G), to_dev(y)))
+    ref = np.array([oracle.potential(g, y, 0.01) for g in G])
+    assert rel_err(phi, ref) < 1e-14
+
+
+@pytest.mark.parametrize("N,scale,cur,kind", [
+    (200, 1.0, 0.0, "interior"), (1000, 1.0, 0.37, "interior"), (4097, 0.6, 0.1, "bridge"),
+    (50, 1.0, 0.99, "end"), (8192, 1.0, 0.0, "interior"), (1, 1.0, 0.0, "single"),
+])
+def test_next_step_parity(ctx, N, scale, cur, kind):
+    case(f"next_step N={N} {kind}")
+    d = inputs.potentials(N, N, scale=80.0)
+    if kind == "bridge":
+        d = d - d.mean()
+    if kind == "end":
+        d = 1e-3 * d
+    tau = N / 2.0
+    out3, logw, w = ctx.next_step(to_dev(d), scale, cur, tau, 1e-6)
+    o = host(out3)
+    ref = oracle.next_step(d, scale, cur, tau, 1e-6)
+    assert abs(o[0] - ref["next"]) <= 1e-12 * max(1e-6, ref["next"] - cur)
+    assert abs(o[1] - ref["dlogZ"]) < 1e-10 * max(1.0, abs(ref["dlogZ"]))
+    assert abs(o[2] - ref["ess"]) < 1e-8 * N
+    assert rel_err(host(w), ref["w"]) < 1e-10
+    if kind == "end":
+        assert o[0] == 1.0
+
+
+def test_next_step_minimum_step_and_nan(ctx):
+    case("next_step min step / NaN")
+    d = np.zeros(100)
+    d[1:] = 1e9
+    o = host(ctx.next_step(to_dev(d), 1.0, 0.0, 50.0, 1e-6)[0])
+    assert o[0] == 1e-6
+    d[5] = np.nan
+    o = host(ctx.next_step(to_dev(d), 1.0, 0.0, 50.0, 1e-6)[0])
+    assert np.isnan(o[0])
+
+
+@pytest.mark.parametrize("N,zero_frac", [(1, 0.0), (3, 0.0), (1000, 0.0), (1023, 0.3),
+                                          (8192, 0.1), (100003, 0.0)])
+def test_resample_bit_exact(ctx, N, zero_frac):
+    case(f"resample N={N}")
+    w = inputs.weights(N, N, spread=4.0, zero_frac=zero_frac)
+    if w.max() == 0:
+        w[0] = 1.0
+    u = inputs.uniforms53(N + 1, N)
+    anc = host(ctx.resample(to_dev(w), to_dev(u)))
+    np.testing.assert_array_equal(anc, oracle.resample(w, u))
+
+
+def test_resample_invalid_gives_minus_one(ctx):
+    case("resample invalid")
+    anc = host(ctx.resample(to_dev(np.zeros(10)), to_dev(np.zeros(10))))
+    assert (anc == -1).all()
+
+
+def test_gather(ctx):
+    case("gather")
+    src = inputs.theta_batch(3, 500, 7)
+    anc = inputs.rng(4).integers(0, 500, size=321).astype(np.int32)
+    anc[5] = 600  # out of range -> NaN row
+    out = host(ctx.gather(to_dev(anc, torch.int32), to_dev(src)))
+    ok = anc < 500
+    np.testing.assert_array_equal(out[ok], src[anc[ok]])
+    assert np.isnan(out[5]).all()
+
+
+def test_philox_matches_oracle(ctx):
+    case("philox fill")
+    n = 5000
+    u = host(ctx.philox(123, 3, 7, 2, n, normal=False))
+    uo = np.array([oracle.uniform(123, 3, 7, 2, i) for i in range(n)])
+    np.testing.assert_array_equal(u, uo)
+    z = host(ctx.philox(99, 4, 1, 3, n, normal=True))
+    zo = np.array([oracle.normal(99, 4, 1, 3, i) for i in range(n)])
+    assert np.abs(z - zo).max() < 1e-13
+
+
+@pytest.mark.parametrize("mode", ["temper", "bridge", "bridge_end"])
+def test_pcn_step_parity(ctx, mode):
+    case(f"pcn_step {mode}")
+    K, N, m, sn = 10, 150, 3, 0.01
+    l_lo, l_hi = (4, 4) if mode == "temper" else (4, 5)
+    beta, zeta = 0.2, (0.4 if mode == "bridge" else 1.0)
+    th = inputs.theta_batch(11, N, K)
+    y = oracle.forward(5, K, 1.0, 0.3, m, inputs.theta_batch(12, 1, K))[0] + sn * inputs.rng(1).standard_normal(9)
+    Glo = oracle.forward(l_lo, K, 1.0, 0.3, m, th)
+    Ghi = oracle.forward(l_hi, K, 1.0, 0.3, m, th)
+    plo = np.array([oracle.potential(g, y, sn) for g in Glo])
+    phi = np.array([oracle.potential(g, y, sn) for g in Ghi])
+    xi = inputs.theta_batch(13, N, K)
+    u = 1.0 - inputs.uniforms53(14, N)  # (0, 1]
+    # oracle step
+    thp = oracle.pcn_propose(th, xi, 0.5)
+    Glp = oracle.forward(l_lo, K, 1.0, 0.3, m, thp)
+    Ghp = oracle.forward(l_hi, K, 1.0, 0.3, m, thp)
+    plp = np.array([oracle.potential(g, y, sn) for g in Glp])
+    php = np.array([oracle.potential(g, y, sn) for g in Ghp])
+    if mode == "temper":
+        old, new = beta * plo, beta * plp
+    elif mode == "bridge":
+        old = beta * ((1 - zeta) * plo + zeta * phi)
+        new = beta * ((1 - zeta) * plp + zeta * php)
+    else:
+        old, new = beta * phi, beta * php
+    acc_ref = np.array([oracle.mh_accept(o, n_, uu) for o, n_, uu in zip(old, new, u)])
+    # GPU step
+    T, GL, GH = to_dev(th), to_dev(Glo), to_dev(Ghi)
+    PL, PH = to_dev(plo), to_dev(phi)
+    acc = host(ctx.pcn_step(l_lo, l_hi, beta, zeta, 0.5, T, GL, GH if l_hi != l_lo else None, PL,
+                            PH if l_hi != l_lo else None, to_dev(y), to_dev(xi), to_dev(u)))
+    np.testing.assert_array_equal(acc.astype(bool), acc_ref)
+    assert 0 < acc_ref.sum() < N  # both outcomes exercised
+    th_ref = np.where(acc_ref[:, None], thp, th)
+    assert rel_err(host(T), th_ref) < 1e-15
+    if mode != "bridge_end":
+        assert rel_err(host(GL), np.where(acc_ref[:, None], Glp, Glo)) < 1e-10
+    if mode != "temper":
+        assert rel_err(host(GH), np.where(acc_ref[:, None], Ghp, Ghi)) < 1e-10
+
+
+def _data(l, K, m, sn, seed=0):
+    th_true = inputs.theta_batch(1000 + seed, 1, K)
+    return oracle.forward(l, K, 1.0, 0.3, m, th_true)[0] + sn * inputs.rng(2000 + seed).standard_normal(m * m)
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(name="single-level SMC h=1/16", l_min=4, l_max=4, K=10, m=3, sn=0.01, J=200),
+    dict(name="MLS2MC h=1/8..1/32", l_min=3, l_max=5, K=10, m=3, sn=0.01, J=200),
+])
+def test_run_matches_oracle(cfg):
+    device()
+    case(f"run {cfg['name']}")
+    K, m, sn = cfg["K"], cfg["m"], cfg["sn"]
+    y = _data(cfg["l_max"], K, m, sn)
+    ctx = P.Context(cfg["l_min"], cfg["l_max"], K, 1.0, 0.3, m, sn)
+    g = ctx.run(to_dev(y), cfg["J"], J_tilde=min(100, cfg["J"]), tau_star=1.0, n_mcmc=5, s_pcn=0.5, seed=5)
+    r = oracle.run_sampler(y, l_min=cfg["l_min"], l_max=cfg["l_max"], K=K, m=m, sigma_n=sn, J=cfg["J"],
+                           J_tilde=min(100, cfg["J"]), seed=5, n_mcmc=5, s_pcn=0.5)
+    print(f"  stages gpu {g['n_stages']} oracle {r['n_stages']}, gpu {g['seconds']:.2f}s")
+    assert g["n_stages"] == r["n_stages"]
+    np.testing.assert_array_equal(g["stage_type"], r["stage_type"])
+    np.testing.assert_array_equal(g["stage_level"], r["stage_level"])
+    np.testing.assert_allclose(g["stage_beta"], r["stage_beta"], rtol=1e-8)
+    np.testing.assert_allclose(g["stage_zeta"], r["stage_zeta"], rtol=1e-8, atol=1e-12)
+    assert g["solves"] == r["solves"]
+    assert g["accepted"] == r["accepted"]
+    assert abs(g["log_Z"] - r["log_Z"]) < 1e-7 * max(1, abs(r["log_Z"]))
+    th = host(g["theta"])
+    assert rel_err(th.mean(0), r["theta"].mean(0)) < 1e-8
+    assert rel_err(th.var(0), r["theta"].var(0)) < 1e-8
+    assert g["not_converged"] == 0
+
+
+def test_run_is_deterministic():
+    device()
+    case("run determinism")
+    y = _data(4, 10, 3, 0.01)
+    ctx = P.Context(3, 4, 10, 1.0, 0.3, 3, 0.01)
+    a = ctx.run(to_dev(y), 128, seed=3)
+    b = ctx.run(to_dev(y), 128, seed=3)
+    assert torch.equal(a["theta"], b["theta"])
+    assert a["log_Z"] == b["log_Z"]
