@@ -1,0 +1,224 @@
+"""Benchmark of the MLS^2MC hot path on one MI355X.
+
+Workload (synthetic, seeded): MLS^2MC on levels h = 1/8 .. 1/64 (l = 3..6),
+K = 50 separable-exponential KL terms (sigma^2 = 1, correlation length 0.3),
+25 observations on a 5x5 interior grid, sigma_n = 0.005, J = 1000 particles,
+5 pCN steps per stage with s = 0.5, ESS target 0.5 J.
+
+A step is one SMC stage at the finest level (l = 6) over the whole particle
+batch: adaptive next temperature (log-sum-exp weights), integer-CDF
+resampling, gather, and 5 pCN steps, each proposal going through the KL
+field GEMM, the multigrid-PCG solve, the observations and the potential.
+`value` = forward solves/s at l = 6 inside these stages (5 J solves per
+step).  Extra fields: per-level solves/s of plain forward batches,
+time-to-posterior of the whole sampler (plain FP64 and mixed precision),
+the roofline of the solver kernel measured live with HIP events recorded by
+the library on its launch stream, and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic bytes per fine-level unknown per PCG iteration of the FP64
+# multigrid-PCG (PCG vector work + V(1,1) cycle, each array read once and
+# written once per sweep, coarse levels included)
+B_ITER_FP64 = 293.0
+B_ITER_MIXED = 147.0
+
+WL = dict(name="mls2mc h=1/8..1/64 K=50 Nobs=25 J=1000", l_min=3, l_max=6, K=50, m=5,
+          sigma_n=0.005, J=1000, corr=0.3, n_mcmc=5, s_pcn=0.5, tau_star=1.0)
+
+
+def solve_bytes(l, nobs, particles, iters, b_iter):
+    n = 1 << l
+    M = (n - 1) ** 2
+    n_e = 2 * n * n
+    setup = 8 * n_e + (4.0 / 3.0) * 2 * 2 * n * (n - 1) * 8
+    return particles * (setup + 8 * 4 * nobs) + iters * b_iter * M
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(l, K, m, corr, budget_s=12.0):
+    import numpy as np
+
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    rng = np.random.default_rng(7)
+    th = rng.standard_normal((2 * cores, K))
+    t0 = time.perf_counter()
+    oracle.forward(l, K, 1.0, corr, m, th, nthreads=cores)
+    t_cal = time.perf_counter() - t0
+    n = int(max(2 * cores, min(20000, 2 * cores * budget_s / max(t_cal, 1e-3))))
+    th = rng.standard_normal((n, K))
+    t0 = time.perf_counter()
+    oracle.forward(l, K, 1.0, corr, m, th, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="forward solves/s", cores=cores, kind="oracle",
+                sample=f"{n} forward solves at h=1/{1 << l}, K={K} (KL field, generic P1 "
+                       f"assembly, banded Cholesky, observation), OpenMP over particles, {dt:.1f}s")
+
+
+def copy_calibration(gib=2.0):
+    """plain device copy of known size, for scaling rocprofv3 byte counters"""
+    import torch
+    n = int(gib * (1 << 30) // 8)
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip per-level and time-to-posterior")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the particle axis would shard across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    dev = torch.device("cuda:0")
+    W = WL
+    K, m, J, l = W["K"], W["m"], W["J"], W["l_max"]
+    ctx = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"])
+    nobs = ctx.nobs
+    rng = np.random.default_rng(2024)
+    th_true = torch.tensor(rng.standard_normal((1, K)), device=dev)
+    y = ctx.forward(l, th_true)[0] + W["sigma_n"] * torch.tensor(rng.standard_normal(nobs), device=dev)
+    y = y.contiguous()
+
+    extras = {}
+    if not args.no_extras:
+        # time-to-posterior, plain FP64 (one untimed warm run first)
+        ctx.run(y, 200, seed=1)
+        torch.cuda.synchronize()
+        r = ctx.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=11)
+        thp = r["theta"].cpu().numpy()
+        extras["time_to_posterior_fp64_s"] = round(r["seconds"], 4)
+        extras["run_fp64"] = dict(stages=r["n_stages"], solves={str(i): v for i, v in enumerate(r["solves"]) if v},
+                                  log_Z=r["log_Z"], mean_pcg_iters=r["iters_total"] / max(1, sum(r["solves"])),
+                                  accept_rate=r["accepted"] / max(1, r["proposed"]))
+        log(f"time-to-posterior fp64 {r['seconds']:.3f}s stages {r['n_stages']}")
+        ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
+        ctxm.run(y, 200, seed=1)
+        rm = ctxm.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=11)
+        extras["time_to_posterior_mixed_s"] = round(rm["seconds"], 4)
+        thm = rm["theta"].cpu().numpy()
+        extras["run_mixed"] = dict(stages=rm["n_stages"], log_Z=rm["log_Z"],
+                                   posterior_mean_rel_diff_vs_fp64=float(
+                                       np.abs(thm.mean(0) - thp.mean(0)).sum() / np.abs(thp.mean(0)).sum()))
+        log(f"time-to-posterior mixed {rm['seconds']:.3f}s")
+        ctxm.close()
+        # per-level throughput of plain forward batches (J particles)
+        per = {}
+        th = torch.tensor(rng.standard_normal((J, K)), device=dev)
+        for lv in range(W["l_min"], W["l_max"] + 1):
+            ctx.forward(lv, th)
+            torch.cuda.synchronize()
+            reps = 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.forward(lv, th)
+            torch.cuda.synchronize()
+            per[f"h=1/{1 << lv}"] = round(reps * J / (time.perf_counter() - t0), 1)
+        extras["forward_solves_per_s_by_level"] = per
+        log(f"per-level {per}")
+
+    # ---- state for the timed stages: posterior-like particles at level 6
+    theta = torch.tensor(rng.standard_normal((J, K)), device=dev)
+    if not args.no_extras:
+        theta = torch.tensor(thp, device=dev)
+    G = ctx.forward(l, theta)
+    phi = ctx.loglik(G, y)
+    theta2, G2, phi2 = torch.empty_like(theta), torch.empty_like(G), torch.empty_like(phi)
+    stream = torch.cuda.current_stream()
+    beta0 = 0.5
+
+    def step(k):
+        nonlocal theta, G, phi, theta2, G2, phi2
+        out3, logw, w = ctx.next_step(phi, 1.0, beta0, J / (1 + W["tau_star"] ** 2))
+        u = ctx.philox(99, 3, k, 0, J, normal=False)
+        anc = ctx.resample(w, u)
+        P.mls2mc_gather(ctx.h, anc, theta, theta2)
+        P.mls2mc_gather(ctx.h, anc, G, G2)
+        P.mls2mc_gather(ctx.h, anc, phi.view(-1, 1), phi2.view(-1, 1))
+        theta, theta2, G, G2, phi, phi2 = theta2, theta, G2, G, phi2, phi
+        for s in range(W["n_mcmc"]):
+            xi = ctx.philox(99, 4, k, s, J * K, normal=True).view(J, K)
+            uu = ctx.philox(99, 5, k, s, J, normal=False)
+            ctx.pcn_step(l, l, 0.75, 1.0, W["s_pcn"], theta, G, None, phi, None, y, xi, uu)
+
+    for k in range(args.warmup):
+        step(10_000 + k)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.profile(False)
+    ps = ctx.profile_read(P.PROF_SOLVE, l)
+    pg = ctx.profile_read(P.PROF_GEMM, l)
+    solves = args.steps * W["n_mcmc"] * J
+    value = solves / dt
+    alg = solve_bytes(l, nobs, ps["items"], ps["iters"], B_ITER_FP64)
+    avg_ms = ps["ms"] / max(1, ps["launches"])
+    achieved = alg / ps["launches"] / (avg_ms * 1e-3) / 1e9 if ps["launches"] else 0.0
+    gemm_flops = 2.0 * pg["items"] * K * (2 << (2 * l))
+    extras["solver_kernel"] = dict(launches=ps["launches"], avg_ms=round(avg_ms, 4),
+                                   mean_pcg_iters=ps["iters"] / max(1, ps["items"]),
+                                   share_of_step_time=round(ps["ms"] * 1e-3 / dt, 3))
+    extras["kl_gemm"] = dict(launches=pg["launches"], avg_ms=round(pg["ms"] / max(1, pg["launches"]), 4),
+                             tflops=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12, 3),
+                             frac_of_fp64_peak=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12 / FP64_PEAK_TFLOPS, 4))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(l, K, m, W["corr"])
+        log(f"cpu baseline {cpu['value']:.1f} solves/s on {cpu['cores']} cores")
+    out = {
+        "metric": "forward solves/s per level; MLS²MC time-to-posterior, plain vs surrogate+FP32",
+        "value": round(value, 2),
+        "unit": "forward solves/s (h=1/64, inside SMC stages)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["name"], "levels": "h=1/8..1/64", "K": K, "n_obs": nobs, "J": J,
+                   "sigma_n": W["sigma_n"], "step": "one SMC stage at h=1/64: next_step, resample, "
+                   "gather, 5 pCN steps (KL GEMM + MG-PCG solve + observation + potential)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "solve_f64_kernel (h=1/64)"},
+        "cpu_baseline": cpu,
+        **extras,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -237,6 +237,25 @@ int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const double* y,
 int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint32_t stage,
                        uint32_t sub, int64_t n, int normal, double* out, void* stream);
 
+/* ---- kernel-time instrumentation ---- */
+/* When enabled, the library records a pair of HIP events on the launch
+ * stream around every launch of the solver kernel and of the KL GEMM, and
+ * accumulates the PCG iterations of the solved particles on the device.
+ * enable = 1 clears the records and starts; enable = 0 stops (records are
+ * kept until the next enable = 1).                                         */
+#define MLS2MC_PROF_SOLVE 0 /* multigrid-PCG solver kernel (incl. observation) */
+#define MLS2MC_PROF_GEMM 1  /* KL field GEMM                                   */
+typedef struct {
+    int64_t launches; /* launches recorded                                 */
+    double ms;        /* summed event-measured kernel durations            */
+    int64_t items;    /* particles (solver) or field rows (GEMM)            */
+    int64_t iters;    /* PCG iterations summed over particles (solver; MIXED:
+                         inner iterations over all refinement sweeps)       */
+} mls2mc_prof_entry;
+int mls2mc_profile(mls2mc_ctx* ctx, int enable);
+/* Totals for one kernel class and level (synchronizes the device).         */
+int mls2mc_profile_read(mls2mc_ctx* ctx, int kclass, int l, mls2mc_prof_entry* out);
+
 #ifdef __cplusplus
 }
 #endif

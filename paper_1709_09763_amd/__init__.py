@@ -12,5 +12,6 @@ from ._lib import (  # noqa: F401
     Problem, RunConfig, lib, library_path, mls2mc_create, mls2mc_destroy, mls2mc_forward,
     mls2mc_forward_field, mls2mc_gather, mls2mc_kl_field, mls2mc_last_error, mls2mc_loglik,
     mls2mc_n_elem, mls2mc_n_obs, mls2mc_n_unknowns, mls2mc_next_step, mls2mc_pcn_step,
-    mls2mc_philox_fill, mls2mc_resample, mls2mc_run, mls2mc_version,
+    mls2mc_philox_fill, mls2mc_profile, mls2mc_profile_read, mls2mc_resample, mls2mc_run,
+    mls2mc_version, PROF_GEMM, PROF_SOLVE,
 )

@@ -48,6 +48,12 @@ class RunResult(C.Structure):
                 ("stage_ess", _dp), ("stage_acc_rate", _dp)]
 
 
+class ProfEntry(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("items", C.c_int64),
+                ("iters", C.c_int64)]
+
+
+PROF_SOLVE, PROF_GEMM = 0, 1
 _lib = None
 _vp = C.c_void_p
 
@@ -82,6 +88,8 @@ def lib():
         L.mls2mc_run.argtypes = [_vp, C.POINTER(RunConfig), _vp, _vp, C.POINTER(RunResult), _vp]
         L.mls2mc_philox_fill.argtypes = [_vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                          C.c_int64, C.c_int, _vp, _vp]
+        L.mls2mc_profile.argtypes = [_vp, C.c_int]
+        L.mls2mc_profile_read.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(ProfEntry)]
         _lib = L
     return _lib
 
@@ -245,6 +253,16 @@ def mls2mc_run(h, cfg: RunConfig, y, theta_out, max_stage_log=4000):
     return out
 
 
+def mls2mc_profile(h, enable):
+    _check(lib().mls2mc_profile(h, int(enable)), "mls2mc_profile")
+
+
+def mls2mc_profile_read(h, kclass, l):
+    e = ProfEntry()
+    _check(lib().mls2mc_profile_read(h, kclass, l, C.byref(e)), "mls2mc_profile_read")
+    return dict(launches=e.launches, ms=e.ms, items=e.items, iters=e.iters)
+
+
 class Context:
     """Owns one library context; methods mirror the C entry points."""
 
@@ -266,6 +284,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def profile(self, enable=True):
+        mls2mc_profile(self.h, enable)
+
+    def profile_read(self, kclass, l):
+        return mls2mc_profile_read(self.h, kclass, l)
 
     def kl_field(self, l, theta, kind=FIELD_LOG_F64):
         dt = torch.float32 if kind == FIELD_KAPPA_F32 else torch.float64

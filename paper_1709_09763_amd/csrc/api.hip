@@ -80,11 +80,79 @@ int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double
     return MLS2MC_OK;
 }
 
+int prof_begin(mls2mc_ctx* ctx, int kclass, int l, int64_t items, hipStream_t s, ProfRec* rec)
+{
+    MLS_CHECK_HIP(hipEventCreate(&rec->a));
+    MLS_CHECK_HIP(hipEventCreate(&rec->b));
+    MLS_CHECK_HIP(hipEventRecord(rec->a, s));
+    ctx->prof[kclass][l].items += items;
+    return MLS2MC_OK;
+}
+
+int prof_end(mls2mc_ctx* ctx, int kclass, int l, const ProfRec& rec, hipStream_t s)
+{
+    MLS_CHECK_HIP(hipEventRecord(rec.b, s));
+    ctx->prof[kclass][l].recs.push_back(rec);
+    return MLS2MC_OK;
+}
+
+static void prof_clear(mls2mc_ctx* ctx)
+{
+    for (auto& row : ctx->prof)
+        for (auto& slot : row) {
+            for (auto& r : slot.recs) {
+                if (r.a) (void)hipEventDestroy(r.a);
+                if (r.b) (void)hipEventDestroy(r.b);
+            }
+            slot.recs.clear();
+            slot.items = 0;
+        }
+}
+
 }  // namespace mls
 
 using namespace mls;
 
 extern "C" {
+
+int mls2mc_profile(mls2mc_ctx* ctx, int enable)
+{
+    MLS_REQUIRE(ctx != nullptr, "null context");
+    if (enable) {
+        MLS_CHECK_HIP(hipDeviceSynchronize());
+        prof_clear(ctx);
+        if (!ctx->d_prof_iters)
+            MLS_CHECK_HIP(hipMalloc(&ctx->d_prof_iters, sizeof(int64_t) * 2 * (kMaxLevel + 1)));
+        MLS_CHECK_HIP(hipMemset(ctx->d_prof_iters, 0, sizeof(int64_t) * 2 * (kMaxLevel + 1)));
+    }
+    ctx->prof_on = enable != 0;
+    return MLS2MC_OK;
+}
+
+int mls2mc_profile_read(mls2mc_ctx* ctx, int kclass, int l, mls2mc_prof_entry* out)
+{
+    MLS_REQUIRE(ctx && out, "profile_read: null argument");
+    MLS_REQUIRE(kclass == MLS2MC_PROF_SOLVE || kclass == MLS2MC_PROF_GEMM, "profile_read: bad class");
+    MLS_REQUIRE(l >= 0 && l <= kMaxLevel, "profile_read: bad level");
+    MLS_CHECK_HIP(hipDeviceSynchronize());
+    const ProfSlot& slot = ctx->prof[kclass][l];
+    out->launches = (int64_t)slot.recs.size();
+    out->items = slot.items;
+    out->ms = 0.0;
+    for (const auto& r : slot.recs) {
+        float ms = 0.f;
+        MLS_CHECK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        out->ms += ms;
+    }
+    out->iters = 0;
+    if (kclass == MLS2MC_PROF_SOLVE && ctx->d_prof_iters) {
+        int64_t v[2];
+        MLS_CHECK_HIP(hipMemcpy(v, ctx->d_prof_iters + 2 * l, sizeof(v), hipMemcpyDeviceToHost));
+        out->iters = v[0];
+    }
+    return MLS2MC_OK;
+}
+
 
 const char* mls2mc_last_error(void) { return g_last_error.c_str(); }
 
@@ -112,6 +180,9 @@ int mls2mc_destroy(mls2mc_ctx* ctx)
     ctx->ws_pcn.release();
     ctx->ws_status.release();
     ctx->ws_run.release();
+    ctx->ws_prof.release();
+    prof_clear(ctx);
+    if (ctx->d_prof_iters) (void)hipFree(ctx->d_prof_iters);
     delete ctx;
     return MLS2MC_OK;
 }

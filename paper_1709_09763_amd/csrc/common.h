@@ -72,6 +72,15 @@ struct ObsTable {
     double* w = nullptr;     // device, 3 * nobs
 };
 
+// ---------------------------------------------------------- profiling --
+struct ProfRec {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+struct ProfSlot {
+    std::vector<ProfRec> recs;
+    int64_t items = 0;
+};
+
 // --------------------------------------------------------------- ctx --
 }  // namespace mls
 
@@ -99,6 +108,11 @@ struct mls2mc_ctx {
     int solver_block[mls::kMaxLevel + 1] = {};
     double rtol = 1e-11;
     int max_iters = 200;
+    // instrumentation (see mls2mc_profile)
+    bool prof_on = false;
+    mls::ProfSlot prof[2][mls::kMaxLevel + 1];
+    int64_t* d_prof_iters = nullptr;  // [kMaxLevel+1][2] device counters
+    mls::DevBuf ws_prof;              // iteration scratch when the caller passes none
 };
 
 namespace mls {
@@ -145,6 +159,8 @@ int launch_ess_cv(int64_t N, const double* dlo, const double* dhi, double scale,
 int launch_reduce_i32(int64_t N, const int32_t* v, const int8_t* st, int64_t* out2,
                       hipStream_t s);
 int launch_d2f(const double* a, float* b, int64_t n, hipStream_t s);
+int prof_begin(mls2mc_ctx* ctx, int kclass, int l, int64_t items, hipStream_t s, ProfRec* rec);
+int prof_end(mls2mc_ctx* ctx, int kclass, int l, const ProfRec& rec, hipStream_t s);
 
 int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
                   int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s);

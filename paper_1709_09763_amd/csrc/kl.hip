@@ -264,6 +264,8 @@ int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void
     const int K = ctx->prob.K;
     MLS_REQUIRE((N + 63) / 64 <= 65535, "kl_field: N too large for one launch");
     dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((N + 63) / 64));
+    ProfRec rec;
+    if (ctx->prof_on) MLS_TRY(prof_begin(ctx, MLS2MC_PROF_GEMM, l, N, s, &rec));
     if (kind == MLS2MC_FIELD_LOG_F64) {
         kl_gemm_f64<false><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne);
     } else if (kind == MLS2MC_FIELD_KAPPA_F64) {
@@ -276,6 +278,7 @@ int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void
         MLS_REQUIRE(false, "kl_field: unknown output kind");
     }
     MLS_CHECK_HIP(hipGetLastError());
+    if (ctx->prof_on) MLS_TRY(prof_end(ctx, MLS2MC_PROF_GEMM, l, rec, s));
     return MLS2MC_OK;
 }
 

@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kNS) void reduce_iters_kernel(int64_t N, const int3
     double a = 0.0, b = 0.0;
     for (int64_t j = threadIdx.x; j < N; j += kNS) {
         a += (double)v[j];
-        b += st[j] != 0 ? 1.0 : 0.0;
+        if (st) b += st[j] != 0 ? 1.0 : 0.0;
     }
     a = block_sum<kNS>(a, red);
     b = block_sum<kNS>(b, red);

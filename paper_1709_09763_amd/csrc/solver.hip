@@ -508,6 +508,14 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     P.inv_sigma = 1.0 / ctx->prob.sigma_n;
     P.tol2 = ctx->rtol * ctx->rtol;
     P.max_iters = ctx->max_iters;
+    ProfRec rec;
+    if (ctx->prof_on) {
+        if (!P.iters) {  // the iteration totals need per-particle counts
+            MLS_TRY(ctx->ws_prof.ensure(sizeof(int32_t) * (size_t)a.N));
+            P.iters = ctx->ws_prof.as<int32_t>();
+        }
+        MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
+    }
     dim3 g((unsigned)grid);
 #define MLS_LAUNCH(BSV)                                                              \
     if (mixed) solve_mixed_kernel<BSV><<<g, BSV, 0, s>>>(P);                         \
@@ -522,6 +530,10 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     }
 #undef MLS_LAUNCH
     MLS_CHECK_HIP(hipGetLastError());
+    if (ctx->prof_on) {
+        MLS_TRY(prof_end(ctx, MLS2MC_PROF_SOLVE, l, rec, s));
+        MLS_TRY(launch_reduce_i32(a.N, P.iters, nullptr, ctx->d_prof_iters + 2 * l, s));
+    }
     return MLS2MC_OK;
 }
 
