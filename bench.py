@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip per-level and time-to-posterior")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -112,6 +113,13 @@ def main():
     y = y.contiguous()
 
     extras = {}
+    if not args.no_autotune:
+        tuned = {}
+        for lv in range(W["l_min"], W["l_max"] + 1):
+            ms, (g, b) = ctx.autotune(lv, J)
+            tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, ms=round(ms, 4))
+        extras["autotuned_solver_launch"] = tuned
+        log(f"autotuned {tuned}")
     if not args.no_extras:
         # time-to-posterior, plain FP64 (one untimed warm run first)
         ctx.run(y, 200, seed=1)
@@ -124,6 +132,9 @@ def main():
                                   accept_rate=r["accepted"] / max(1, r["proposed"]))
         log(f"time-to-posterior fp64 {r['seconds']:.3f}s stages {r['n_stages']}")
         ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
+        if not args.no_autotune:
+            for lv in range(W["l_min"], W["l_max"] + 1):
+                ctxm.autotune(lv, J)
         ctxm.run(y, 200, seed=1)
         rm = ctxm.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=11)
         extras["time_to_posterior_mixed_s"] = round(rm["seconds"], 4)

@@ -237,6 +237,18 @@ int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const double* y,
 int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint32_t stage,
                        uint32_t sub, int64_t n, int normal, double* out, void* stream);
 
+/* ---- launch shape of the persistent solver ---- */
+/* Autotune the solver launch for level l on N prior draws: every candidate
+ * (persistent workgroups = w x CUs capped at N, w in {1,2,3,4,6,8,12,16};
+ * block in {64,...,1024}) is timed with HIP events (best of 3) and the
+ * fastest is kept in the context for level l.  best_ms (host, may be NULL)
+ * receives its time.  Synchronous; allocates its own temporary buffers.   */
+int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_ms, void* stream);
+/* Read / set the launch shape of level l (grid 0 or block 0 = built-in
+ * default), e.g. to restore tuned shapes cached by the caller.            */
+int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block);
+int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block);
+
 /* ---- kernel-time instrumentation ---- */
 /* When enabled, the library records a pair of HIP events on the launch
  * stream around every launch of the solver kernel and of the KL GEMM, and

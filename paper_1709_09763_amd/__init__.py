@@ -13,5 +13,5 @@ from ._lib import (  # noqa: F401
     mls2mc_forward_field, mls2mc_gather, mls2mc_kl_field, mls2mc_last_error, mls2mc_loglik,
     mls2mc_n_elem, mls2mc_n_obs, mls2mc_n_unknowns, mls2mc_next_step, mls2mc_pcn_step,
     mls2mc_philox_fill, mls2mc_profile, mls2mc_profile_read, mls2mc_resample, mls2mc_run,
-    mls2mc_version, PROF_GEMM, PROF_SOLVE,
+    mls2mc_version, PROF_GEMM, PROF_SOLVE, mls2mc_autotune, mls2mc_get_launch, mls2mc_set_launch,
 )

@@ -88,6 +88,9 @@ def lib():
         L.mls2mc_run.argtypes = [_vp, C.POINTER(RunConfig), _vp, _vp, C.POINTER(RunResult), _vp]
         L.mls2mc_philox_fill.argtypes = [_vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                          C.c_int64, C.c_int, _vp, _vp]
+        L.mls2mc_autotune.argtypes = [_vp, C.c_int, C.c_int64, C.POINTER(C.c_double), _vp]
+        L.mls2mc_get_launch.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mls2mc_set_launch.argtypes = [_vp, C.c_int, C.c_int, C.c_int]
         L.mls2mc_profile.argtypes = [_vp, C.c_int]
         L.mls2mc_profile_read.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(ProfEntry)]
         _lib = L
@@ -253,6 +256,22 @@ def mls2mc_run(h, cfg: RunConfig, y, theta_out, max_stage_log=4000):
     return out
 
 
+def mls2mc_autotune(h, l, N):
+    ms = C.c_double()
+    _check(lib().mls2mc_autotune(h, l, N, C.byref(ms), _stream()), "mls2mc_autotune")
+    return ms.value
+
+
+def mls2mc_get_launch(h, l):
+    g, b = C.c_int(), C.c_int()
+    _check(lib().mls2mc_get_launch(h, l, C.byref(g), C.byref(b)), "mls2mc_get_launch")
+    return g.value, b.value
+
+
+def mls2mc_set_launch(h, l, grid, block):
+    _check(lib().mls2mc_set_launch(h, l, grid, block), "mls2mc_set_launch")
+
+
 def mls2mc_profile(h, enable):
     _check(lib().mls2mc_profile(h, int(enable)), "mls2mc_profile")
 
@@ -284,6 +303,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def autotune(self, l, N):
+        ms = mls2mc_autotune(self.h, l, N)
+        return ms, mls2mc_get_launch(self.h, l)
+
+    def get_launch(self, l):
+        return mls2mc_get_launch(self.h, l)
+
+    def set_launch(self, l, grid, block):
+        mls2mc_set_launch(self.h, l, grid, block)
 
     def profile(self, enable=True):
         mls2mc_profile(self.h, enable)
