@@ -48,24 +48,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(l, K, m, corr, budget_s=12.0):
+def cpu_baseline(l, K, m, corr, budget_s=15.0):
+    """the oracle as it stands, timed on the host cores on chunks of prior
+    draws until the time budget is used"""
     import numpy as np
 
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     rng = np.random.default_rng(7)
-    th = rng.standard_normal((2 * cores, K))
-    t0 = time.perf_counter()
-    oracle.forward(l, K, 1.0, corr, m, th, nthreads=cores)
-    t_cal = time.perf_counter() - t0
-    n = int(max(2 * cores, min(20000, 2 * cores * budget_s / max(t_cal, 1e-3))))
-    th = rng.standard_normal((n, K))
-    t0 = time.perf_counter()
-    oracle.forward(l, K, 1.0, corr, m, th, nthreads=cores)
+    chunk = 4 * cores
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        oracle.forward(l, K, 1.0, corr, m, rng.standard_normal((chunk, K)), nthreads=cores)
+        n += chunk
     dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="forward solves/s", cores=cores, kind="oracle",
-                sample=f"{n} forward solves at h=1/{1 << l}, K={K} (KL field, generic P1 "
-                       f"assembly, banded Cholesky, observation), OpenMP over particles, {dt:.1f}s")
+                sample=f"{n} forward solves at h=1/{1 << l}, K={K} from the prior, in chunks of "
+                       f"{chunk} (KL field, generic P1 assembly, banded Cholesky, observation), "
+                       f"OpenMP over particles, {dt:.1f}s")
 
 
 def copy_calibration(gib=2.0):
@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-level and time-to-posterior")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
+    ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -113,13 +115,23 @@ def main():
     y = y.contiguous()
 
     extras = {}
-    if not args.no_autotune:
+    shapes = {}
+    if args.tuned:
+        shapes = {int(k): v for k, v in json.load(open(args.tuned))["fp64"].items()}
+        for lv, sh in shapes.items():
+            ctx.set_launch(lv, sh["grid"], sh["block"])
+        extras["solver_launch"] = {f"h=1/{1 << lv}": sh for lv, sh in shapes.items()}
+    elif not args.no_autotune:
         tuned = {}
         for lv in range(W["l_min"], W["l_max"] + 1):
             ms, (g, b) = ctx.autotune(lv, J)
+            shapes[lv] = dict(grid=g, block=b)
             tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, ms=round(ms, 4))
         extras["autotuned_solver_launch"] = tuned
         log(f"autotuned {tuned}")
+        if args.save_tuned:
+            json.dump({"device": torch.cuda.get_device_name(0), "workload": W["name"],
+                       "fp64": {str(k): v for k, v in shapes.items()}}, open(args.save_tuned, "w"), indent=1)
     if not args.no_extras:
         # time-to-posterior, plain FP64 (one untimed warm run first)
         ctx.run(y, 200, seed=1)
@@ -132,7 +144,7 @@ def main():
                                   accept_rate=r["accepted"] / max(1, r["proposed"]))
         log(f"time-to-posterior fp64 {r['seconds']:.3f}s stages {r['n_stages']}")
         ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
-        if not args.no_autotune:
+        if not args.no_autotune and not args.tuned:
             for lv in range(W["l_min"], W["l_max"] + 1):
                 ctxm.autotune(lv, J)
         ctxm.run(y, 200, seed=1)

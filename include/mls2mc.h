@@ -186,6 +186,57 @@ int mls2mc_pcn_step(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, double* 
                     const double* y, const double* xi, const double* u,
                     uint8_t* accepted_out, void* stream);
 
+/* ---- learned surrogate theta -> G(theta) (MLP K -> H -> H -> N_obs) ---- */
+/* The network has two hidden layers of width `hidden` with erf-GELU
+ * activations; matrix products run as BF16 MFMA with FP32 accumulation,
+ * master weights and Adam moments are FP32.  Parameter layout (FP32):
+ * W1[H x K], b1[H], W2[H x H], b2[H], W3[N_obs x H], b3[N_obs] (row-major,
+ * out x in).  Inputs and outputs are standardised with the mean and standard
+ * deviation of the training pairs (per component) once training has run.  */
+/* (Re)create the surrogate: He-initialised weights (Philox normals from
+ * `seed`), zero biases, an empty ring of `capacity` training pairs.
+ * hidden: multiple of 16 in [16, 1024].  Synchronous.                      */
+int mls2mc_surrogate_init(mls2mc_ctx* ctx, int hidden, int64_t capacity, uint64_t seed,
+                          void* stream);
+int mls2mc_surrogate_n_params(const mls2mc_ctx* ctx);
+int64_t mls2mc_surrogate_n_pairs(const mls2mc_ctx* ctx);
+/* copy FP32 parameters in / out (device arrays of n_params floats)         */
+int mls2mc_surrogate_set_params(mls2mc_ctx* ctx, const float* params, void* stream);
+int mls2mc_surrogate_get_params(mls2mc_ctx* ctx, float* params, void* stream);
+/* append n pairs (theta: n x K, G: n x N_obs, device doubles) to the ring;
+ * the ring keeps the most recent `capacity` pairs.                          */
+int mls2mc_surrogate_add_pairs(mls2mc_ctx* ctx, int64_t n, const double* theta, const double* G,
+                               void* stream);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the mean over batch and outputs
+ * of (net(x) - t)^2 / 2 with standardised x, t; `epochs` passes over a host-
+ * shuffled permutation (seeded) in minibatches of `batch`.  loss_out (host,
+ * may be NULL) receives the last minibatch loss of each epoch.  Synchronous
+ * at epoch ends.  Needs at least `batch` pairs.                            */
+int mls2mc_surrogate_train(mls2mc_ctx* ctx, int epochs, int batch, double lr, uint64_t seed,
+                           float* loss_out, void* stream);
+/* G_out[N x N_obs] = surrogate(theta[N x K]) in the units of G.             */
+int mls2mc_surrogate_predict(mls2mc_ctx* ctx, int64_t N, const double* theta, double* G_out,
+                             void* stream);
+/* Loss and its gradient for raw (unstandardised) inputs x[B x K] and targets
+ * t[B x N_obs] (device doubles): loss_out (1 float), grad_out (n_params
+ * floats), both device.  For gradient checks.                              */
+int mls2mc_surrogate_loss_grad(mls2mc_ctx* ctx, int64_t B, const double* x, const double* target,
+                               float* loss_out, float* grad_out, void* stream);
+/* Delayed-acceptance pCN step (two-stage Metropolis-Hastings, Christen and
+ * Fox 2005) for the same target as mls2mc_pcn_step.  Stage 1 accepts iff
+ * log u1 < -(Psi~' - Psi~) with Psi~ = beta Phi(surrogate(theta)); only the
+ * stage-1 survivors are solved with the FEM forward (compacted on the
+ * device, no host synchronisation); stage 2 accepts iff log u2 < -(Psi' -
+ * Psi) + (Psi~' - Psi~).  The chain is exact for any surrogate.
+ * accepted_out (N uint8) and stage1_out (N uint8, may be NULL) receive the
+ * outcomes; n_solved_lo / n_solved_hi (device int64, may be NULL) are
+ * incremented by the number of solves done on l_lo / l_hi.                 */
+int mls2mc_pcn_step_da(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, double* theta,
+                       double* G_lo, double* G_hi, double* phi_lo, double* phi_hi,
+                       const double* y, const double* xi, const double* u1, const double* u2,
+                       uint8_t* accepted_out, uint8_t* stage1_out, int64_t* n_solved_lo,
+                       int64_t* n_solved_hi, void* stream);
+
 /* ---- the whole MLS^2MC sampler (Sec. 4, update scheme of Sec. 4.4) ---- */
 typedef struct {
     int64_t J;          /* particles, 1 <= J <= 2^26                        */
@@ -197,6 +248,19 @@ typedef struct {
     double s_pcn;       /* pCN step size                                    */
     uint64_t seed;      /* Philox key                                       */
     int max_stages;     /* safety cap (0 = 4000)                            */
+    /* learned surrogate with delayed acceptance (0 = off).  Pairs (theta',
+     * G_l(theta')) of the pCN proposals of tempering stages on levels <=
+     * sur_collect_max_level go into the ring; the network is trained once on
+     * reaching level sur_da_min_level and every pCN step on levels >= it is
+     * a delayed-acceptance step (second-stage uniforms: Philox stream 6).   */
+    int surrogate;
+    int sur_collect_max_level;
+    int sur_da_min_level;
+    int64_t sur_pairs;  /* ring capacity (0 = 20480)                        */
+    int sur_epochs;     /* 0 = 30                                           */
+    int sur_hidden;     /* 0 = 256                                          */
+    int sur_batch;      /* 0 = 256                                          */
+    double sur_lr;      /* 0 = 1e-3                                         */
 } mls2mc_run_config;
 
 typedef struct {
@@ -209,6 +273,10 @@ typedef struct {
     int64_t iters_total;   /* PCG iterations summed over all solves          */
     int64_t not_converged; /* solves reported with status != 0               */
     double seconds;        /* wall time of the run (host clock)              */
+    int64_t stage1_passed; /* delayed acceptance: proposals solved with FEM  */
+    int64_t da_proposed;   /* delayed acceptance: proposals screened         */
+    double sur_train_seconds;
+    double sur_final_loss;
     /* optional per-stage log (host arrays of max_stage_log entries, or NULL).
      * stage types: 0 tempering, 1 tempering after a discarded look-ahead,
      * 2 first bridging sub-step of a level update chosen by the look-ahead,
@@ -232,7 +300,7 @@ int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const double* y,
                double* theta_out, mls2mc_run_result* res, void* stream);
 
 /* Philox4x32-10 uniforms/normals on the device, the same streams mls2mc_run
- * uses: out[i] for idx = i, counter {idx, sub, stage, stream}.  normal = 0:
+ * uses (6: second-stage uniforms of delayed acceptance): out[i] for idx = i, counter {idx, sub, stage, stream}.  normal = 0:
  * uniform in [0,1) (multiple of 2^-53); normal = 1: Box-Muller normal.      */
 int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint32_t stage,
                        uint32_t sub, int64_t n, int normal, double* out, void* stream);

@@ -31,7 +31,7 @@ class Config(C.Structure):
         ("tau_ess", C.c_double), ("tau_lu", C.c_double), ("eps", C.c_double),
         ("n_mcmc", C.c_int), ("s_pcn", C.c_double), ("seed", C.c_uint64),
         ("max_stages", C.c_int), ("nthreads", C.c_int),
-        ("lin_A", _dp), ("lin_E", _dp),
+        ("lin_A", _dp), ("lin_E", _dp), ("da_S", _dp),
     ]
 
 
@@ -39,7 +39,7 @@ class Result(C.Structure):
     _fields_ = [
         ("n_stages", C.c_int), ("log_Z", C.c_double), ("final_level", C.c_int),
         ("final_beta", C.c_double), ("solves", C.c_int64 * 16), ("accepted", C.c_int64),
-        ("proposed", C.c_int64), ("stage_type", _ip), ("stage_level", _ip),
+        ("proposed", C.c_int64), ("stage1_passed", C.c_int64), ("stage_type", _ip), ("stage_level", _ip),
         ("stage_beta", _dp), ("stage_zeta", _dp), ("stage_ess", _dp), ("max_stage_log", C.c_int),
     ]
 
@@ -64,6 +64,7 @@ def lib():
         L.orc_next_step.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                     _dp, _dp, _dp, _dp, _dp]
         L.orc_mh_accept.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_da_accept.argtypes = [C.c_double] * 6 + [_ip]
         L.orc_forward.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64,
                                   _dp, _dp, C.c_int]
         L.orc_forward_kappa.argtypes = [C.c_int, C.c_int, C.c_int64, _dp, _dp, _dp, C.c_int]
@@ -264,10 +265,16 @@ def mh_accept(psi_old, psi_new, u):
     return bool(lib().orc_mh_accept(psi_old, psi_new, u))
 
 
+def da_accept(psi_old, psi_new, psis_old, psis_new, u1, u2):
+    s1 = C.c_int()
+    a = lib().orc_da_accept(psi_old, psi_new, psis_old, psis_new, u1, u2, C.byref(s1))
+    return bool(a), bool(s1.value)
+
+
 def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=0.3, m=3,
                 nobs=None, sigma_n=0.01, J=200, J_tilde=None, tau_star=1.0, tau_lu=None,
                 eps=1e-6, n_mcmc=5, s_pcn=0.5, seed=0, max_stages=2000, nthreads=0,
-                lin_A=None, lin_E=None):
+                lin_A=None, lin_E=None, da_S=None):
     """Run the MLS^2MC sampler; returns a dict of results and final particles."""
     y = _f64(y)
     cfg = Config()
@@ -289,6 +296,10 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
         keep += [A, E]
         cfg.lin_A = _d(A)
         cfg.lin_E = _d(E)
+    if da_S is not None:
+        S = _f64(da_S)
+        keep.append(S)
+        cfg.da_S = _d(S)
     res = Result()
     ms = max_stages
     st = np.zeros(ms, dtype=np.int32)
@@ -307,7 +318,7 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
     n = min(res.n_stages, ms)
     return dict(theta=theta, log_Z=res.log_Z, n_stages=res.n_stages, final_level=res.final_level,
                 final_beta=res.final_beta, solves=list(res.solves), accepted=res.accepted,
-                proposed=res.proposed, stage_type=st[:n].copy(), stage_level=sl[:n].copy(),
+                proposed=res.proposed, stage1_passed=res.stage1_passed, stage_type=st[:n].copy(), stage_level=sl[:n].copy(),
                 stage_beta=sb[:n].copy(), stage_zeta=sz[:n].copy(), stage_ess=se[:n].copy())
 
 

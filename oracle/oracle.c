@@ -599,6 +599,15 @@ int orc_mh_accept(double psi_old, double psi_new, double u)
     return log(u) < -(psi_new - psi_old);
 }
 
+int orc_da_accept(double psi_old, double psi_new, double psis_old, double psis_new, double u1,
+                  double u2, int* stage1)
+{
+    int s1 = log(u1) < -(psis_new - psis_old);
+    if (stage1) *stage1 = s1;
+    if (!s1) return 0;
+    return log(u2) < -(psi_new - psi_old) + (psis_new - psis_old);
+}
+
 /* ======================================================================
  * The MLS^2MC sampler (Sec. 4), update scheme of Sec. 4.4: the first update
  * and every update after a level update are tempering updates; otherwise
@@ -606,7 +615,7 @@ int orc_mh_accept(double psi_old, double psi_new, double u)
  * taken when cv^LU >= tau_LU.  At beta = 1 the remaining levels are bridged.
  * Random streams: 0 prior, 3 resampling, 4 pCN normals, 5 pCN uniforms.
  * ==================================================================== */
-enum { ST_PRIOR = 0, ST_RESAMPLE = 3, ST_PCN_XI = 4, ST_PCN_U = 5 };
+enum { ST_PRIOR = 0, ST_RESAMPLE = 3, ST_PCN_XI = 4, ST_PCN_U = 5, ST_PCN_U2 = 6 };
 
 typedef struct {
     const orc_config* cfg;
@@ -678,8 +687,23 @@ static void orc_gather(int64_t J, int K, int nobs, const int32_t* anc, orc_state
 
 /* n_mcmc pCN steps targeting exp(-beta[(1-zeta)Phi_lo + zeta Phi_hi]) times
  * the prior.  bridge = 0: only Phi_lo (level l) is used (zeta ignored).    */
+/* surrogate potential beta * Phi(S theta) of the delayed-acceptance stage 1 */
+static double orc_sur_psi(const orc_config* cfg, int nobs, const double* th, const double* y,
+                          double beta)
+{
+    double ph = 0.0;
+    for (int o = 0; o < nobs; ++o) {
+        double g = 0.0;
+        for (int k = 0; k < cfg->K; ++k) g += cfg->da_S[o * cfg->K + k] * th[k];
+        double r = (y[o] - g) / cfg->sigma_n;
+        ph += r * r;
+    }
+    return beta * 0.5 * ph;
+}
+
 static int orc_mutate(orc_model* md, const double* y, int stage, int l, int bridge, double beta,
-                      double zeta, orc_state* s, int64_t* solves, int64_t* acc, int64_t* prop)
+                      double zeta, orc_state* s, int64_t* solves, int64_t* acc, int64_t* prop,
+                      int64_t* pass1)
 {
     const orc_config* cfg = md->cfg;
     int64_t J = cfg->J;
@@ -718,7 +742,17 @@ static int orc_mutate(orc_model* md, const double* y, int stage, int l, int brid
             } else { psi_old = beta * s->phihi[j]; psi_new = beta * ph[j]; }
             double u = orc_uniform(cfg->seed, ST_PCN_U, (uint32_t)stage, (uint32_t)mstep, (uint32_t)j);
             ++*prop;
-            if (orc_mh_accept(psi_old, psi_new, u)) {
+            int ok;
+            if (cfg->da_S) {
+                double u2 = orc_uniform(cfg->seed, ST_PCN_U2, (uint32_t)stage, (uint32_t)mstep, (uint32_t)j);
+                int s1;
+                ok = orc_da_accept(psi_old, psi_new, orc_sur_psi(cfg, nobs, s->theta + j * K, y, beta),
+                                   orc_sur_psi(cfg, nobs, th + j * K, y, beta), u, u2, &s1);
+                *pass1 += s1;
+            } else {
+                ok = orc_mh_accept(psi_old, psi_new, u);
+            }
+            if (ok) {
                 ++*acc;
                 memcpy(s->theta + j * K, th + j * K, sizeof(double) * K);
                 if (need_lo) { memcpy(s->Glo + j * nobs, Gl + j * nobs, sizeof(double) * nobs); s->philo[j] = pl[j]; }
@@ -758,6 +792,8 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
     res->n_stages = 0; res->log_Z = 0.0;
     memset(res->solves, 0, sizeof(res->solves));
     res->accepted = res->proposed = 0;
+    res->stage1_passed = 0;
+    if (cfg->da_S && cfg->model != ORC_MODEL_LINEAR) return ORC_EINVAL;
 
     orc_state s, tmp;
     double* buf = (double*)malloc(sizeof(double) * 2 * (J * K + 2 * J * nobs + 2 * J));
@@ -813,7 +849,8 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
             rc = orc_resample(J, w, u, anc);
             if (rc) break;
             orc_gather(J, K, nobs, anc, &s, &tmp, 0);
-            rc = orc_mutate(&md, y, stage, l, 0, nb, 1.0, &s, res->solves, &res->accepted, &res->proposed);
+            rc = orc_mutate(&md, y, stage, l, 0, nb, 1.0, &s, res->solves, &res->accepted, &res->proposed,
+                            &res->stage1_passed);
             if (rc) break;
             beta = nb;
             orc_log_stage(res, checked ? 1 : 0, l, beta, 0.0, ess);
@@ -841,7 +878,8 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
                 rc = orc_resample(J, w, u, anc);
                 if (rc) break;
                 orc_gather(J, K, nobs, anc, &s, &tmp, 1);
-                rc = orc_mutate(&md, y, stage, l, 1, beta, nz, &s, res->solves, &res->accepted, &res->proposed);
+                rc = orc_mutate(&md, y, stage, l, 1, beta, nz, &s, res->solves, &res->accepted, &res->proposed,
+                                &res->stage1_passed);
                 if (rc) break;
                 zeta = nz;
                 orc_log_stage(res, first ? (checked ? 2 : 3) : 4, l + 1, beta, zeta, ess);

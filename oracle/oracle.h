@@ -106,6 +106,14 @@ void orc_pcn_propose(int64_t N, int K, double s, const double* theta,
 /* returns 1 if accepted: log u < -(psi_new - psi_old)                     */
 int orc_mh_accept(double psi_old, double psi_new, double u);
 
+/* delayed acceptance (two-stage Metropolis-Hastings of Christen and Fox,
+ * 2005) with a cheap approximation psis of the potential psi: stage 1
+ * accepts iff log u1 < -(psis_new - psis_old); stage 2, reached only after
+ * stage 1, accepts iff log u2 < -(psi_new - psi_old) + (psis_new -
+ * psis_old).  Returns 1 if the move is accepted; *stage1 = stage-1 outcome. */
+int orc_da_accept(double psi_old, double psi_new, double psis_old, double psis_new,
+                  double u1, double u2, int* stage1);
+
 /* ---- the MLS^2MC sampler ---- */
 enum { ORC_MODEL_PDE = 0, ORC_MODEL_LINEAR = 1 };
 
@@ -130,6 +138,10 @@ typedef struct {
     /* linear model G_l(theta) = (A + 2^{-2l} E) theta, each nobs x K       */
     const double* lin_A;
     const double* lin_E;
+    /* delayed-acceptance pCN with the linear surrogate G~(theta) = S theta
+     * (nobs x K, linear model only); NULL = plain pCN.  Uniforms of the
+     * second stage come from stream 6.                                     */
+    const double* da_S;
 } orc_config;
 
 typedef struct {
@@ -139,6 +151,7 @@ typedef struct {
     double final_beta;
     int64_t solves[16];     /* forward evaluations per level                */
     int64_t accepted, proposed;
+    int64_t stage1_passed;  /* delayed acceptance: proposals past stage 1   */
     /* per stage: type, level, beta, zeta, ESS.  Types: 0 tempering update,
      * 1 tempering update after a discarded look-ahead, 2 first bridging
      * sub-step of a level update chosen by the look-ahead, 3 first bridging

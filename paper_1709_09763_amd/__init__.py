@@ -14,4 +14,7 @@ from ._lib import (  # noqa: F401
     mls2mc_n_elem, mls2mc_n_obs, mls2mc_n_unknowns, mls2mc_next_step, mls2mc_pcn_step,
     mls2mc_philox_fill, mls2mc_profile, mls2mc_profile_read, mls2mc_resample, mls2mc_run,
     mls2mc_version, PROF_GEMM, PROF_SOLVE, mls2mc_autotune, mls2mc_get_launch, mls2mc_set_launch,
+    mls2mc_pcn_step_da, mls2mc_surrogate_add_pairs, mls2mc_surrogate_get_params, mls2mc_surrogate_init,
+    mls2mc_surrogate_loss_grad, mls2mc_surrogate_n_pairs, mls2mc_surrogate_n_params,
+    mls2mc_surrogate_predict, mls2mc_surrogate_set_params, mls2mc_surrogate_train,
 )

@@ -32,7 +32,10 @@ class Stage(C.Structure):
 class RunConfig(C.Structure):
     _fields_ = [("J", C.c_int64), ("J_tilde", C.c_int64), ("tau_star", C.c_double),
                 ("tau_lu", C.c_double), ("eps", C.c_double), ("n_mcmc", C.c_int),
-                ("s_pcn", C.c_double), ("seed", C.c_uint64), ("max_stages", C.c_int)]
+                ("s_pcn", C.c_double), ("seed", C.c_uint64), ("max_stages", C.c_int),
+                ("surrogate", C.c_int), ("sur_collect_max_level", C.c_int),
+                ("sur_da_min_level", C.c_int), ("sur_pairs", C.c_int64), ("sur_epochs", C.c_int),
+                ("sur_hidden", C.c_int), ("sur_batch", C.c_int), ("sur_lr", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -43,7 +46,9 @@ class RunResult(C.Structure):
     _fields_ = [("n_stages", C.c_int), ("final_level", C.c_int), ("final_beta", C.c_double),
                 ("log_Z", C.c_double), ("solves", C.c_int64 * 16), ("accepted", C.c_int64),
                 ("proposed", C.c_int64), ("iters_total", C.c_int64), ("not_converged", C.c_int64),
-                ("seconds", C.c_double), ("max_stage_log", C.c_int), ("stage_type", _ip),
+                ("seconds", C.c_double), ("stage1_passed", C.c_int64), ("da_proposed", C.c_int64),
+                ("sur_train_seconds", C.c_double), ("sur_final_loss", C.c_double),
+                ("max_stage_log", C.c_int), ("stage_type", _ip),
                 ("stage_level", _ip), ("stage_beta", _dp), ("stage_zeta", _dp),
                 ("stage_ess", _dp), ("stage_acc_rate", _dp)]
 
@@ -91,6 +96,18 @@ def lib():
         L.mls2mc_autotune.argtypes = [_vp, C.c_int, C.c_int64, C.POINTER(C.c_double), _vp]
         L.mls2mc_get_launch.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.mls2mc_set_launch.argtypes = [_vp, C.c_int, C.c_int, C.c_int]
+        L.mls2mc_surrogate_init.argtypes = [_vp, C.c_int, C.c_int64, C.c_uint64, _vp]
+        L.mls2mc_surrogate_n_params.argtypes = [_vp]
+        L.mls2mc_surrogate_n_pairs.argtypes = [_vp]
+        L.mls2mc_surrogate_n_pairs.restype = C.c_int64
+        L.mls2mc_surrogate_set_params.argtypes = [_vp, _vp, _vp]
+        L.mls2mc_surrogate_get_params.argtypes = [_vp, _vp, _vp]
+        L.mls2mc_surrogate_add_pairs.argtypes = [_vp, C.c_int64, _vp, _vp, _vp]
+        L.mls2mc_surrogate_train.argtypes = [_vp, C.c_int, C.c_int, C.c_double, C.c_uint64,
+                                             C.POINTER(C.c_float), _vp]
+        L.mls2mc_surrogate_predict.argtypes = [_vp, C.c_int64, _vp, _vp, _vp]
+        L.mls2mc_surrogate_loss_grad.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+        L.mls2mc_pcn_step_da.argtypes = [_vp, C.POINTER(Stage), C.c_int64] + [_vp] * 14
         L.mls2mc_profile.argtypes = [_vp, C.c_int]
         L.mls2mc_profile_read.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(ProfEntry)]
         _lib = L
@@ -250,10 +267,76 @@ def mls2mc_run(h, cfg: RunConfig, y, theta_out, max_stage_log=4000):
     out = dict(n_stages=res.n_stages, final_level=res.final_level, final_beta=res.final_beta,
                log_Z=res.log_Z, solves=list(res.solves), accepted=res.accepted,
                proposed=res.proposed, iters_total=res.iters_total,
-               not_converged=res.not_converged, seconds=res.seconds)
+               not_converged=res.not_converged, seconds=res.seconds,
+               stage1_passed=res.stage1_passed, da_proposed=res.da_proposed,
+               sur_train_seconds=res.sur_train_seconds, sur_final_loss=res.sur_final_loss)
     for k, v in arrs.items():
         out[k] = v[:n].copy()
     return out
+
+
+def mls2mc_surrogate_init(h, hidden=256, capacity=20480, seed=0):
+    _check(lib().mls2mc_surrogate_init(h, hidden, capacity, seed, _stream()), "mls2mc_surrogate_init")
+
+
+def mls2mc_surrogate_n_params(h):
+    return lib().mls2mc_surrogate_n_params(h)
+
+
+def mls2mc_surrogate_n_pairs(h):
+    return lib().mls2mc_surrogate_n_pairs(h)
+
+
+def mls2mc_surrogate_set_params(h, params):
+    _check(lib().mls2mc_surrogate_set_params(h, _ptr(params, torch.float32, name="params"), _stream()),
+           "mls2mc_surrogate_set_params")
+
+
+def mls2mc_surrogate_get_params(h, params):
+    _check(lib().mls2mc_surrogate_get_params(h, _ptr(params, torch.float32, name="params"), _stream()),
+           "mls2mc_surrogate_get_params")
+
+
+def mls2mc_surrogate_add_pairs(h, theta, G):
+    _check(lib().mls2mc_surrogate_add_pairs(h, theta.shape[0], _ptr(theta, torch.float64, name="theta"),
+                                            _ptr(G, torch.float64, name="G"), _stream()),
+           "mls2mc_surrogate_add_pairs")
+
+
+def mls2mc_surrogate_train(h, epochs, batch=256, lr=1e-3, seed=0):
+    losses = (C.c_float * max(1, epochs))()
+    _check(lib().mls2mc_surrogate_train(h, epochs, batch, lr, seed, losses, _stream()),
+           "mls2mc_surrogate_train")
+    return [losses[i] for i in range(epochs)]
+
+
+def mls2mc_surrogate_predict(h, theta, G_out):
+    _check(lib().mls2mc_surrogate_predict(h, theta.shape[0], _ptr(theta, torch.float64, name="theta"),
+                                          _ptr(G_out, torch.float64, name="G_out"), _stream()),
+           "mls2mc_surrogate_predict")
+
+
+def mls2mc_surrogate_loss_grad(h, x, t, loss_out, grad_out):
+    _check(lib().mls2mc_surrogate_loss_grad(h, x.shape[0], _ptr(x, torch.float64, name="x"),
+                                            _ptr(t, torch.float64, name="t"),
+                                            _ptr(loss_out, torch.float32, name="loss_out"),
+                                            _ptr(grad_out, torch.float32, name="grad_out"), _stream()),
+           "mls2mc_surrogate_loss_grad")
+
+
+def mls2mc_pcn_step_da(h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u1, u2,
+                       accepted_out, stage1_out=None, n_solved_lo=None, n_solved_hi=None):
+    st = Stage(l_lo, l_hi, beta, zeta, s)
+    f64 = torch.float64
+    _check(lib().mls2mc_pcn_step_da(
+        h, C.byref(st), theta.shape[0], _ptr(theta, f64, name="theta"),
+        _ptr(G_lo, f64, name="G_lo", optional=True), _ptr(G_hi, f64, name="G_hi", optional=True),
+        _ptr(phi_lo, f64, name="phi_lo", optional=True), _ptr(phi_hi, f64, name="phi_hi", optional=True),
+        _ptr(y, f64, name="y"), _ptr(xi, f64, name="xi"), _ptr(u1, f64, name="u1"), _ptr(u2, f64, name="u2"),
+        _ptr(accepted_out, torch.uint8, name="accepted_out"),
+        _ptr(stage1_out, torch.uint8, name="stage1_out", optional=True),
+        _ptr(n_solved_lo, torch.int64, name="n_solved_lo", optional=True),
+        _ptr(n_solved_hi, torch.int64, name="n_solved_hi", optional=True), _stream()), "mls2mc_pcn_step_da")
 
 
 def mls2mc_autotune(h, l, N):
@@ -379,8 +462,11 @@ class Context:
         return acc
 
     def run(self, y, J, J_tilde=0, tau_star=1.0, tau_lu=0.0, eps=0.0, n_mcmc=5, s_pcn=0.5, seed=0,
-            max_stages=0):
-        cfg = RunConfig(J, J_tilde, tau_star, tau_lu, eps, n_mcmc, s_pcn, seed, max_stages)
+            max_stages=0, surrogate=False, sur_collect_max_level=0, sur_da_min_level=0, sur_pairs=0,
+            sur_epochs=0, sur_hidden=0, sur_batch=0, sur_lr=0.0):
+        cfg = RunConfig(J, J_tilde, tau_star, tau_lu, eps, n_mcmc, s_pcn, seed, max_stages,
+                        int(surrogate), sur_collect_max_level, sur_da_min_level, sur_pairs, sur_epochs,
+                        sur_hidden, sur_batch, sur_lr)
         theta = torch.empty((J, self.K), dtype=torch.float64, device=y.device)
         out = mls2mc_run(self.h, cfg, y, theta)
         out["theta"] = theta

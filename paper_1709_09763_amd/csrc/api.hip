@@ -49,9 +49,18 @@ static int check_level(const mls2mc_ctx* ctx, int l)
     return MLS2MC_OK;
 }
 
-// theta -> KL field -> solve, in chunks that bound the field buffer to 2 GiB
+__global__ void chunk_count_kernel(const int64_t* __restrict__ total, int64_t q0, int64_t n,
+                                   int64_t* __restrict__ out)
+{
+    const int64_t r = *total - q0;
+    out[0] = r < 0 ? 0 : (r > n ? n : r);
+}
+
+// theta -> KL field -> solve, in chunks that bound the field buffer to 2 GiB.
+// N_dev (optional, device): only the first min(N, *N_dev) rows are solved.
 int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
-                  int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s)
+                  int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s,
+                  const int64_t* N_dev)
 {
     const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
@@ -61,10 +70,18 @@ int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double
     if (chunk > N) chunk = N;
     MLS_TRY(ctx->ws_kappa.ensure((size_t)chunk * ne * esz));
     const int K = ctx->prob.K, nobs = ctx->nobs;
+    if (N_dev && N > chunk && !ctx->d_chunk_count)
+        MLS_CHECK_HIP(hipMalloc(&ctx->d_chunk_count, sizeof(int64_t) * 8));
     for (int64_t q0 = 0; q0 < N; q0 += chunk) {
         const int64_t n = (N - q0 < chunk) ? N - q0 : chunk;
+        const int64_t* cnt = N_dev;
+        if (N_dev && N > chunk) {
+            chunk_count_kernel<<<1, 1, 0, s>>>(N_dev, q0, n, ctx->d_chunk_count);
+            MLS_CHECK_HIP(hipGetLastError());
+            cnt = ctx->d_chunk_count;
+        }
         MLS_TRY(launch_kl_field(ctx, l, n, theta + q0 * K, ctx->ws_kappa.ptr,
-                                mixed ? MLS2MC_FIELD_KAPPA_F32 : MLS2MC_FIELD_KAPPA_F64, s));
+                                mixed ? MLS2MC_FIELD_KAPPA_F32 : MLS2MC_FIELD_KAPPA_F64, s, cnt));
         SolveArgs a;
         a.l = l;
         a.N = n;
@@ -75,6 +92,7 @@ int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double
         a.iters = iters ? iters + q0 : nullptr;
         a.y = y;
         a.phi = phi ? phi + q0 : nullptr;
+        a.N_dev = cnt;
         MLS_TRY(launch_solve(ctx, a, s));
     }
     return MLS2MC_OK;
@@ -181,6 +199,9 @@ int mls2mc_destroy(mls2mc_ctx* ctx)
     ctx->ws_status.release();
     ctx->ws_run.release();
     ctx->ws_prof.release();
+    ctx->ws_da.release();
+    surrogate_destroy(ctx);
+    if (ctx->d_chunk_count) (void)hipFree(ctx->d_chunk_count);
     prof_clear(ctx);
     if (ctx->d_prof_iters) (void)hipFree(ctx->d_prof_iters);
     delete ctx;

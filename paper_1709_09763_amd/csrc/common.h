@@ -81,6 +81,9 @@ struct ProfSlot {
     int64_t items = 0;
 };
 
+struct Surrogate;
+void surrogate_destroy(mls2mc_ctx* ctx);
+
 // --------------------------------------------------------------- ctx --
 }  // namespace mls
 
@@ -113,6 +116,9 @@ struct mls2mc_ctx {
     mls::ProfSlot prof[2][mls::kMaxLevel + 1];
     int64_t* d_prof_iters = nullptr;  // [kMaxLevel+1][2] device counters
     mls::DevBuf ws_prof;              // iteration scratch when the caller passes none
+    mls::Surrogate* sur = nullptr;    // learned surrogate (mlp.hip)
+    mls::DevBuf ws_da;                // delayed-acceptance scratch
+    int64_t* d_chunk_count = nullptr; // per-chunk device counts
 };
 
 namespace mls {
@@ -120,7 +126,7 @@ namespace mls {
 // ------------------------------------------------------------ launchers --
 int build_kl_tables(mls2mc_ctx* ctx);
 int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void* out, int kind,
-                    hipStream_t s);
+                    hipStream_t s, const int64_t* N_dev = nullptr);
 int build_obs_tables(mls2mc_ctx* ctx);
 
 struct SolveArgs {
@@ -134,6 +140,7 @@ struct SolveArgs {
     int32_t* iters = nullptr;     // N or null
     const double* y = nullptr;    // fused potential (null: off)
     double* phi = nullptr;
+    const int64_t* N_dev = nullptr;  // device-side count <= N (null: N)
 };
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s);
 
@@ -163,7 +170,8 @@ int prof_begin(mls2mc_ctx* ctx, int kclass, int l, int64_t items, hipStream_t s,
 int prof_end(mls2mc_ctx* ctx, int kclass, int l, const ProfRec& rec, hipStream_t s);
 
 int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
-                  int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s);
+                  int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s,
+                  const int64_t* N_dev = nullptr);
 
 // --------------------------------------------------- device utilities --
 __device__ __forceinline__ double wave_sum(double v)

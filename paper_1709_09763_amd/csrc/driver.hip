@@ -15,7 +15,7 @@
 
 namespace mls {
 
-enum { ST_PRIOR = 0, ST_RESAMPLE = 3, ST_PCN_XI = 4, ST_PCN_U = 5 };
+enum { ST_PRIOR = 0, ST_RESAMPLE = 3, ST_PCN_XI = 4, ST_PCN_U = 5, ST_PCN_U2 = 6 };
 
 __global__ void diff_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
                             double* __restrict__ d)
@@ -41,10 +41,11 @@ __global__ void count_u8_kernel(int64_t n, const uint8_t* __restrict__ v, int64_
 struct RunState {
     double *theta, *Glo, *Ghi, *plo, *phi;      // current state
     double *theta2, *Glo2, *Ghi2, *plo2, *phi2; // gather targets
-    double *d, *w, *u, *xi, *upcn, *out3, *cv;
+    double *d, *w, *u, *xi, *upcn, *upcn2, *out3, *cv;
     int32_t* anc;
     uint8_t* acc;
-    int64_t* counters;  // [iters, not converged, accepted]
+    uint8_t* pass1;
+    int64_t* counters;  // [iters, not converged, accepted, -, -, -, -, -, DA solves per level 8..23]
     int8_t* st;
     int32_t* it;
 };
@@ -73,8 +74,15 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
 
     // ---- state buffers
     size_t nd = 2 * ((size_t)J * K + 2 * (size_t)J * nobs + 2 * (size_t)J);  // state + gather
-    nd += 3 * (size_t)J + (size_t)J * K + (size_t)J + 8;                     // d w u xi upcn out3 cv
-    size_t bytes = nd * sizeof(double) + (size_t)J * (sizeof(int32_t) * 2 + 2) + 64 * sizeof(int64_t);
+    nd += 3 * (size_t)J + (size_t)J * K + 2 * (size_t)J + 8;                 // d w u xi upcn(2) out3 cv
+    size_t bytes = nd * sizeof(double) + (size_t)J * (sizeof(int32_t) * 2 + 3) + 64 * sizeof(int64_t);
+    const bool use_sur = cfg->surrogate != 0;
+    const int sur_collect = cfg->sur_collect_max_level;
+    const int sur_da = cfg->sur_da_min_level;
+    if (use_sur) {
+        MLS_REQUIRE(sur_da > ctx->prob.l_min && sur_da <= ctx->prob.l_max && sur_collect < sur_da,
+                    "run: surrogate needs l_min < sur_da_min_level <= l_max and sur_collect_max_level < sur_da_min_level");
+    }
     MLS_TRY(ctx->ws_run.ensure(bytes));
     RunState R;
     double* p = ctx->ws_run.as<double>();
@@ -84,18 +92,28 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     R.theta2 = take((size_t)J * K); R.Glo2 = take((size_t)J * nobs); R.Ghi2 = take((size_t)J * nobs);
     R.plo2 = take(J); R.phi2 = take(J);
     R.d = take(J); R.w = take(J); R.u = take(J); R.xi = take((size_t)J * K); R.upcn = take(J);
+    R.upcn2 = take(J);
     R.out3 = take(4); R.cv = take(4);
-    R.counters = reinterpret_cast<int64_t*>(p); p += 8;
+    R.counters = reinterpret_cast<int64_t*>(p); p += 32;
     R.it = reinterpret_cast<int32_t*>(p);
     R.anc = R.it + J;
     R.st = reinterpret_cast<int8_t*>(R.anc + J);
     R.acc = reinterpret_cast<uint8_t*>(R.st + J);
-    MLS_CHECK_HIP(hipMemsetAsync(R.counters, 0, 8 * sizeof(int64_t), s));
+    R.pass1 = R.acc + J;
+    MLS_CHECK_HIP(hipMemsetAsync(R.counters, 0, 32 * sizeof(int64_t), s));
 
     res->n_stages = 0;
     res->log_Z = 0.0;
     for (int i = 0; i < 16; ++i) res->solves[i] = 0;
     res->accepted = res->proposed = 0;
+    res->stage1_passed = res->da_proposed = 0;
+    res->sur_train_seconds = 0.0;
+    res->sur_final_loss = 0.0;
+    bool sur_ready = false;
+    if (use_sur) {
+        MLS_TRY(mls2mc_surrogate_init(ctx, cfg->sur_hidden > 0 ? cfg->sur_hidden : 256,
+                                      cfg->sur_pairs > 0 ? cfg->sur_pairs : 20480, cfg->seed ^ 0x51u, stream));
+    }
 
     auto fwd = [&](int l, int64_t n, const double* th, double* G, double* ph) -> int {
         if (n == 0) return MLS2MC_OK;
@@ -124,11 +142,28 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         st.beta = beta;
         st.zeta = bridge ? zeta : 1.0;
         st.s = cfg->s_pcn;
+        const bool da = sur_ready && l >= sur_da;
         for (int m = 0; m < cfg->n_mcmc; ++m) {
             MLS_TRY(launch_philox(cfg->seed, ST_PCN_XI, (uint32_t)stage, (uint32_t)m, J * K, 1, R.xi, s));
             MLS_TRY(launch_philox(cfg->seed, ST_PCN_U, (uint32_t)stage, (uint32_t)m, J, 0, R.upcn, s));
+            if (da) {
+                MLS_TRY(launch_philox(cfg->seed, ST_PCN_U2, (uint32_t)stage, (uint32_t)m, J, 0, R.upcn2, s));
+                MLS_TRY(mls2mc_pcn_step_da(ctx, &st, J, R.theta, R.Glo, R.Ghi, R.plo, R.phi, y, R.xi, R.upcn,
+                                           R.upcn2, R.acc, R.pass1, R.counters + 8 + l, R.counters + 8 + l + 1,
+                                           stream));
+                count_u8_kernel<<<1, 256, 0, s>>>(J, R.acc, R.counters + 2);
+                count_u8_kernel<<<1, 256, 0, s>>>(J, R.pass1, R.counters + 3);
+                MLS_CHECK_HIP(hipGetLastError());
+                res->proposed += J;
+                res->da_proposed += J;
+                continue;
+            }
             MLS_TRY(mls2mc_pcn_step(ctx, &st, J, R.theta, R.Glo, R.Ghi, R.plo, R.phi, y, R.xi, R.upcn,
                                     R.acc, stream));
+            if (use_sur && !bridge && l <= sur_collect) {  // proposals and their solves -> training pairs
+                const double* thn = ctx->ws_pcn.as<double>();
+                MLS_TRY(mls2mc_surrogate_add_pairs(ctx, J, thn, thn + (size_t)J * K, stream));
+            }
             // iteration statistics of the proposals' solves
             const int32_t* itl = ctx->ws_status.as<int32_t>();
             const int8_t* stl = reinterpret_cast<const int8_t*>(itl + 2 * J);
@@ -180,6 +215,17 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     int rc = MLS2MC_OK;
     while (true) {
         if (beta == 1.0 && l == ctx->prob.l_max) break;
+        if (use_sur && !sur_ready && l >= sur_da && mls2mc_surrogate_n_pairs(ctx) >= 256) {
+            const auto ts = std::chrono::steady_clock::now();
+            const int epochs = cfg->sur_epochs > 0 ? cfg->sur_epochs : 30;
+            std::vector<float> losses(epochs);
+            MLS_TRY(mls2mc_surrogate_train(ctx, epochs, cfg->sur_batch > 0 ? cfg->sur_batch : 256,
+                                           cfg->sur_lr > 0 ? cfg->sur_lr : 1e-3, cfg->seed ^ 0x7a11u,
+                                           losses.data(), stream));
+            res->sur_train_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
+            res->sur_final_loss = epochs ? losses.back() : 0.0;
+            sur_ready = true;
+        }
         if (stage >= max_stages) { set_error("run: stage cap reached"); rc = MLS2MC_ESINGULAR; break; }
         bool do_lu, checked = false;
         if (beta == 1.0) do_lu = true;
@@ -250,12 +296,14 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     res->final_level = l;
     res->final_beta = beta;
     MLS_CHECK_HIP(hipMemcpyAsync(theta_out, R.theta, sizeof(double) * J * K, hipMemcpyDeviceToDevice, s));
-    int64_t c3[3];
+    int64_t c3[32];
     MLS_CHECK_HIP(hipMemcpyAsync(c3, R.counters, sizeof(c3), hipMemcpyDeviceToHost, s));
     MLS_CHECK_HIP(hipStreamSynchronize(s));
     res->iters_total = c3[0];
     res->not_converged = c3[1];
     res->accepted = c3[2];
+    res->stage1_passed = c3[3];
+    for (int lv = 0; lv <= kMaxLevel && lv < 16; ++lv) res->solves[lv] += c3[8 + lv];  // delayed-acceptance solves
     res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }

@@ -179,8 +179,10 @@ template <bool EXP>
 __global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ theta,
                                                    const double* __restrict__ B,
                                                    double* __restrict__ out, int64_t N, int K,
-                                                   int64_t ne)
+                                                   int64_t ne, const int64_t* __restrict__ N_dev)
 {
+    if (N_dev) N = min(N, *N_dev);
+    if ((int64_t)blockIdx.y * 64 >= N) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int64_t e0 = (int64_t)blockIdx.x * 64;
@@ -216,8 +218,10 @@ __global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ th
 __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ theta,
                                                     const __hip_bfloat16* __restrict__ Bt,
                                                     float* __restrict__ out, int64_t N, int K,
-                                                    int Kp, int64_t ne)
+                                                    int Kp, int64_t ne, const int64_t* __restrict__ N_dev)
 {
+    if (N_dev) N = min(N, *N_dev);
+    if ((int64_t)blockIdx.y * 64 >= N) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int64_t e0 = (int64_t)blockIdx.x * 64;
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ t
 }
 
 int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void* out, int kind,
-                    hipStream_t s)
+                    hipStream_t s, const int64_t* N_dev)
 {
     if (N == 0) return MLS2MC_OK;
     const int64_t ne = n_elem(l);
@@ -267,13 +271,13 @@ int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void
     ProfRec rec;
     if (ctx->prof_on) MLS_TRY(prof_begin(ctx, MLS2MC_PROF_GEMM, l, N, s, &rec));
     if (kind == MLS2MC_FIELD_LOG_F64) {
-        kl_gemm_f64<false><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne);
+        kl_gemm_f64<false><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne, N_dev);
     } else if (kind == MLS2MC_FIELD_KAPPA_F64) {
-        kl_gemm_f64<true><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne);
+        kl_gemm_f64<true><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne, N_dev);
     } else if (kind == MLS2MC_FIELD_KAPPA_F32) {
         MLS_REQUIRE(ctx->d_B16[l] != nullptr, "kl_field: BF16 basis needs precision MIXED");
         const int Kp = (K + 31) / 32 * 32;
-        kl_gemm_bf16<<<grid, 256, 0, s>>>(theta, ctx->d_B16[l], (float*)out, N, K, Kp, ne);
+        kl_gemm_bf16<<<grid, 256, 0, s>>>(theta, ctx->d_B16[l], (float*)out, N, K, Kp, ne, N_dev);
     } else {
         MLS_REQUIRE(false, "kl_field: unknown output kind");
     }

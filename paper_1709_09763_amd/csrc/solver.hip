@@ -263,6 +263,7 @@ __device__ void setup_hierarchy(T* slot, int l, const Lv<T>& F, const KT* __rest
 struct SolveParams {
     int l;
     int64_t N;
+    const int64_t* N_dev;
     const void* kappa;
     void* ws;
     int64_t slot_elems;
@@ -319,8 +320,9 @@ __global__ __launch_bounds__(BS) void solve_f64_kernel(SolveParams P)
     F.n = 1 << l; F.lg = l; F.s = F.n + 1;
     const int ne = 2 << (2 * l);
     const double h2 = 1.0 / (double)(F.n * F.n);
+    const int64_t NN = P.N_dev ? min(P.N, *P.N_dev) : P.N;
 
-    for (int64_t q = blockIdx.x; q < P.N; q += gridDim.x) {
+    for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
         const double* kap = (const double*)P.kappa + q * ne;
         zero_boundary<BS>(X, F.n);
         zero_boundary<BS>(Z, F.n);
@@ -398,8 +400,9 @@ __global__ __launch_bounds__(BS) void solve_mixed_kernel(SolveParams P)
     const double h2 = 1.0 / (double)(F.n * F.n);
     const float inner_tol2 = 1e-10f;  // inner relative reduction 1e-5 per sweep
     const int max_outer = 12;
+    const int64_t NN = P.N_dev ? min(P.N, *P.N_dev) : P.N;
 
-    for (int64_t q = blockIdx.x; q < P.N; q += gridDim.x) {
+    for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
         const float* kap = (const float*)P.kappa + q * ne;
         zero_boundary<BS>(X, F.n);
         zero_boundary<BS>(Z, F.n);
@@ -502,7 +505,7 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     if (grid < 1) grid = 1;
     MLS_TRY(ctx->ws_solver.ensure((size_t)grid * slot * esz));
     SolveParams P;
-    P.l = l; P.N = a.N; P.kappa = a.kappa; P.ws = ctx->ws_solver.ptr; P.slot_elems = slot;
+    P.l = l; P.N = a.N; P.N_dev = a.N_dev; P.kappa = a.kappa; P.ws = ctx->ws_solver.ptr; P.slot_elems = slot;
     P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
     P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w; P.nobs = ctx->nobs;
     P.inv_sigma = 1.0 / ctx->prob.sigma_n;

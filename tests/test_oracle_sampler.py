@@ -151,3 +151,42 @@ def test_pde_brute_force_posterior_k1():
     se = ms.std(ddof=1) / np.sqrt(R)
     assert abs(ms.mean() - mq) < 4 * se + 0.02 * np.sqrt(vq), (ms.mean(), mq, se)
     assert abs(np.mean(vs) / vq - 1) < 0.15, (np.mean(vs), vq)
+
+
+def test_delayed_acceptance_rule_special_cases():
+    rng = inputs.rng(77)
+    for _ in range(2000):
+        po, pn = rng.normal(0, 3, 2)
+        u1, u2 = 1.0 - inputs.uniforms53(int(rng.integers(1 << 30)), 2)
+        # perfect surrogate: stage 2 always accepts after stage 1
+        a, s1 = oracle.da_accept(po, pn, po, pn, u1, u2)
+        assert a == s1
+        # constant surrogate: stage 1 always passes; stage 2 is plain MH with u2
+        a, s1 = oracle.da_accept(po, pn, 5.0, 5.0, u1, u2)
+        assert s1 and a == oracle.mh_accept(po, pn, u2)
+    # stage 1 rejects -> no move, whatever stage 2 would say
+    a, s1 = oracle.da_accept(0.0, -100.0, 0.0, 100.0, 0.5, 0.5)
+    assert not s1 and not a
+
+
+@pytest.mark.slow
+def test_delayed_acceptance_keeps_linear_gaussian_posterior():
+    # a deliberately poor surrogate (perturbed forward matrix) must not bias
+    # the posterior: the two-stage rule is exact for any surrogate
+    s = 0.2
+    A, E, y = _lin_problem(s=s, seed=11)
+    m, C, logZ = _lin_posterior(A + 2.0 ** -6 * E, y, s)
+    S = A + 0.3 * inputs.rng(12).standard_normal(A.shape)
+    R, J = 8, 2000
+    means, vars_, pass_frac = [], [], []
+    for seed in range(R):
+        r = oracle.run_sampler(y, model="linear", l_min=3, l_max=3, K=3, nobs=4, sigma_n=s, J=J,
+                               seed=300 + seed, lin_A=A, lin_E=E, da_S=S)
+        means.append(r["theta"].mean(0))
+        vars_.append(r["theta"].var(0))
+        pass_frac.append(r["stage1_passed"] / r["proposed"])
+    means = np.array(means)
+    se = means.std(0, ddof=1) / np.sqrt(R)
+    assert np.all(np.abs(means.mean(0) - m) < 4 * se + 0.02 * np.sqrt(np.diag(C)))
+    np.testing.assert_allclose(np.mean(vars_, 0), np.diag(C), rtol=0.1)
+    assert 0.05 < np.mean(pass_frac) < 0.95  # the surrogate does filter
