@@ -126,6 +126,25 @@ int mls2mc_forward_field(mls2mc_ctx* ctx, int l, int64_t N, const double* kappa,
                          double* G_out, double* p_out, int8_t* status_out,
                          int32_t* iters_out, void* stream);
 
+/* Fused forward over many items (e.g. independent sampler instances and
+ * levels): for each item, G_out = G_l(theta) as in mls2mc_forward, and
+ * phi_out = Phi (Sec. 2.1 potential) when y is given.  All items run in one
+ * grouped KL GEMM launch and one persistent solver launch over a device
+ * work list (finest level first), cut into several such pairs only when
+ * the coefficient buffer would exceed 8 GiB.  items is a host array.        */
+typedef struct {
+    int l;                /* level, within [l_min, l_max] of the context         */
+    int64_t N;            /* particles                                            */
+    const double* theta;  /* N x K                                                */
+    double* G_out;        /* N x N_obs                                            */
+    const double* y;      /* N_obs data for the fused potential, or NULL          */
+    double* phi_out;      /* N, or NULL (needs y)                                 */
+    int8_t* status_out;   /* N, or NULL                                           */
+    int32_t* iters_out;   /* N, or NULL                                           */
+} mls2mc_forward_item;
+int mls2mc_forward_batch(mls2mc_ctx* ctx, int n_items, const mls2mc_forward_item* items,
+                         void* stream);
+
 /* Potential (Sec. 2.1): phi_out[q] = 1/2 sum_o ((y_o - G[q,o]) / sigma_n)^2.
  * G: N x N_obs, y: N_obs, phi_out: N (all double, device).                 */
 int mls2mc_loglik(mls2mc_ctx* ctx, int64_t N, const double* G, const double* y,
@@ -277,6 +296,7 @@ typedef struct {
     int64_t da_proposed;   /* delayed acceptance: proposals screened         */
     double sur_train_seconds;
     double sur_final_loss;
+    int64_t graphs_launched; /* mls2mc_run_batch: HIP graphs launched        */
     /* optional per-stage log (host arrays of max_stage_log entries, or NULL).
      * stage types: 0 tempering, 1 tempering after a discarded look-ahead,
      * 2 first bridging sub-step of a level update chosen by the look-ahead,
@@ -298,6 +318,28 @@ typedef struct {
  * resampling uniforms, 4 pCN normals, 5 pCN uniforms.                      */
 int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const double* y,
                double* theta_out, mls2mc_run_result* res, void* stream);
+
+/* Many independent MLS^2MC instances (own data, seed, particle count and
+ * finest level; shared problem of the context) in lock-step rounds: each
+ * round every active instance performs one SMC sub-step.  The forward
+ * solves of a phase, across all instances and levels, run as one fused
+ * work-list launch, and with use_graphs != 0 the mutation phase of each round
+ * (all pCN steps of all instances) is captured as a HIP graph and launched
+ * once.  Each instance draws the Philox streams of mls2mc_run with its own
+ * seed.  cfg supplies the shared settings (J and seed are per instance;
+ * the surrogate fields must be 0).  res: n_inst results.  stream may be NULL
+ * (a private stream is used; capture needs a non-default stream).
+ * Synchronous.                                                             */
+typedef struct {
+    int64_t J;          /* particles                                        */
+    int l_max;          /* finest level of this instance                    */
+    const double* y;    /* N_obs data (device)                              */
+    uint64_t seed;      /* Philox key                                       */
+    double* theta_out;  /* J x K final particles (device)                   */
+} mls2mc_instance;
+int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, int n_inst,
+                     const mls2mc_instance* inst, mls2mc_run_result* res, int use_graphs,
+                     void* stream);
 
 /* Philox4x32-10 uniforms/normals on the device, the same streams mls2mc_run
  * uses (6: second-stage uniforms of delayed acceptance): out[i] for idx = i, counter {idx, sub, stage, stream}.  normal = 0:

@@ -42,13 +42,24 @@ _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 
 
+class ForwardItem(C.Structure):
+    _fields_ = [("l", C.c_int), ("N", C.c_int64), ("theta", C.c_void_p), ("G_out", C.c_void_p),
+                ("y", C.c_void_p), ("phi_out", C.c_void_p), ("status_out", C.c_void_p),
+                ("iters_out", C.c_void_p)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("J", C.c_int64), ("l_max", C.c_int), ("y", C.c_void_p), ("seed", C.c_uint64),
+                ("theta_out", C.c_void_p)]
+
+
 class RunResult(C.Structure):
     _fields_ = [("n_stages", C.c_int), ("final_level", C.c_int), ("final_beta", C.c_double),
                 ("log_Z", C.c_double), ("solves", C.c_int64 * 16), ("accepted", C.c_int64),
                 ("proposed", C.c_int64), ("iters_total", C.c_int64), ("not_converged", C.c_int64),
                 ("seconds", C.c_double), ("stage1_passed", C.c_int64), ("da_proposed", C.c_int64),
                 ("sur_train_seconds", C.c_double), ("sur_final_loss", C.c_double),
-                ("max_stage_log", C.c_int), ("stage_type", _ip),
+                ("graphs_launched", C.c_int64), ("max_stage_log", C.c_int), ("stage_type", _ip),
                 ("stage_level", _ip), ("stage_beta", _dp), ("stage_zeta", _dp),
                 ("stage_ess", _dp), ("stage_acc_rate", _dp)]
 
@@ -108,6 +119,9 @@ def lib():
         L.mls2mc_surrogate_predict.argtypes = [_vp, C.c_int64, _vp, _vp, _vp]
         L.mls2mc_surrogate_loss_grad.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
         L.mls2mc_pcn_step_da.argtypes = [_vp, C.POINTER(Stage), C.c_int64] + [_vp] * 14
+        L.mls2mc_forward_batch.argtypes = [_vp, C.c_int, C.POINTER(ForwardItem), _vp]
+        L.mls2mc_run_batch.argtypes = [_vp, C.POINTER(RunConfig), C.c_int, C.POINTER(Instance),
+                                       C.POINTER(RunResult), C.c_int, _vp]
         L.mls2mc_profile.argtypes = [_vp, C.c_int]
         L.mls2mc_profile_read.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(ProfEntry)]
         _lib = L
@@ -196,6 +210,23 @@ def mls2mc_forward_field(h, l, kappa, G_out, p_out=None, status_out=None, iters_
         _ptr(iters_out, torch.int32, (N,), "iters_out", True), _stream()), "mls2mc_forward_field")
 
 
+def mls2mc_forward_batch(h, items):
+    """items: list of dicts l, theta, G_out and optional y, phi_out, status_out, iters_out"""
+    arr = (ForwardItem * max(1, len(items)))()
+    nobs = mls2mc_n_obs(h)
+    for i, it in enumerate(items):
+        N = it["theta"].shape[0]
+        arr[i].l = it["l"]
+        arr[i].N = N
+        arr[i].theta = _ptr(it["theta"], torch.float64, name="theta")
+        arr[i].G_out = _ptr(it["G_out"], torch.float64, (N, nobs), "G_out")
+        arr[i].y = _ptr(it.get("y"), torch.float64, (nobs,), "y", True)
+        arr[i].phi_out = _ptr(it.get("phi_out"), torch.float64, (N,), "phi_out", True)
+        arr[i].status_out = _ptr(it.get("status_out"), torch.int8, (N,), "status_out", True)
+        arr[i].iters_out = _ptr(it.get("iters_out"), torch.int32, (N,), "iters_out", True)
+    _check(lib().mls2mc_forward_batch(h, len(items), arr, _stream()), "mls2mc_forward_batch")
+
+
 def mls2mc_loglik(h, G, y, phi_out):
     N = G.shape[0]
     _check(lib().mls2mc_loglik(h, N, _ptr(G, torch.float64, name="G"),
@@ -246,6 +277,52 @@ def mls2mc_pcn_step(h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi
         _ptr(phi_hi, f64, name="phi_hi", optional=True), _ptr(y, f64, name="y"),
         _ptr(xi, f64, name="xi"), _ptr(u, f64, name="u"),
         _ptr(accepted_out, torch.uint8, (N,), "accepted_out", True), _stream()), "mls2mc_pcn_step")
+
+
+def _result_dict(res, arrs):
+    n = min(res.n_stages, res.max_stage_log)
+    out = dict(n_stages=res.n_stages, final_level=res.final_level, final_beta=res.final_beta,
+               log_Z=res.log_Z, solves=list(res.solves), accepted=res.accepted,
+               proposed=res.proposed, iters_total=res.iters_total,
+               not_converged=res.not_converged, seconds=res.seconds,
+               stage1_passed=res.stage1_passed, da_proposed=res.da_proposed,
+               sur_train_seconds=res.sur_train_seconds, sur_final_loss=res.sur_final_loss,
+               graphs_launched=res.graphs_launched)
+    for k, v in arrs.items():
+        out[k] = v[:n].copy()
+    return out
+
+
+def _stage_arrays(res, ms):
+    import numpy as np
+    arrs = dict(stage_type=np.zeros(ms, np.int32), stage_level=np.zeros(ms, np.int32),
+                stage_beta=np.zeros(ms), stage_zeta=np.zeros(ms), stage_ess=np.zeros(ms),
+                stage_acc_rate=np.zeros(ms))
+    res.max_stage_log = ms
+    res.stage_type = arrs["stage_type"].ctypes.data_as(_ip)
+    res.stage_level = arrs["stage_level"].ctypes.data_as(_ip)
+    for k in ("stage_beta", "stage_zeta", "stage_ess", "stage_acc_rate"):
+        setattr(res, k, arrs[k].ctypes.data_as(_dp))
+    return arrs
+
+
+def mls2mc_run_batch(h, cfg: RunConfig, instances, use_graphs=True, max_stage_log=1000):
+    """instances: list of dicts J, l_max, y (device), seed, theta_out (device J x K)"""
+    n = len(instances)
+    inst = (Instance * n)()
+    res = (RunResult * n)()
+    arrs = []
+    for i, d in enumerate(instances):
+        inst[i].J = d["J"]
+        inst[i].l_max = d["l_max"]
+        inst[i].y = _ptr(d["y"], torch.float64, name="y")
+        inst[i].seed = d["seed"]
+        inst[i].theta_out = _ptr(d["theta_out"], torch.float64, name="theta_out")
+        arrs.append(_stage_arrays(res[i], max_stage_log))
+    torch.cuda.synchronize()
+    _check(lib().mls2mc_run_batch(h, C.byref(cfg), n, inst, res, int(use_graphs), None),
+           "mls2mc_run_batch")
+    return [_result_dict(res[i], arrs[i]) for i in range(n)]
 
 
 def mls2mc_run(h, cfg: RunConfig, y, theta_out, max_stage_log=4000):
@@ -460,6 +537,15 @@ class Context:
         mls2mc_pcn_step(self.h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y,
                         xi, u, acc)
         return acc
+
+    def run_batch(self, instances, J_tilde=0, tau_star=1.0, n_mcmc=5, s_pcn=0.5, use_graphs=True):
+        cfg = RunConfig(0, J_tilde, tau_star, 0.0, 0.0, n_mcmc, s_pcn, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0)
+        for d in instances:
+            d.setdefault("theta_out", torch.empty((d["J"], self.K), dtype=torch.float64, device="cuda:0"))
+        out = mls2mc_run_batch(self.h, cfg, instances, use_graphs)
+        for d, o in zip(instances, out):
+            o["theta"] = d["theta_out"]
+        return out
 
     def run(self, y, J, J_tilde=0, tau_star=1.0, tau_lu=0.0, eps=0.0, n_mcmc=5, s_pcn=0.5, seed=0,
             max_stages=0, surrogate=False, sur_collect_max_level=0, sur_da_min_level=0, sur_pairs=0,

@@ -200,6 +200,10 @@ int mls2mc_destroy(mls2mc_ctx* ctx)
     ctx->ws_run.release();
     ctx->ws_prof.release();
     ctx->ws_da.release();
+    ctx->ws_list.release();
+    ctx->ws_batch.release();
+    if (ctx->h_list) (void)hipHostFree(ctx->h_list);
+    if (ctx->h_list_ev) (void)hipEventDestroy(ctx->h_list_ev);
     surrogate_destroy(ctx);
     if (ctx->d_chunk_count) (void)hipFree(ctx->d_chunk_count);
     prof_clear(ctx);

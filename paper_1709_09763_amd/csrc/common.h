@@ -109,6 +109,8 @@ struct mls2mc_ctx {
     int n_cu = 256;                             // compute units of the device
     int solver_grid[mls::kMaxLevel + 1] = {};  // persistent grid per level (0 = auto)
     int solver_block[mls::kMaxLevel + 1] = {};
+    int solver_nu[mls::kMaxLevel + 1] = {};     // Gauss-Seidel sweeps per V-cycle side (0 = 1)
+    int list_grid = 0, list_block = 0;          // work-list launch shape (0 = auto)
     double rtol = 1e-11;
     int max_iters = 200;
     // instrumentation (see mls2mc_profile)
@@ -118,6 +120,11 @@ struct mls2mc_ctx {
     mls::DevBuf ws_prof;              // iteration scratch when the caller passes none
     mls::Surrogate* sur = nullptr;    // learned surrogate (mlp.hip)
     mls::DevBuf ws_da;                // delayed-acceptance scratch
+    mls::DevBuf ws_list;              // device copies of work lists
+    mls::DevBuf ws_batch;             // state of mls2mc_run_batch
+    void* h_list = nullptr;           // pinned host staging of work lists
+    size_t h_list_bytes = 0;
+    hipEvent_t h_list_ev = nullptr;   // last copy out of h_list
     int64_t* d_chunk_count = nullptr; // per-chunk device counts
 };
 
@@ -143,6 +150,54 @@ struct SolveArgs {
     const int64_t* N_dev = nullptr;  // device-side count <= N (null: N)
 };
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s);
+
+// one entry of a fused multi-instance / multi-level solver launch
+struct SolveItem {
+    int l;
+    int64_t N;
+    int64_t base;        // sum of N over the items before this one
+    const void* kappa;   // N x n_e(l)
+    double* G;           // N x nobs
+    double* phi;         // N or null (fused potential with y)
+    const double* y;
+    int8_t* status;      // N or null
+    int32_t* iters;      // N or null
+};
+int launch_solve_list(mls2mc_ctx* ctx, const SolveItem* items_dev, int n_items, int64_t total, int lmax,
+                      bool mixed, hipStream_t s);
+
+// one entry of a grouped KL GEMM launch (64 x 64 output tiles)
+struct GemmItem {
+    const double* theta;          // N x K
+    const double* B;              // K x n_e (FP64 basis of the level)
+    const __hip_bfloat16* B16;    // n_e x Kp (BF16 basis, mixed)
+    void* out;                    // N x n_e kappa (double, or float for mixed)
+    int64_t N, ne;
+    int64_t tile_base;            // tiles of the items before this one
+    int64_t tiles_x;              // ceil(ne / 64)
+};
+int launch_kl_list(mls2mc_ctx* ctx, const GemmItem* items_dev, int n_items, int64_t total_tiles, hipStream_t s);
+// build and enqueue one fused forward over many (level, theta) items
+struct FwdItem {
+    int l;
+    int64_t N;
+    const double* theta;
+    double* G;
+    const double* y;
+    double* phi;
+    int8_t* status;
+    int32_t* iters;
+};
+int forward_list(mls2mc_ctx* ctx, const std::vector<FwdItem>& items, hipStream_t s);
+struct ListChunk {  // one prepared (grouped GEMM, work-list solve) pair
+    const GemmItem* gemm;
+    const SolveItem* solve;
+    int n;
+    int64_t tiles, total;
+    int lmax;
+};
+int prepare_list(mls2mc_ctx* ctx, const std::vector<FwdItem>& items, std::vector<ListChunk>& out, hipStream_t s);
+int enqueue_list(mls2mc_ctx* ctx, const std::vector<ListChunk>& chunks, hipStream_t s);
 
 int launch_loglik(mls2mc_ctx* ctx, int64_t N, const double* G, const double* y, double* phi,
                   hipStream_t s);

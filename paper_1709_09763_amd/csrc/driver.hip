@@ -109,6 +109,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     res->stage1_passed = res->da_proposed = 0;
     res->sur_train_seconds = 0.0;
     res->sur_final_loss = 0.0;
+    res->graphs_launched = 0;
     bool sur_ready = false;
     if (use_sur) {
         MLS_TRY(mls2mc_surrogate_init(ctx, cfg->sur_hidden > 0 ? cfg->sur_hidden : 256,

@@ -176,17 +176,14 @@ int build_kl_tables(mls2mc_ctx* ctx)
 // i = lane%16, k = lane/16; B[k][j] with j = lane%16, k = lane/16.  Result:
 // lane holds D[lane/16 + 4v][lane%16], v = 0..3 (FP64 accumulator layout).
 template <bool EXP>
-__global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ theta,
-                                                   const double* __restrict__ B,
-                                                   double* __restrict__ out, int64_t N, int K,
-                                                   int64_t ne, const int64_t* __restrict__ N_dev)
+__device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ theta, const double* __restrict__ B,
+                                              double* __restrict__ out, int64_t N, int K, int64_t ne,
+                                              int64_t bx, int64_t by)
 {
-    if (N_dev) N = min(N, *N_dev);
-    if ((int64_t)blockIdx.y * 64 >= N) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
-    const int64_t e0 = (int64_t)blockIdx.x * 64;
-    const int64_t p0 = (int64_t)blockIdx.y * 64 + wv * 16;
+    const int64_t e0 = bx * 64;
+    const int64_t p0 = by * 64 + wv * 16;
     const int64_t prow = p0 + r;
     dbl4 acc[4];
 #pragma unroll
@@ -210,22 +207,30 @@ __global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ th
         }
 }
 
+template <bool EXP>
+__global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ theta,
+                                                   const double* __restrict__ B,
+                                                   double* __restrict__ out, int64_t N, int K,
+                                                   int64_t ne, const int64_t* __restrict__ N_dev)
+{
+    if (N_dev) N = min(N, *N_dev);
+    if ((int64_t)blockIdx.y * 64 >= N) return;
+    gemm_f64_tile<EXP>(theta, B, out, N, K, ne, blockIdx.x, blockIdx.y);
+}
+
 // BF16 on the matrix cores with FP32 accumulation: v_mfma_f32_16x16x32_bf16.
 // Operand lanes: A[i][8*(lane/16) + 0..7] with i = lane%16 (theta rows,
 // rounded to BF16 here); B^T[j][8*(lane/16) + 0..7] with j = lane%16 (the
 // basis is stored transposed, n_e x Kp, K padded to 32 with zeros).
 // Output kappa = expf(a) in FP32.  Tile 64 x 64 as above.
-__global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ theta,
-                                                    const __hip_bfloat16* __restrict__ Bt,
-                                                    float* __restrict__ out, int64_t N, int K,
-                                                    int Kp, int64_t ne, const int64_t* __restrict__ N_dev)
+__device__ __forceinline__ void gemm_bf16_tile(const double* __restrict__ theta,
+                                               const __hip_bfloat16* __restrict__ Bt, float* __restrict__ out,
+                                               int64_t N, int K, int Kp, int64_t ne, int64_t bx, int64_t by)
 {
-    if (N_dev) N = min(N, *N_dev);
-    if ((int64_t)blockIdx.y * 64 >= N) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
-    const int64_t e0 = (int64_t)blockIdx.x * 64;
-    const int64_t p0 = (int64_t)blockIdx.y * 64 + wv * 16;
+    const int64_t e0 = bx * 64;
+    const int64_t p0 = by * 64 + wv * 16;
     const int64_t prow = p0 + r;
     flt4 acc[4];
 #pragma unroll
@@ -258,6 +263,45 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ t
             const int64_t row = p0 + 4 * kq + v, col = e0 + c * 16 + r;
             if (row < N && col < ne) out[row * ne + col] = expf(acc[c][v]);
         }
+}
+
+__global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ theta,
+                                                    const __hip_bfloat16* __restrict__ Bt,
+                                                    float* __restrict__ out, int64_t N, int K,
+                                                    int Kp, int64_t ne, const int64_t* __restrict__ N_dev)
+{
+    if (N_dev) N = min(N, *N_dev);
+    if ((int64_t)blockIdx.y * 64 >= N) return;
+    gemm_bf16_tile(theta, Bt, out, N, K, Kp, ne, blockIdx.x, blockIdx.y);
+}
+
+// Grouped launch: one 1-D grid over the 64x64 tiles of several items (each
+// its own theta, level basis and output).
+__global__ __launch_bounds__(256) void kl_gemm_list(const GemmItem* __restrict__ items, int n_items, int K,
+                                                    int Kp, int bf16)
+{
+    const int64_t t = blockIdx.x;
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    const GemmItem& it = items[lo];
+    const int64_t lt = t - it.tile_base;
+    const int64_t bx = lt % it.tiles_x, by = lt / it.tiles_x;
+    if (bf16) gemm_bf16_tile(it.theta, it.B16, (float*)it.out, it.N, K, Kp, it.ne, bx, by);
+    else gemm_f64_tile<true>(it.theta, it.B, (double*)it.out, it.N, K, it.ne, bx, by);
+}
+
+int launch_kl_list(mls2mc_ctx* ctx, const GemmItem* items_dev, int n_items, int64_t total_tiles, hipStream_t s)
+{
+    if (total_tiles == 0) return MLS2MC_OK;
+    MLS_REQUIRE(total_tiles < (int64_t(1) << 31), "kl_gemm_list: too many tiles");
+    const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
+    const int K = ctx->prob.K, Kp = (K + 31) / 32 * 32;
+    kl_gemm_list<<<(unsigned)total_tiles, 256, 0, s>>>(items_dev, n_items, K, Kp, mixed ? 1 : 0);
+    MLS_CHECK_HIP(hipGetLastError());
+    return MLS2MC_OK;
 }
 
 int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void* out, int kind,

@@ -26,6 +26,8 @@
 // the coarse correction and black then red after it, which makes the cycle
 // a symmetric positive definite preconditioner.  Coarsest level l = 1 has one
 // unknown and is solved exactly.
+#include <algorithm>
+
 #include "common.h"
 
 namespace mls {
@@ -176,7 +178,8 @@ __device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __rest
 }
 
 template <int BS, typename T>
-__device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs, T* __restrict__ sol)
+__device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs, T* __restrict__ sol,
+                       int nu)
 {
     if (l == 1) {  // the fine level is the coarsest: one unknown, exact
         if (threadIdx.x == 0) {
@@ -191,10 +194,12 @@ __device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs
         const Lv<T> L = (Lk == l) ? F : coarse_level(slot, l, Lk);
         const T* b = (Lk == l) ? rhs : L.b;
         T* x = (Lk == l) ? sol : L.x;
-        smooth_colour<BS>(L, b, x, 0, true);
-        __syncthreads();
-        smooth_colour<BS>(L, b, x, 1, false);
-        __syncthreads();
+        for (int sw = 0; sw < nu; ++sw) {  // (red, black)^nu
+            smooth_colour<BS>(L, b, x, 0, sw == 0);
+            __syncthreads();
+            smooth_colour<BS>(L, b, x, 1, false);
+            __syncthreads();
+        }
         MLS_FOR_INTERIOR(L, {
             L.res[c] = b[c] - (diag_at(L.wx, L.wy, c, L.s) * x[c] - nb_sum(L.wx, L.wy, x, c, L.s));
         })
@@ -234,10 +239,12 @@ __device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs
             x[c] += v;
         })
         __syncthreads();
-        smooth_colour<BS>(L, b, x, 1, false);
-        __syncthreads();
-        smooth_colour<BS>(L, b, x, 0, false);
-        __syncthreads();
+        for (int sw = 0; sw < nu; ++sw) {  // (black, red)^nu: the adjoint order
+            smooth_colour<BS>(L, b, x, 1, false);
+            __syncthreads();
+            smooth_colour<BS>(L, b, x, 0, false);
+            __syncthreads();
+        }
     }
 }
 
@@ -260,6 +267,209 @@ __device__ void setup_hierarchy(T* slot, int l, const Lv<T>& F, const KT* __rest
     }
 }
 
+// One particle's solve: its level, coefficient row and output rows.
+struct Job {
+    int l;
+    const void* kap;     // n_e coefficients (double, or float for mixed)
+    double* G;           // N_obs
+    double* p_out;       // M or null
+    int8_t* status;      // 1 or null
+    int32_t* iters;      // 1 or null
+    const double* y;     // data for the fused potential, or null
+    double* phi;         // 1 or null
+    const int32_t* obs_idx;
+    const double* obs_w;
+};
+
+struct Common {
+    int nobs;
+    double inv_sigma;
+    double tol2;
+    int max_iters;
+    int nu;
+};
+
+template <int BS, typename T>
+__device__ void observe_and_store(const Job& J, const Common& C, const T* X, int n, int8_t st, int it,
+                                  double* red)
+{
+    double ph = 0.0;
+    for (int o = threadIdx.x; o < C.nobs; o += BS) {
+        double g = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g += J.obs_w[3 * o + k] * (double)X[J.obs_idx[3 * o + k]];
+        J.G[o] = g;
+        if (J.y) {
+            const double r = (J.y[o] - g) * C.inv_sigma;
+            ph += r * r;
+        }
+    }
+    if (J.p_out) {
+        const int64_t M = (int64_t)(n - 1) * (n - 1);
+        for (int64_t t = threadIdx.x; t < M; t += BS) {
+            const int j = 1 + (int)(t / (n - 1)), i = 1 + (int)(t % (n - 1));
+            J.p_out[t] = (double)X[j * (n + 1) + i];
+        }
+    }
+    if (J.y) ph = block_sum<BS>(ph, red);
+    if (threadIdx.x == 0) {
+        if (J.status) *J.status = st;
+        if (J.iters) *J.iters = it;
+        if (J.phi) *J.phi = 0.5 * ph;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ inline Lv<T> fine_level(T* slot, int l)
+{
+    const int64_t S = pad_sz(l);
+    Lv<T> F;
+    F.wx = slot + 5 * S; F.wy = slot + 6 * S; F.res = slot + 7 * S;
+    F.x = slot + 2 * S; F.b = slot + S; F.kap = nullptr;
+    F.n = 1 << l; F.lg = l; F.s = F.n + 1;
+    return F;
+}
+
+// ---------------------------------------------------------- FP64 solve --
+template <int BS>
+__device__ void solve_one_f64(double* slot, const Job& J, const Common& C, double* red)
+{
+    const int l = J.l;
+    const int64_t S = pad_sz(l);
+    double *X = slot, *R = slot + S, *Z = slot + 2 * S, *Pv = slot + 3 * S, *Q = slot + 4 * S;
+    const Lv<double> F = fine_level(slot, l);
+    const double h2 = 1.0 / (double)(F.n * F.n);
+    const double* kap = (const double*)J.kap;
+    zero_boundary<BS>(X, F.n);
+    zero_boundary<BS>(Z, F.n);
+    zero_boundary<BS>(Pv, F.n);
+    setup_hierarchy<BS>(slot, l, F, kap);
+    MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
+    __syncthreads();
+    vcycle<BS>(slot, l, F, R, Z, C.nu);
+    double rz = 0.0;
+    MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; Pv[c] = Z[c]; })
+    rz = block_sum<BS>(rz, red);
+    const double rz0 = rz;
+    int it = 0;
+    int8_t st = 1;
+    if (!(rz0 > 0.0) || !isfinite(rz0)) st = 2;
+    while (st == 1 && it < C.max_iters) {
+        double pq = 0.0;
+        MLS_FOR_INTERIOR(F, {
+            const double v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
+            Q[c] = v;
+            pq += Pv[c] * v;
+        })
+        pq = block_sum<BS>(pq, red);
+        const double alpha = rz / pq;
+        MLS_FOR_INTERIOR(F, {
+            X[c] += alpha * Pv[c];
+            R[c] -= alpha * Q[c];
+        })
+        __syncthreads();
+        vcycle<BS>(slot, l, F, R, Z, C.nu);
+        double rzn = 0.0;
+        MLS_FOR_INTERIOR(F, { rzn += R[c] * Z[c]; })
+        rzn = block_sum<BS>(rzn, red);
+        ++it;
+        if (!isfinite(rzn)) { st = 2; break; }
+        if (rzn <= C.tol2 * rz0) { st = 0; break; }
+        const double beta = rzn / rz;
+        rz = rzn;
+        MLS_FOR_INTERIOR(F, { Pv[c] = Z[c] + beta * Pv[c]; })
+        __syncthreads();
+    }
+    observe_and_store<BS>(J, C, X, F.n, st, it, red);
+}
+
+// --------------------------------------------------------- mixed solve --
+// FP32 multigrid-PCG inside FP64 iterative refinement: the system matrix is
+// the one defined by the FP32 edge weights (promoted exactly to FP64 for the
+// residual), r64 = b - A x64 in FP64, the correction A d = r64 is solved
+// with FP32 MG-PCG to a loose tolerance, x64 += d.  The coarsest solve of
+// the hierarchy is done in FP64.
+template <int BS>
+__device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, double* red)
+{
+    const int l = J.l;
+    const int64_t S = pad_sz(l);
+    float *X = slot, *R = slot + S, *Z = slot + 2 * S, *Pv = slot + 3 * S, *Q = slot + 4 * S;
+    const Lv<float> F = fine_level(slot, l);
+    const int64_t hier = slot_elems_hd(l, false);
+    double* X64 = (double*)(slot + ((hier + 1) & ~int64_t(1)));
+    double* R64 = X64 + S;
+    const double h2 = 1.0 / (double)(F.n * F.n);
+    const double inner_tol2 = 1e-10;  // relative reduction 1e-5 per refinement sweep
+    const int max_outer = 12;
+    const float* kap = (const float*)J.kap;
+    zero_boundary<BS>(X, F.n);
+    zero_boundary<BS>(Z, F.n);
+    zero_boundary<BS>(Pv, F.n);
+    zero_boundary<BS>(X64, F.n);
+    setup_hierarchy<BS>(slot, l, F, kap);
+    MLS_FOR_INTERIOR(F, { X64[c] = 0.0; R64[c] = h2; })
+    __syncthreads();
+    double rr0 = 0.0;
+    MLS_FOR_INTERIOR(F, { rr0 += h2 * h2; })
+    rr0 = block_sum<BS>(rr0, red);
+    int it = 0;
+    int8_t st = 1;
+    for (int outer = 0; outer < max_outer && st == 1; ++outer) {
+        MLS_FOR_INTERIOR(F, { X[c] = 0.f; R[c] = (float)R64[c]; })
+        __syncthreads();
+        vcycle<BS>(slot, l, F, R, Z, C.nu);
+        double rz = 0.0;
+        MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; Pv[c] = Z[c]; })
+        rz = block_sum<BS>(rz, red);
+        const double rzi0 = rz;
+        for (int k = 0; k < C.max_iters && rz > 0.0; ++k) {
+            double pq = 0.0;
+            MLS_FOR_INTERIOR(F, {
+                const float v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
+                Q[c] = v;
+                pq += (double)Pv[c] * (double)v;
+            })
+            pq = block_sum<BS>(pq, red);
+            const float alpha = (float)(rz / pq);
+            MLS_FOR_INTERIOR(F, {
+                X[c] += alpha * Pv[c];
+                R[c] -= alpha * Q[c];
+            })
+            __syncthreads();
+            vcycle<BS>(slot, l, F, R, Z, C.nu);
+            double rzn = 0.0;
+            MLS_FOR_INTERIOR(F, { rzn += (double)R[c] * (double)Z[c]; })
+            rzn = block_sum<BS>(rzn, red);
+            ++it;
+            if (!isfinite(rzn)) { st = 2; break; }
+            if (rzn <= inner_tol2 * rzi0) break;
+            const float beta = (float)(rzn / rz);
+            rz = rzn;
+            MLS_FOR_INTERIOR(F, { Pv[c] = Z[c] + beta * Pv[c]; })
+            __syncthreads();
+        }
+        if (st == 2) break;
+        MLS_FOR_INTERIOR(F, { X64[c] += (double)X[c]; })
+        __syncthreads();
+        double rr = 0.0;
+        MLS_FOR_INTERIOR(F, {
+            const double d = (double)F.wx[c - 1] + (double)F.wx[c] + (double)F.wy[c - F.s] + (double)F.wy[c];
+            const double nb = (double)F.wx[c - 1] * X64[c - 1] + (double)F.wx[c] * X64[c + 1]
+                            + (double)F.wy[c - F.s] * X64[c - F.s] + (double)F.wy[c] * X64[c + F.s];
+            const double r = h2 - (d * X64[c] - nb);
+            R64[c] = r;
+            rr += r * r;
+        })
+        rr = block_sum<BS>(rr, red);
+        if (!isfinite(rr)) { st = 2; break; }
+        if (rr <= C.tol2 * rr0) st = 0;
+    }
+    observe_and_store<BS>(J, C, X64, F.n, st, it, red);
+}
+
+// ----------------------------------------------------- single-level kernel --
 struct SolveParams {
     int l;
     int64_t N;
@@ -275,206 +485,77 @@ struct SolveParams {
     double* phi;
     const int32_t* obs_idx;
     const double* obs_w;
-    int nobs;
-    double inv_sigma;
-    double tol2;
-    int max_iters;
+    Common C;
 };
 
-template <int BS, typename T>
-__device__ double observe_and_store(const SolveParams& P, int64_t q, const T* X, int n, double* red)
-{
-    double ph = 0.0;
-    for (int o = threadIdx.x; o < P.nobs; o += BS) {
-        double g = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) g += P.obs_w[3 * o + k] * (double)X[P.obs_idx[3 * o + k]];
-        P.G[q * P.nobs + o] = g;
-        if (P.y) {
-            const double r = (P.y[o] - g) * P.inv_sigma;
-            ph += r * r;
-        }
-    }
-    if (P.p_out) {
-        const int64_t M = (int64_t)(n - 1) * (n - 1);
-        for (int64_t t = threadIdx.x; t < M; t += BS) {
-            const int j = 1 + (int)(t / (n - 1)), i = 1 + (int)(t % (n - 1));
-            P.p_out[q * M + t] = (double)X[j * (n + 1) + i];
-        }
-    }
-    return P.y ? block_sum<BS>(ph, red) : 0.0;
-}
-
-// ------------------------------------------------------- FP64 kernel --
-template <int BS>
-__global__ __launch_bounds__(BS) void solve_f64_kernel(SolveParams P)
+template <int BS, bool MIXED>
+__global__ __launch_bounds__(BS) void solve_kernel(SolveParams P)
 {
     __shared__ double red[BS / 64];
     const int l = P.l;
-    double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
-    const int64_t S = pad_sz(l);
-    double *X = slot, *R = slot + S, *Z = slot + 2 * S, *Pv = slot + 3 * S, *Q = slot + 4 * S;
-    Lv<double> F;
-    F.wx = slot + 5 * S; F.wy = slot + 6 * S; F.res = slot + 7 * S;
-    F.x = Z; F.b = R; F.kap = nullptr;
-    F.n = 1 << l; F.lg = l; F.s = F.n + 1;
-    const int ne = 2 << (2 * l);
-    const double h2 = 1.0 / (double)(F.n * F.n);
+    const int64_t ne = int64_t(2) << (2 * l);
+    const int64_t M = ((int64_t(1) << l) - 1) * ((int64_t(1) << l) - 1);
     const int64_t NN = P.N_dev ? min(P.N, *P.N_dev) : P.N;
-
     for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
-        const double* kap = (const double*)P.kappa + q * ne;
-        zero_boundary<BS>(X, F.n);
-        zero_boundary<BS>(Z, F.n);
-        zero_boundary<BS>(Pv, F.n);
-        setup_hierarchy<BS>(slot, l, F, kap);
-        MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
-        __syncthreads();
-        vcycle<BS>(slot, l, F, R, Z);
-        double rz = 0.0;
-        MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; Pv[c] = Z[c]; })
-        rz = block_sum<BS>(rz, red);
-        const double rz0 = rz;
-        int it = 0;
-        int8_t st = 1;
-        if (!(rz0 > 0.0) || !isfinite(rz0)) st = 2;
-        while (st == 1 && it < P.max_iters) {
-            double pq = 0.0;
-            MLS_FOR_INTERIOR(F, {
-                const double v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
-                Q[c] = v;
-                pq += Pv[c] * v;
-            })
-            pq = block_sum<BS>(pq, red);
-            const double alpha = rz / pq;
-            MLS_FOR_INTERIOR(F, {
-                X[c] += alpha * Pv[c];
-                R[c] -= alpha * Q[c];
-            })
-            __syncthreads();
-            vcycle<BS>(slot, l, F, R, Z);
-            double rzn = 0.0;
-            MLS_FOR_INTERIOR(F, { rzn += R[c] * Z[c]; })
-            rzn = block_sum<BS>(rzn, red);
-            ++it;
-            if (!isfinite(rzn)) { st = 2; break; }
-            if (rzn <= P.tol2 * rz0) { st = 0; break; }
-            const double beta = rzn / rz;
-            rz = rzn;
-            MLS_FOR_INTERIOR(F, { Pv[c] = Z[c] + beta * Pv[c]; })
-            __syncthreads();
-        }
-        double ph = observe_and_store<BS>(P, q, X, F.n, red);
-        if (threadIdx.x == 0) {
-            if (P.status) P.status[q] = st;
-            if (P.iters) P.iters[q] = it;
-            if (P.phi) P.phi[q] = 0.5 * ph;
-        }
-        __syncthreads();
+        Job J;
+        J.l = l;
+        J.kap = MIXED ? (const void*)((const float*)P.kappa + q * ne) : (const void*)((const double*)P.kappa + q * ne);
+        J.G = P.G + q * P.C.nobs;
+        J.p_out = P.p_out ? P.p_out + q * M : nullptr;
+        J.status = P.status ? P.status + q : nullptr;
+        J.iters = P.iters ? P.iters + q : nullptr;
+        J.y = P.y;
+        J.phi = P.phi ? P.phi + q : nullptr;
+        J.obs_idx = P.obs_idx;
+        J.obs_w = P.obs_w;
+        if (MIXED) solve_one_mixed<BS>((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
+        else solve_one_f64<BS>((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
     }
 }
 
-// ----------------------------------------------------- mixed kernel --
-// FP32 multigrid-PCG inside FP64 iterative refinement: the system matrix is
-// the one defined by the FP32 edge weights (promoted exactly to FP64 for the
-// residual), r64 = b - A x64 in FP64, the correction A d = r64 is solved
-// with FP32 MG-PCG to a loose tolerance, x64 += d.  The coarsest solve of
-// the hierarchy is done in FP64.
-template <int BS>
-__global__ __launch_bounds__(BS) void solve_mixed_kernel(SolveParams P)
+// -------------------------------------------------- work-list kernel --
+// One persistent launch over the particles of many (instance, level)
+// items: particle p belongs to the item whose prefix range holds p; items
+// are ordered by level, finest first, so the costliest particles start
+// first.  Slots are sized for the finest level in the list.
+struct ListParams {
+    const SolveItem* items;
+    int n_items;
+    int64_t total;
+    void* ws;
+    int64_t slot_elems;
+    const int32_t* obs_idx[kMaxLevel + 1];
+    const double* obs_w[kMaxLevel + 1];
+    Common C;
+};
+
+template <int BS, bool MIXED>
+__global__ __launch_bounds__(BS) void solve_list_kernel(ListParams P)
 {
     __shared__ double red[BS / 64];
-    const int l = P.l;
-    float* slot = (float*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
-    const int64_t S = pad_sz(l);
-    float *X = slot, *R = slot + S, *Z = slot + 2 * S, *Pv = slot + 3 * S, *Q = slot + 4 * S;
-    Lv<float> F;
-    F.wx = slot + 5 * S; F.wy = slot + 6 * S; F.res = slot + 7 * S;
-    F.x = Z; F.b = R; F.kap = nullptr;
-    F.n = 1 << l; F.lg = l; F.s = F.n + 1;
-    // FP64 arrays after the float hierarchy (8-byte aligned: slot_elems even)
-    const int64_t hier = slot_elems_hd(l, false);
-    double* X64 = (double*)(slot + ((hier + 1) & ~int64_t(1)));
-    double* R64 = X64 + S;
-    const int ne = 2 << (2 * l);
-    const double h2 = 1.0 / (double)(F.n * F.n);
-    const float inner_tol2 = 1e-10f;  // inner relative reduction 1e-5 per sweep
-    const int max_outer = 12;
-    const int64_t NN = P.N_dev ? min(P.N, *P.N_dev) : P.N;
-
-    for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
-        const float* kap = (const float*)P.kappa + q * ne;
-        zero_boundary<BS>(X, F.n);
-        zero_boundary<BS>(Z, F.n);
-        zero_boundary<BS>(Pv, F.n);
-        zero_boundary<BS>(X64, F.n);
-        setup_hierarchy<BS>(slot, l, F, kap);
-        MLS_FOR_INTERIOR(F, { X64[c] = 0.0; R64[c] = h2; })
-        __syncthreads();
-        double rr0 = 0.0;
-        MLS_FOR_INTERIOR(F, { rr0 += h2 * h2; })
-        rr0 = block_sum<BS>(rr0, red);
-        int it = 0;
-        int8_t st = 1;
-        for (int outer = 0; outer < max_outer && st == 1; ++outer) {
-            // inner FP32 PCG on A d = r64, d in X (float), zero start
-            MLS_FOR_INTERIOR(F, { X[c] = 0.f; R[c] = (float)R64[c]; })
-            __syncthreads();
-            vcycle<BS>(slot, l, F, R, Z);
-            double rz = 0.0;
-            MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; Pv[c] = Z[c]; })
-            rz = block_sum<BS>(rz, red);
-            const double rzi0 = rz;
-            for (int k = 0; k < P.max_iters && rz > 0.0; ++k) {
-                double pq = 0.0;
-                MLS_FOR_INTERIOR(F, {
-                    const float v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
-                    Q[c] = v;
-                    pq += (double)Pv[c] * (double)v;
-                })
-                pq = block_sum<BS>(pq, red);
-                const float alpha = (float)(rz / pq);
-                MLS_FOR_INTERIOR(F, {
-                    X[c] += alpha * Pv[c];
-                    R[c] -= alpha * Q[c];
-                })
-                __syncthreads();
-                vcycle<BS>(slot, l, F, R, Z);
-                double rzn = 0.0;
-                MLS_FOR_INTERIOR(F, { rzn += (double)R[c] * (double)Z[c]; })
-                rzn = block_sum<BS>(rzn, red);
-                ++it;
-                if (!isfinite(rzn)) { st = 2; break; }
-                if (rzn <= (double)inner_tol2 * rzi0) break;
-                const float beta = (float)(rzn / rz);
-                rz = rzn;
-                MLS_FOR_INTERIOR(F, { Pv[c] = Z[c] + beta * Pv[c]; })
-                __syncthreads();
-            }
-            if (st == 2) break;
-            // x64 += d; r64 = b - A x64 in FP64 with the FP32 weights promoted
-            MLS_FOR_INTERIOR(F, { X64[c] += (double)X[c]; })
-            __syncthreads();
-            double rr = 0.0;
-            MLS_FOR_INTERIOR(F, {
-                const double d = (double)F.wx[c - 1] + (double)F.wx[c] + (double)F.wy[c - F.s] + (double)F.wy[c];
-                const double nb = (double)F.wx[c - 1] * X64[c - 1] + (double)F.wx[c] * X64[c + 1]
-                                + (double)F.wy[c - F.s] * X64[c - F.s] + (double)F.wy[c] * X64[c + F.s];
-                const double r = h2 - (d * X64[c] - nb);
-                R64[c] = r;
-                rr += r * r;
-            })
-            rr = block_sum<BS>(rr, red);
-            if (!isfinite(rr)) { st = 2; break; }
-            if (rr <= P.tol2 * rr0) st = 0;
+    for (int64_t p = blockIdx.x; p < P.total; p += gridDim.x) {
+        int lo = 0, hi = P.n_items - 1;  // last item with base <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.items[mid].base <= p) lo = mid; else hi = mid - 1;
         }
-        double ph = observe_and_store<BS>(P, q, X64, F.n, red);
-        if (threadIdx.x == 0) {
-            if (P.status) P.status[q] = st;
-            if (P.iters) P.iters[q] = it;
-            if (P.phi) P.phi[q] = 0.5 * ph;
-        }
-        __syncthreads();
+        const SolveItem& it = P.items[lo];
+        const int64_t q = p - it.base;
+        const int l = it.l;
+        const int64_t ne = int64_t(2) << (2 * l);
+        Job J;
+        J.l = l;
+        J.kap = MIXED ? (const void*)((const float*)it.kappa + q * ne) : (const void*)((const double*)it.kappa + q * ne);
+        J.G = it.G + q * P.C.nobs;
+        J.p_out = nullptr;
+        J.status = it.status ? it.status + q : nullptr;
+        J.iters = it.iters ? it.iters + q : nullptr;
+        J.y = it.y;
+        J.phi = it.phi ? it.phi + q : nullptr;
+        J.obs_idx = P.obs_idx[l];
+        J.obs_w = P.obs_w[l];
+        if (MIXED) solve_one_mixed<BS>((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
+        else solve_one_f64<BS>((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
     }
 }
 
@@ -486,6 +567,27 @@ static int default_block(int l)
     if (l == 6) return 256;
     return 512;
 }
+
+static Common make_common(const mls2mc_ctx* ctx, int l)
+{
+    Common C;
+    C.nobs = ctx->nobs;
+    C.inv_sigma = 1.0 / ctx->prob.sigma_n;
+    C.tol2 = ctx->rtol * ctx->rtol;
+    C.max_iters = ctx->max_iters;
+    C.nu = (l >= 0 && ctx->solver_nu[l] > 0) ? ctx->solver_nu[l] : 1;
+    return C;
+}
+
+#define MLS_SWITCH_BS(bs, MIXED, KERNEL, grid, stream, params)                                   \
+    switch (bs) {                                                                                \
+        case 64: KERNEL<64, MIXED><<<grid, 64, 0, stream>>>(params); break;                       \
+        case 128: KERNEL<128, MIXED><<<grid, 128, 0, stream>>>(params); break;                    \
+        case 256: KERNEL<256, MIXED><<<grid, 256, 0, stream>>>(params); break;                    \
+        case 512: KERNEL<512, MIXED><<<grid, 512, 0, stream>>>(params); break;                    \
+        case 1024: KERNEL<1024, MIXED><<<grid, 1024, 0, stream>>>(params); break;                 \
+        default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
+    }
 
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
 {
@@ -507,10 +609,8 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     SolveParams P;
     P.l = l; P.N = a.N; P.N_dev = a.N_dev; P.kappa = a.kappa; P.ws = ctx->ws_solver.ptr; P.slot_elems = slot;
     P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
-    P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w; P.nobs = ctx->nobs;
-    P.inv_sigma = 1.0 / ctx->prob.sigma_n;
-    P.tol2 = ctx->rtol * ctx->rtol;
-    P.max_iters = ctx->max_iters;
+    P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w;
+    P.C = make_common(ctx, l);
     ProfRec rec;
     if (ctx->prof_on) {
         if (!P.iters) {  // the iteration totals need per-particle counts
@@ -520,23 +620,45 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
         MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
     }
     dim3 g((unsigned)grid);
-#define MLS_LAUNCH(BSV)                                                              \
-    if (mixed) solve_mixed_kernel<BSV><<<g, BSV, 0, s>>>(P);                         \
-    else solve_f64_kernel<BSV><<<g, BSV, 0, s>>>(P);
-    switch (bs) {
-        case 64: MLS_LAUNCH(64) break;
-        case 128: MLS_LAUNCH(128) break;
-        case 256: MLS_LAUNCH(256) break;
-        case 512: MLS_LAUNCH(512) break;
-        case 1024: MLS_LAUNCH(1024) break;
-        default: MLS_REQUIRE(false, "solver: unsupported block size");
-    }
-#undef MLS_LAUNCH
+    if (mixed) { MLS_SWITCH_BS(bs, true, solve_kernel, g, s, P) }
+    else { MLS_SWITCH_BS(bs, false, solve_kernel, g, s, P) }
     MLS_CHECK_HIP(hipGetLastError());
     if (ctx->prof_on) {
         MLS_TRY(prof_end(ctx, MLS2MC_PROF_SOLVE, l, rec, s));
         MLS_TRY(launch_reduce_i32(a.N, P.iters, nullptr, ctx->d_prof_iters + 2 * l, s));
     }
+    return MLS2MC_OK;
+}
+
+// Work-list launch.  items_dev: device copy of the items (bases set, finest
+// level first); lmax: finest level in the list; total: sum of N.
+static void list_shape(const mls2mc_ctx* ctx, int lmax, int64_t total, bool mixed, int64_t* grid,
+                       int64_t* slot, int* bs);
+
+int launch_solve_list(mls2mc_ctx* ctx, const SolveItem* items_dev, int n_items, int64_t total, int lmax,
+                      bool mixed, hipStream_t s)
+{
+    if (total == 0 || n_items == 0) return MLS2MC_OK;
+    int64_t grid, slot;
+    int bs;
+    list_shape(ctx, lmax, total, mixed, &grid, &slot, &bs);
+    const size_t esz = mixed ? sizeof(float) : sizeof(double);
+    MLS_TRY(ctx->ws_solver.ensure((size_t)grid * slot * esz));
+    ListParams P;
+    P.items = items_dev;
+    P.n_items = n_items;
+    P.total = total;
+    P.ws = ctx->ws_solver.ptr;
+    P.slot_elems = slot;
+    for (int l = 0; l <= kMaxLevel; ++l) {
+        P.obs_idx[l] = ctx->obs[l].idx;
+        P.obs_w[l] = ctx->obs[l].w;
+    }
+    P.C = make_common(ctx, lmax);
+    dim3 g((unsigned)grid);
+    if (mixed) { MLS_SWITCH_BS(bs, true, solve_list_kernel, g, s, P) }
+    else { MLS_SWITCH_BS(bs, false, solve_list_kernel, g, s, P) }
+    MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
 }
 
@@ -581,3 +703,178 @@ int build_obs_tables(mls2mc_ctx* ctx)
 }
 
 }  // namespace mls
+
+namespace mls {
+
+// Fused forward over many items (instances and levels): items are ordered
+// finest level first and cut into chunks whose coefficient buffer fits the
+// field workspace (8 GiB); each chunk is one grouped GEMM launch and one
+// persistent work-list solver launch.  prepare_list stages the work lists
+// (pinned host memory, asynchronous copy) and sizes every workspace the
+// launches use; enqueue_list only launches, so it can be captured in a HIP
+// graph and replayed while the prepared lists stay valid.
+static void list_shape(const mls2mc_ctx* ctx, int lmax, int64_t total, bool mixed, int64_t* grid,
+                       int64_t* slot, int* bs)
+{
+    int64_t sl = solver_slot_elems(lmax, mixed);
+    sl = (sl + 63) & ~int64_t(63);
+    const size_t esz = mixed ? sizeof(float) : sizeof(double);
+    int64_t g = ctx->list_grid ? ctx->list_grid : (int64_t)ctx->n_cu * 4;
+    const int64_t cap = (int64_t)((16ull << 30) / (sl * esz));
+    if (g > cap) g = cap;
+    if (g > total) g = total;
+    if (g < 1) g = 1;
+    *grid = g;
+    *slot = sl;
+    *bs = ctx->list_block ? ctx->list_block : default_block(lmax);
+}
+
+int prepare_list(mls2mc_ctx* ctx, const std::vector<FwdItem>& items_in, std::vector<ListChunk>& out,
+                 hipStream_t s)
+{
+    out.clear();
+    std::vector<FwdItem> items;
+    for (const auto& it : items_in)
+        if (it.N > 0) items.push_back(it);
+    if (items.empty()) return MLS2MC_OK;
+    std::stable_sort(items.begin(), items.end(), [](const FwdItem& a, const FwdItem& b) { return a.l > b.l; });
+    const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
+    const size_t esz = mixed ? sizeof(float) : sizeof(double);
+    const size_t cap_bytes = 8ull << 30;
+    struct Piece { FwdItem it; int64_t off; };
+    std::vector<std::vector<Piece>> chunks(1);
+    size_t used = 0;
+    for (const auto& it : items) {
+        const size_t per = (size_t)n_elem(it.l) * esz;
+        int64_t done = 0;
+        while (done < it.N) {
+            const int64_t fit = (int64_t)((cap_bytes - used) / per);
+            if (fit <= 0) { chunks.emplace_back(); used = 0; continue; }
+            const int64_t n = std::min(fit, it.N - done);
+            FwdItem p = it;
+            p.N = n;
+            chunks.back().push_back({p, done});
+            used += (size_t)n * per;
+            done += n;
+        }
+    }
+    size_t max_kap = 0, stage_bytes = 0;
+    for (const auto& ch : chunks) {
+        size_t b = 0;
+        for (const auto& pc : ch) b += (size_t)pc.it.N * n_elem(pc.it.l) * esz;
+        max_kap = std::max(max_kap, b);
+        stage_bytes += ((ch.size() * (sizeof(GemmItem) + sizeof(SolveItem))) + 255) & ~size_t(255);
+    }
+    MLS_TRY(ctx->ws_kappa.ensure(max_kap));
+    if (ctx->h_list_bytes < stage_bytes) {
+        if (ctx->h_list) {
+            if (ctx->h_list_ev) (void)hipEventSynchronize(ctx->h_list_ev);
+            (void)hipHostFree(ctx->h_list);
+        }
+        ctx->h_list = nullptr;
+        ctx->h_list_bytes = 0;
+        MLS_CHECK_HIP(hipHostMalloc(&ctx->h_list, stage_bytes * 2));
+        ctx->h_list_bytes = stage_bytes * 2;
+    }
+    MLS_TRY(ctx->ws_list.ensure(stage_bytes));
+    // the previous call's asynchronous copies read the staging buffer
+    if (ctx->h_list_ev) MLS_CHECK_HIP(hipEventSynchronize(ctx->h_list_ev));
+    else MLS_CHECK_HIP(hipEventCreateWithFlags(&ctx->h_list_ev, hipEventDisableTiming));
+    const int K = ctx->prob.K;
+    char* hb = (char*)ctx->h_list;
+    char* db = (char*)ctx->ws_list.ptr;
+    size_t off = 0;
+    size_t ws_need = 0;
+    for (const auto& ch : chunks) {
+        GemmItem* hg = (GemmItem*)(hb + off);
+        SolveItem* hs = (SolveItem*)(hb + off + ch.size() * sizeof(GemmItem));
+        ListChunk lc;
+        lc.n = (int)ch.size();
+        lc.tiles = 0;
+        lc.total = 0;
+        lc.lmax = 0;
+        size_t kap_off = 0;
+        for (size_t i = 0; i < ch.size(); ++i) {
+            const FwdItem& it = ch[i].it;
+            const int64_t q0 = ch[i].off;
+            const int64_t ne = n_elem(it.l);
+            void* kap = (char*)ctx->ws_kappa.ptr + kap_off;
+            kap_off += (size_t)it.N * ne * esz;
+            GemmItem g;
+            g.theta = it.theta + q0 * K;
+            g.B = ctx->d_B[it.l];
+            g.B16 = ctx->d_B16[it.l];
+            g.out = kap;
+            g.N = it.N;
+            g.ne = ne;
+            g.tile_base = lc.tiles;
+            g.tiles_x = (ne + 63) / 64;
+            lc.tiles += g.tiles_x * ((it.N + 63) / 64);
+            hg[i] = g;
+            SolveItem v;
+            v.l = it.l;
+            v.N = it.N;
+            v.base = lc.total;
+            v.kappa = kap;
+            v.G = it.G + q0 * ctx->nobs;
+            v.phi = it.phi ? it.phi + q0 : nullptr;
+            v.y = it.y;
+            v.status = it.status ? it.status + q0 : nullptr;
+            v.iters = it.iters ? it.iters + q0 : nullptr;
+            hs[i] = v;
+            lc.total += it.N;
+            lc.lmax = std::max(lc.lmax, it.l);
+        }
+        const size_t bytes = ch.size() * (sizeof(GemmItem) + sizeof(SolveItem));
+        MLS_CHECK_HIP(hipMemcpyAsync(db + off, hb + off, bytes, hipMemcpyHostToDevice, s));
+        lc.gemm = (const GemmItem*)(db + off);
+        lc.solve = (const SolveItem*)(db + off + ch.size() * sizeof(GemmItem));
+        int64_t grid, slot;
+        int bs;
+        list_shape(ctx, lc.lmax, lc.total, mixed, &grid, &slot, &bs);
+        ws_need = std::max(ws_need, (size_t)grid * slot * esz);
+        out.push_back(lc);
+        off += (bytes + 255) & ~size_t(255);
+    }
+    MLS_CHECK_HIP(hipEventRecord(ctx->h_list_ev, s));
+    MLS_TRY(ctx->ws_solver.ensure(ws_need));
+    return MLS2MC_OK;
+}
+
+int enqueue_list(mls2mc_ctx* ctx, const std::vector<ListChunk>& chunks, hipStream_t s)
+{
+    const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
+    for (const auto& lc : chunks) {
+        MLS_TRY(launch_kl_list(ctx, lc.gemm, lc.n, lc.tiles, s));
+        MLS_TRY(launch_solve_list(ctx, lc.solve, lc.n, lc.total, lc.lmax, mixed, s));
+    }
+    return MLS2MC_OK;
+}
+
+int forward_list(mls2mc_ctx* ctx, const std::vector<FwdItem>& items, hipStream_t s)
+{
+    std::vector<ListChunk> chunks;
+    MLS_TRY(prepare_list(ctx, items, chunks, s));
+    return enqueue_list(ctx, chunks, s);
+}
+
+}  // namespace mls
+
+using namespace mls;
+
+extern "C" int mls2mc_forward_batch(mls2mc_ctx* ctx, int n_items, const mls2mc_forward_item* items, void* stream)
+{
+    MLS_REQUIRE(ctx != nullptr, "null context");
+    MLS_REQUIRE(n_items >= 0 && n_items <= 65536, "forward_batch: need 0 <= n_items <= 65536");
+    MLS_REQUIRE(n_items == 0 || items, "forward_batch: null items");
+    std::vector<FwdItem> v;
+    for (int i = 0; i < n_items; ++i) {
+        const mls2mc_forward_item& it = items[i];
+        MLS_REQUIRE(it.l >= ctx->prob.l_min && it.l <= ctx->prob.l_max, "forward_batch: level outside the context");
+        MLS_REQUIRE(it.N >= 0, "forward_batch: N < 0");
+        MLS_REQUIRE(it.N == 0 || (it.theta && it.G_out), "forward_batch: null pointer");
+        MLS_REQUIRE(!it.phi_out || it.y, "forward_batch: phi_out needs y");
+        v.push_back({it.l, it.N, it.theta, it.G_out, it.y, it.phi_out, it.status_out, it.iters_out});
+    }
+    return forward_list(ctx, v, (hipStream_t)stream);
+}
