@@ -68,6 +68,140 @@ def cpu_baseline(l, K, m, corr, budget_s=15.0):
                        f"OpenMP over particles, {dt:.1f}s")
 
 
+def rel_err_paper(mean, truth, lam):
+    """relative error of a posterior mean with Lambda^{1/2} weights (Sec. 5.1)"""
+    import numpy as np
+    w = np.sqrt(lam)
+    return float(np.abs(w * (mean - truth)).sum() / np.abs(w * truth).sum())
+
+
+def tune_levels(ctx, levels, J):
+    out = {}
+    for lv in levels:
+        ms, (g, b, nu) = ctx.autotune(lv, min(J, 512 if lv >= 7 else J))
+        out[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, ms=round(ms, 4))
+    return out
+
+
+def leg_fast(args):
+    """h=1/8..1/256, K=100, 49 obs, sigma_n=0.002, J=4096: time-to-posterior of
+    the plain FP64 form and of the mixed-precision + surrogate form"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    K, m, sn, J, lmin, lmax = 100, 7, 0.002, 4096, 3, 8
+    rng = np.random.default_rng(77)
+    th_true = rng.standard_normal(K)
+    ctx = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn)
+    lam = ctx.kl_eigenvalues()
+    y = ctx.forward(lmax, torch.tensor(th_true[None, :], device=dev))[0]
+    y = (y + sn * torch.tensor(rng.standard_normal(m * m), device=dev)).contiguous()
+    out = {}
+    tuned = tune_levels(ctx, range(lmin, lmax + 1), J)
+    log(f"fast leg: tuned fp64 {tuned}")
+    r = ctx.run(y, J, seed=21)
+    mp = r["theta"].cpu().numpy().mean(0)
+    out["plain_fp64"] = dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
+                             solves={str(i): v for i, v in enumerate(r["solves"]) if v},
+                             rel_err_vs_truth=rel_err_paper(mp, th_true, lam), log_Z=r["log_Z"])
+    log(f"plain {out['plain_fp64']}")
+    ctxm = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn, precision=P.MIXED)
+    tune_levels(ctxm, range(lmin, lmax + 1), J)
+    rm = ctxm.run(y, J, seed=21, surrogate=True, sur_collect_max_level=6, sur_da_min_level=7,
+                  sur_pairs=20480, sur_epochs=30, sur_hidden=256)
+    mf = rm["theta"].cpu().numpy().mean(0)
+    out["mixed_surrogate"] = dict(seconds=round(rm["seconds"], 3), stages=rm["n_stages"],
+                                  solves={str(i): v for i, v in enumerate(rm["solves"]) if v},
+                                  rel_err_vs_truth=rel_err_paper(mf, th_true, lam), log_Z=rm["log_Z"],
+                                  surrogate_train_s=round(rm["sur_train_seconds"], 3),
+                                  stage1_pass_frac=rm["stage1_passed"] / max(1, rm["da_proposed"]))
+    out["rel_err_between_forms"] = rel_err_paper(mf, mp, lam)
+    log(f"fast {out['mixed_surrogate']}")
+    print(json.dumps({
+        "metric": "MLS²MC time-to-posterior, plain vs surrogate+FP32",
+        "value": out["mixed_surrogate"]["seconds"], "unit": "s (mixed precision + surrogate)",
+        "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "bf16/f32/f64",
+        "data": "synthetic", "speedup_vs_plain_fp64": round(out["plain_fp64"]["seconds"] / out["mixed_surrogate"]["seconds"], 3),
+        "config": {"workload": "mls2mc h=1/8..1/256 K=100 Nobs=49 sigma_n=0.002 J=4096"}, **out}))
+
+
+def leg_batched(args):
+    """32 instances, seeds 0..31, J ~ U{256..4096}, finest h in {1/64, 1/128,
+    1/256}, K=100, 49 obs, sigma_n=0.002: fused rounds with HIP graphs"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    K, m, sn, lmin, lmax = 100, 7, 0.002, 3, 8
+    ctx = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn)
+    specs = []
+    for seed in range(32):
+        g = np.random.default_rng(1000 + seed)
+        J = int(g.integers(256, 4097))
+        lm = int(g.choice([6, 7, 8]))
+        th_true = torch.tensor(g.standard_normal((1, K)), device=dev)
+        y = ctx.forward(lm, th_true)[0] + sn * torch.tensor(g.standard_normal(m * m), device=dev)
+        specs.append(dict(J=J, l_max=lm, y=y.contiguous(), seed=seed))
+    t0 = time.perf_counter()
+    out = ctx.run_batch([dict(d) for d in specs], use_graphs=True)
+    dt = time.perf_counter() - t0
+    solves = sum(sum(o["solves"]) for o in out)
+    res = dict(seconds=round(dt, 3), total_particles=sum(d["J"] for d in specs), total_solves=solves,
+               graphs=out[0]["graphs_launched"],
+               finest_levels={str(k): sum(1 for d in specs if d["l_max"] == k) for k in (6, 7, 8)})
+    log(f"batched {res}")
+    if args.batched_sequential:
+        t0 = time.perf_counter()
+        for d in specs:
+            ctx.run(d["y"], d["J"], seed=d["seed"])
+        torch.cuda.synchronize()
+        res["sequential_seconds"] = round(time.perf_counter() - t0, 3)
+    print(json.dumps({
+        "metric": "MLS²MC time-to-posterior (32 uneven instances, fused)", "value": res["seconds"], "unit": "s",
+        "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "32 instances J~U{256..4096}, finest h in {1/64,1/128,1/256}, K=100, Nobs=49"},
+        **res}))
+
+
+def leg_largest(args):
+    """h=1/512, K=200 (correlation length 0.1), 100 obs, J=8192: forward solves/s
+    of plain FP64 and mixed precision batches"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    K, m, sn, J, l = 200, 10, 0.001, 8192, 9
+    rng = np.random.default_rng(5)
+    th = torch.tensor(rng.standard_normal((J, K)), device=dev)
+    res = {}
+    for name, prec in (("fp64", P.FP64), ("mixed", P.MIXED)):
+        ctx = P.Context(l, l, K, 1.0, 0.1, m, sn, precision=prec)
+        ctx.forward(l, th[:1024].contiguous())
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        G, st, it = ctx.forward(l, th, with_stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.profile(False)
+        ps = ctx.profile_read(P.PROF_SOLVE, l)
+        b_iter = B_ITER_FP64 if prec == P.FP64 else B_ITER_MIXED
+        alg = solve_bytes(l, 100, ps["items"], ps["iters"], b_iter)
+        res[name] = dict(solves_per_s=round(J / dt, 1), seconds=round(dt, 3),
+                         mean_iters=float(it.float().mean().item()), converged=int((st == 0).sum().item()),
+                         solver_algorithmic_GBs=round(alg / (ps["ms"] * 1e-3) / 1e9, 1))
+        log(f"largest {name} {res[name]}")
+        ctx.close()
+    print(json.dumps({
+        "metric": "forward solves/s per level", "value": res["fp64"]["solves_per_s"], "unit": "forward solves/s (h=1/512)",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "h=1/512 K=200 corr=0.1 Nobs=100 J=8192 forward batch"}, **res}))
+
+
 def copy_calibration(gib=2.0):
     """plain device copy of known size, for scaling rocprofv3 byte counters"""
     import torch
@@ -91,6 +225,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
+    ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest"],
+                    help="cfg1: the default stage benchmark; others: the extra workloads")
+    ap.add_argument("--batched-sequential", action="store_true",
+                    help="batched workload: also time the instances one after another")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -103,6 +241,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload != "cfg1":
+        {"fast": leg_fast, "batched": leg_batched, "largest": leg_largest}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     W = WL
@@ -119,14 +260,14 @@ def main():
     if args.tuned:
         shapes = {int(k): v for k, v in json.load(open(args.tuned))["fp64"].items()}
         for lv, sh in shapes.items():
-            ctx.set_launch(lv, sh["grid"], sh["block"])
+            ctx.set_launch(lv, sh["grid"], sh["block"], sh.get("nu", 0))
         extras["solver_launch"] = {f"h=1/{1 << lv}": sh for lv, sh in shapes.items()}
     elif not args.no_autotune:
         tuned = {}
         for lv in range(W["l_min"], W["l_max"] + 1):
-            ms, (g, b) = ctx.autotune(lv, J)
-            shapes[lv] = dict(grid=g, block=b)
-            tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, ms=round(ms, 4))
+            ms, (g, b, nu) = ctx.autotune(lv, J)
+            shapes[lv] = dict(grid=g, block=b, nu=nu)
+            tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, ms=round(ms, 4))
         extras["autotuned_solver_launch"] = tuned
         log(f"autotuned {tuned}")
         if args.save_tuned:

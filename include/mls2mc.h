@@ -76,8 +76,10 @@ typedef struct {
     double sigma_n;    /* noise standard deviation, Gamma = sigma_n^2 I (> 0)*/
     int precision;     /* MLS2MC_FP64 or MLS2MC_MIXED                        */
     double rtol;       /* relative solver tolerance on the preconditioned
-                          residual norm; 0 selects 1e-11 (FP64) / 1e-10
-                          (MIXED, after refinement)                         */
+                          residual norm sqrt((r, V r) / (r0, V r0)), V the
+                          multigrid cycle; 0 selects 1e-11 (FP64) / 1e-10
+                          (MIXED, measured on the FP64 residual of the
+                          iterative refinement)                             */
     int max_iters;     /* PCG iteration cap; 0 selects 200                   */
 } mls2mc_problem;
 
@@ -91,6 +93,10 @@ int mls2mc_destroy(mls2mc_ctx* ctx);
 const char* mls2mc_last_error(void);
 /* library version string, e.g. "mls2mc 1.0 gfx950"                         */
 const char* mls2mc_version(void);
+
+/* KL eigenvalues lambda_k (descending, host array of K doubles), e.g. for
+ * the paper's relative error with Lambda^{1/2} weights (Sec. 5.1).        */
+int mls2mc_kl_eigenvalues(const mls2mc_ctx* ctx, double* lambda_out);
 
 /* Observation count and level sizes (host queries).                        */
 int mls2mc_n_obs(const mls2mc_ctx* ctx);
@@ -348,16 +354,18 @@ int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint3
                        uint32_t sub, int64_t n, int normal, double* out, void* stream);
 
 /* ---- launch shape of the persistent solver ---- */
-/* Autotune the solver launch for level l on N prior draws: every candidate
+/* Autotune the solver for level l on N prior draws: every candidate
  * (persistent workgroups = w x CUs capped at N, w in {1,2,3,4,6,8,12,16};
- * block in {64,...,1024}) is timed with HIP events (best of 3) and the
- * fastest is kept in the context for level l.  best_ms (host, may be NULL)
- * receives its time.  Synchronous; allocates its own temporary buffers.   */
+ * block in {64,...,1024}; V-cycle Gauss-Seidel sweeps per side nu in {1,2})
+ * solves the batch to the context's tolerance, is timed with HIP events
+ * (best of 3), and the fastest is kept in the context for level l.  best_ms
+ * (host, may be NULL) receives its time.  Synchronous; allocates its own
+ * temporary buffers.                                                       */
 int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_ms, void* stream);
-/* Read / set the launch shape of level l (grid 0 or block 0 = built-in
- * default), e.g. to restore tuned shapes cached by the caller.            */
-int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block);
-int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block);
+/* Read / set the solver schedule of level l (grid 0, block 0 or nu 0 =
+ * built-in default), e.g. to restore tuned schedules cached by the caller. */
+int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu);
+int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu);
 
 /* ---- kernel-time instrumentation ---- */
 /* When enabled, the library records a pair of HIP events on the launch

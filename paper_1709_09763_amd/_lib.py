@@ -105,8 +105,9 @@ def lib():
         L.mls2mc_philox_fill.argtypes = [_vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                          C.c_int64, C.c_int, _vp, _vp]
         L.mls2mc_autotune.argtypes = [_vp, C.c_int, C.c_int64, C.POINTER(C.c_double), _vp]
-        L.mls2mc_get_launch.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
-        L.mls2mc_set_launch.argtypes = [_vp, C.c_int, C.c_int, C.c_int]
+        L.mls2mc_get_launch.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int)]
+        L.mls2mc_set_launch.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mls2mc_surrogate_init.argtypes = [_vp, C.c_int, C.c_int64, C.c_uint64, _vp]
         L.mls2mc_surrogate_n_params.argtypes = [_vp]
         L.mls2mc_surrogate_n_pairs.argtypes = [_vp]
@@ -119,6 +120,7 @@ def lib():
         L.mls2mc_surrogate_predict.argtypes = [_vp, C.c_int64, _vp, _vp, _vp]
         L.mls2mc_surrogate_loss_grad.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
         L.mls2mc_pcn_step_da.argtypes = [_vp, C.POINTER(Stage), C.c_int64] + [_vp] * 14
+        L.mls2mc_kl_eigenvalues.argtypes = [_vp, C.POINTER(C.c_double)]
         L.mls2mc_forward_batch.argtypes = [_vp, C.c_int, C.POINTER(ForwardItem), _vp]
         L.mls2mc_run_batch.argtypes = [_vp, C.POINTER(RunConfig), C.c_int, C.POINTER(Instance),
                                        C.POINTER(RunResult), C.c_int, _vp]
@@ -208,6 +210,13 @@ def mls2mc_forward_field(h, l, kappa, G_out, p_out=None, status_out=None, iters_
         _ptr(p_out, torch.float64, (N, mls2mc_n_unknowns(l)), "p_out", True),
         _ptr(status_out, torch.int8, (N,), "status_out", True),
         _ptr(iters_out, torch.int32, (N,), "iters_out", True), _stream()), "mls2mc_forward_field")
+
+
+def mls2mc_kl_eigenvalues(h, K):
+    import numpy as np
+    out = np.zeros(K)
+    _check(lib().mls2mc_kl_eigenvalues(h, out.ctypes.data_as(_dp)), "mls2mc_kl_eigenvalues")
+    return out
 
 
 def mls2mc_forward_batch(h, items):
@@ -423,13 +432,13 @@ def mls2mc_autotune(h, l, N):
 
 
 def mls2mc_get_launch(h, l):
-    g, b = C.c_int(), C.c_int()
-    _check(lib().mls2mc_get_launch(h, l, C.byref(g), C.byref(b)), "mls2mc_get_launch")
-    return g.value, b.value
+    g, b, nu = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().mls2mc_get_launch(h, l, C.byref(g), C.byref(b), C.byref(nu)), "mls2mc_get_launch")
+    return g.value, b.value, nu.value
 
 
-def mls2mc_set_launch(h, l, grid, block):
-    _check(lib().mls2mc_set_launch(h, l, grid, block), "mls2mc_set_launch")
+def mls2mc_set_launch(h, l, grid, block, nu=0):
+    _check(lib().mls2mc_set_launch(h, l, grid, block, nu), "mls2mc_set_launch")
 
 
 def mls2mc_profile(h, enable):
@@ -464,6 +473,9 @@ class Context:
         except Exception:
             pass
 
+    def kl_eigenvalues(self):
+        return mls2mc_kl_eigenvalues(self.h, self.K)
+
     def autotune(self, l, N):
         ms = mls2mc_autotune(self.h, l, N)
         return ms, mls2mc_get_launch(self.h, l)
@@ -471,8 +483,8 @@ class Context:
     def get_launch(self, l):
         return mls2mc_get_launch(self.h, l)
 
-    def set_launch(self, l, grid, block):
-        mls2mc_set_launch(self.h, l, grid, block)
+    def set_launch(self, l, grid, block, nu=0):
+        mls2mc_set_launch(self.h, l, grid, block, nu)
 
     def profile(self, enable=True):
         mls2mc_profile(self.h, enable)

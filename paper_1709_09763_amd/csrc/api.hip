@@ -180,6 +180,13 @@ int64_t mls2mc_n_elem(int l) { return (l >= 0 && l <= 15) ? n_elem(l) : -1; }
 int64_t mls2mc_n_unknowns(int l) { return (l >= 0 && l <= 15) ? n_unk(l) : -1; }
 int mls2mc_n_obs(const mls2mc_ctx* ctx) { return ctx ? ctx->nobs : -1; }
 
+int mls2mc_kl_eigenvalues(const mls2mc_ctx* ctx, double* lambda_out)
+{
+    MLS_REQUIRE(ctx && lambda_out, "kl_eigenvalues: null argument");
+    for (int k = 0; k < ctx->prob.K; ++k) lambda_out[k] = ctx->sqrt_lam[k] * ctx->sqrt_lam[k];
+    return MLS2MC_OK;
+}
+
 int mls2mc_destroy(mls2mc_ctx* ctx)
 {
     if (!ctx) return MLS2MC_OK;
@@ -242,7 +249,7 @@ int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out)
         if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
             ctx->n_cu = prop.multiProcessorCount;
     }
-    ctx->rtol = p->rtol > 0 ? p->rtol : (p->precision == MLS2MC_MIXED ? 1e-12 : 1e-11);
+    ctx->rtol = p->rtol > 0 ? p->rtol : (p->precision == MLS2MC_MIXED ? 1e-10 : 1e-11);
     ctx->max_iters = p->max_iters > 0 ? p->max_iters : 200;
     int rc = build_kl_tables(ctx);
     if (rc == MLS2MC_OK) rc = build_obs_tables(ctx);

@@ -388,8 +388,9 @@ __device__ void solve_one_f64(double* slot, const Job& J, const Common& C, doubl
 // FP32 multigrid-PCG inside FP64 iterative refinement: the system matrix is
 // the one defined by the FP32 edge weights (promoted exactly to FP64 for the
 // residual), r64 = b - A x64 in FP64, the correction A d = r64 is solved
-// with FP32 MG-PCG to a loose tolerance, x64 += d.  The coarsest solve of
-// the hierarchy is done in FP64.
+// with FP32 MG-PCG to a loose tolerance, x64 += d.  Convergence is measured
+// like the FP64 solver's, on the preconditioned norm (r64, V r64) relative
+// to its first value.  The coarsest solve of the hierarchy is done in FP64.
 template <int BS>
 __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, double* red)
 {
@@ -402,7 +403,7 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
     double* R64 = X64 + S;
     const double h2 = 1.0 / (double)(F.n * F.n);
     const double inner_tol2 = 1e-10;  // relative reduction 1e-5 per refinement sweep
-    const int max_outer = 12;
+    const int max_outer = 16;
     const float* kap = (const float*)J.kap;
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
@@ -411,11 +412,9 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
     setup_hierarchy<BS>(slot, l, F, kap);
     MLS_FOR_INTERIOR(F, { X64[c] = 0.0; R64[c] = h2; })
     __syncthreads();
-    double rr0 = 0.0;
-    MLS_FOR_INTERIOR(F, { rr0 += h2 * h2; })
-    rr0 = block_sum<BS>(rr0, red);
     int it = 0;
     int8_t st = 1;
+    double rz_first = 0.0;
     for (int outer = 0; outer < max_outer && st == 1; ++outer) {
         MLS_FOR_INTERIOR(F, { X[c] = 0.f; R[c] = (float)R64[c]; })
         __syncthreads();
@@ -423,8 +422,16 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
         double rz = 0.0;
         MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; Pv[c] = Z[c]; })
         rz = block_sum<BS>(rz, red);
+        if (!isfinite(rz)) { st = 2; break; }
+        if (outer == 0) {
+            rz_first = rz;
+            if (!(rz > 0.0)) { st = 2; break; }
+        } else if (rz <= C.tol2 * rz_first) {
+            st = 0;
+            break;
+        }
         const double rzi0 = rz;
-        for (int k = 0; k < C.max_iters && rz > 0.0; ++k) {
+        for (int k = 0; k < C.max_iters; ++k) {
             double pq = 0.0;
             MLS_FOR_INTERIOR(F, {
                 const float v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
@@ -451,20 +458,16 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
             __syncthreads();
         }
         if (st == 2) break;
+        // x64 += d; r64 = b - A x64 in FP64 with the FP32 weights promoted
         MLS_FOR_INTERIOR(F, { X64[c] += (double)X[c]; })
         __syncthreads();
-        double rr = 0.0;
         MLS_FOR_INTERIOR(F, {
             const double d = (double)F.wx[c - 1] + (double)F.wx[c] + (double)F.wy[c - F.s] + (double)F.wy[c];
             const double nb = (double)F.wx[c - 1] * X64[c - 1] + (double)F.wx[c] * X64[c + 1]
                             + (double)F.wy[c - F.s] * X64[c - F.s] + (double)F.wy[c] * X64[c + F.s];
-            const double r = h2 - (d * X64[c] - nb);
-            R64[c] = r;
-            rr += r * r;
+            R64[c] = h2 - (d * X64[c] - nb);
         })
-        rr = block_sum<BS>(rr, red);
-        if (!isfinite(rr)) { st = 2; break; }
-        if (rr <= C.tol2 * rr0) st = 0;
+        __syncthreads();
     }
     observe_and_store<BS>(J, C, X64, F.n, st, it, red);
 }

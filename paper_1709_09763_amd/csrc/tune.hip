@@ -34,7 +34,7 @@ static int time_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s, int re
 
 using namespace mls;
 
-extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block)
+extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu)
 {
     MLS_REQUIRE(ctx != nullptr, "null context");
     MLS_REQUIRE(l >= 1 && l <= kMaxLevel, "set_launch: bad level");
@@ -42,17 +42,20 @@ extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block)
     MLS_REQUIRE(block == 0 || block == 64 || block == 128 || block == 256 || block == 512 ||
                     block == 1024,
                 "set_launch: block must be 0 (auto), 64, 128, 256, 512 or 1024");
+    MLS_REQUIRE(nu >= 0 && nu <= 4, "set_launch: nu must be 0 (default 1) .. 4");
     ctx->solver_grid[l] = grid;
     ctx->solver_block[l] = block;
+    ctx->solver_nu[l] = nu;
     return MLS2MC_OK;
 }
 
-extern "C" int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block)
+extern "C" int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu)
 {
-    MLS_REQUIRE(ctx && grid && block, "get_launch: null argument");
+    MLS_REQUIRE(ctx && grid && block && nu, "get_launch: null argument");
     MLS_REQUIRE(l >= 1 && l <= kMaxLevel, "get_launch: bad level");
     *grid = ctx->solver_grid[l];
     *block = ctx->solver_block[l];
+    *nu = ctx->solver_nu[l];
     return MLS2MC_OK;
 }
 
@@ -87,27 +90,31 @@ extern "C" int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_m
     const int wpc[] = {1, 2, 3, 4, 6, 8, 12, 16};
     const int blocks[] = {64, 128, 256, 512, 1024};
     float best = 1e30f;
-    int bg = 0, bb = 0;
-    for (int b : blocks) {
-        if (rc != MLS2MC_OK) break;
-        if (l <= 3 && b > 256) continue;  // at most (n-1) n = 56 points per sweep
-        int64_t last_grid = -1;
-        for (int w : wpc) {
-            int64_t g = std::min<int64_t>((int64_t)w * cu, N);
-            if (b * w > 2048 * 4) continue;  // beyond 32 waves per CU
-            if (g == last_grid) continue;
-            last_grid = g;
-            ctx->solver_grid[l] = (int)g;
-            ctx->solver_block[l] = b;
-            float ms = 0.f;
-            rc = time_solve(ctx, a, s, 3, &ms);
+    int bg = 0, bb = 0, bn = 1;
+    for (int nu = 1; nu <= 2; ++nu) {
+        ctx->solver_nu[l] = nu;
+        for (int b : blocks) {
             if (rc != MLS2MC_OK) break;
-            if (ms < best) { best = ms; bg = (int)g; bb = b; }
+            if (l <= 3 && b > 256) continue;  // at most (n-1) n = 56 points per sweep
+            int64_t last_grid = -1;
+            for (int w : wpc) {
+                int64_t g = std::min<int64_t>((int64_t)w * cu, N);
+                if (b * w > 2048 * 4) continue;  // beyond 32 waves per CU
+                if (g == last_grid) continue;
+                last_grid = g;
+                ctx->solver_grid[l] = (int)g;
+                ctx->solver_block[l] = b;
+                float ms = 0.f;
+                rc = time_solve(ctx, a, s, 3, &ms);
+                if (rc != MLS2MC_OK) break;
+                if (ms < best) { best = ms; bg = (int)g; bb = b; bn = nu; }
+            }
         }
     }
     ctx->prof_on = prof;
     ctx->solver_grid[l] = bg;
     ctx->solver_block[l] = bb;
+    ctx->solver_nu[l] = bn;
     th.release();
     kap.release();
     G.release();
