@@ -27,10 +27,36 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # algorithmic bytes per fine-level unknown per PCG iteration of the FP64
-# multigrid-PCG (PCG vector work + V(1,1) cycle, each array read once and
-# written once per sweep, coarse levels included)
-B_ITER_FP64 = 293.0
-B_ITER_MIXED = 147.0
+# multigrid-PCG: PCG vector work + V(1,1) cycle, each array read once and
+# written once per sweep, coarse levels included (293 B); each further
+# smoothing step per side adds two sweeps reading x, b and the two weight
+# arrays and writing x, over all levels (2 x 5 x 8 x 4/3 = 106.7 B).
+# Half of both with FP32 inner arrays.
+def b_iter(nu, fp32=False):
+    b = 293.0 + 106.7 * (max(1, nu) - 1)
+    return b / 2 if fp32 else b
+
+
+B_ITER_FP64 = b_iter(1)
+B_ITER_MIXED = b_iter(1, True)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "solve_h64_K50_J1000_pmc.md")
+
+
+def measured_traffic():
+    """HBM bytes per solver launch from the committed rocprofv3 counter
+    summary, or None once the solver source differs from the one measured"""
+    import hashlib
+    try:
+        txt = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = dict(ln.split(":", 1) for ln in txt.splitlines() if ln.startswith(("traffic_bytes", "solver_source")))
+    h = hashlib.sha256()
+    for f in ("solver.hip", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1709_09763_amd", "csrc", f), "rb").read())
+    if vals.get("solver_source_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 WL = dict(name="mls2mc h=1/8..1/64 K=50 Nobs=25 J=1000", l_min=3, l_max=6, K=50, m=5,
           sigma_n=0.005, J=1000, corr=0.3, n_mcmc=5, s_pcn=0.5, tau_star=1.0)
@@ -78,8 +104,8 @@ def rel_err_paper(mean, truth, lam):
 def tune_levels(ctx, levels, J):
     out = {}
     for lv in levels:
-        ms, (g, b, nu) = ctx.autotune(lv, min(J, 512 if lv >= 7 else J))
-        out[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, ms=round(ms, 4))
+        ms, (g, b, nu, lds) = ctx.autotune(lv, min(J, 512 if lv >= 7 else J))
+        out[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, lds=lds, ms=round(ms, 4))
     return out
 
 
@@ -189,8 +215,7 @@ def leg_largest(args):
         dt = time.perf_counter() - t0
         ctx.profile(False)
         ps = ctx.profile_read(P.PROF_SOLVE, l)
-        b_iter = B_ITER_FP64 if prec == P.FP64 else B_ITER_MIXED
-        alg = solve_bytes(l, 100, ps["items"], ps["iters"], b_iter)
+        alg = solve_bytes(l, 100, ps["items"], ps["iters"], b_iter(ctx.get_launch(l)[2], prec == P.MIXED))
         res[name] = dict(solves_per_s=round(J / dt, 1), seconds=round(dt, 3),
                          mean_iters=float(it.float().mean().item()), converged=int((st == 0).sum().item()),
                          solver_algorithmic_GBs=round(alg / (ps["ms"] * 1e-3) / 1e9, 1))
@@ -260,14 +285,14 @@ def main():
     if args.tuned:
         shapes = {int(k): v for k, v in json.load(open(args.tuned))["fp64"].items()}
         for lv, sh in shapes.items():
-            ctx.set_launch(lv, sh["grid"], sh["block"], sh.get("nu", 0))
+            ctx.set_launch(lv, sh["grid"], sh["block"], sh.get("nu", 0), sh.get("lds", 0))
         extras["solver_launch"] = {f"h=1/{1 << lv}": sh for lv, sh in shapes.items()}
     elif not args.no_autotune:
         tuned = {}
         for lv in range(W["l_min"], W["l_max"] + 1):
-            ms, (g, b, nu) = ctx.autotune(lv, J)
-            shapes[lv] = dict(grid=g, block=b, nu=nu)
-            tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, ms=round(ms, 4))
+            ms, (g, b, nu, lds) = ctx.autotune(lv, J)
+            shapes[lv] = dict(grid=g, block=b, nu=nu, lds=lds)
+            tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, lds=lds, ms=round(ms, 4))
         extras["autotuned_solver_launch"] = tuned
         log(f"autotuned {tuned}")
         if args.save_tuned:
@@ -350,7 +375,8 @@ def main():
     pg = ctx.profile_read(P.PROF_GEMM, l)
     solves = args.steps * W["n_mcmc"] * J
     value = solves / dt
-    alg = solve_bytes(l, nobs, ps["items"], ps["iters"], B_ITER_FP64)
+    nu_l = ctx.get_launch(l)[2]
+    alg = solve_bytes(l, nobs, ps["items"], ps["iters"], b_iter(nu_l))
     avg_ms = ps["ms"] / max(1, ps["launches"])
     achieved = alg / ps["launches"] / (avg_ms * 1e-3) / 1e9 if ps["launches"] else 0.0
     gemm_flops = 2.0 * pg["items"] * K * (2 << (2 * l))
@@ -360,6 +386,7 @@ def main():
     extras["kl_gemm"] = dict(launches=pg["launches"], avg_ms=round(pg["ms"] / max(1, pg["launches"]), 4),
                              tflops=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12, 3),
                              frac_of_fp64_peak=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12 / FP64_PEAK_TFLOPS, 4))
+    traffic = measured_traffic()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(l, K, m, W["corr"])
@@ -376,8 +403,10 @@ def main():
                    "sigma_n": W["sigma_n"], "step": "one SMC stage at h=1/64: next_step, resample, "
                    "gather, 5 pCN steps (KL GEMM + MG-PCG solve + observation + potential)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "solve_f64_kernel (h=1/64)"},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+                     "algorithmic_bytes_per_launch": round(alg / max(1, ps["launches"]), 0),
+                     "kernel": "solve_kernel (h=1/64, FP64)", "vcycle_nu": nu_l},
         "cpu_baseline": cpu,
         **extras,
     }

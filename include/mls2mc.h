@@ -355,17 +355,19 @@ int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint3
 
 /* ---- launch shape of the persistent solver ---- */
 /* Autotune the solver for level l on N prior draws: every candidate
- * (persistent workgroups = w x CUs capped at N, w in {1,2,3,4,6,8,12,16};
- * block in {64,...,1024}; V-cycle Gauss-Seidel sweeps per side nu in {1,2})
- * solves the batch to the context's tolerance, is timed with HIP events
- * (best of 3), and the fastest is kept in the context for level l.  best_ms
- * (host, may be NULL) receives its time.  Synchronous; allocates its own
- * temporary buffers.                                                       */
+ * (persistent workgroups = w x CUs capped at N; block size; V-cycle
+ * Gauss-Seidel sweeps per side nu in {1,2}; LDS residency of the multigrid
+ * hierarchy: none or a 64 KiB budget) solves the batch to the context's
+ * tolerance, is timed with HIP events (best of 3), and the fastest is kept
+ * in the context for level l.  best_ms (host, may be NULL) receives its
+ * time.  Synchronous; allocates its own temporary buffers.                 */
 int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_ms, void* stream);
-/* Read / set the solver schedule of level l (grid 0, block 0 or nu 0 =
- * built-in default), e.g. to restore tuned schedules cached by the caller. */
-int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu);
-int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu);
+/* Read / set the solver schedule of level l (grid 0, block 0, nu 0 or
+ * lds_bytes 0 = built-in default; lds_bytes -1 = no LDS residency, else
+ * the per-workgroup LDS budget, at most 65536), e.g. to restore tuned
+ * schedules cached by the caller.                                          */
+int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu, int* lds_bytes);
+int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu, int lds_bytes);
 
 /* ---- kernel-time instrumentation ---- */
 /* When enabled, the library records a pair of HIP events on the launch

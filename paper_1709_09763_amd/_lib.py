@@ -106,8 +106,8 @@ def lib():
                                          C.c_int64, C.c_int, _vp, _vp]
         L.mls2mc_autotune.argtypes = [_vp, C.c_int, C.c_int64, C.POINTER(C.c_double), _vp]
         L.mls2mc_get_launch.argtypes = [_vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                        C.POINTER(C.c_int)]
-        L.mls2mc_set_launch.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int]
+                                        C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.mls2mc_set_launch.argtypes = [_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]
         L.mls2mc_surrogate_init.argtypes = [_vp, C.c_int, C.c_int64, C.c_uint64, _vp]
         L.mls2mc_surrogate_n_params.argtypes = [_vp]
         L.mls2mc_surrogate_n_pairs.argtypes = [_vp]
@@ -432,13 +432,14 @@ def mls2mc_autotune(h, l, N):
 
 
 def mls2mc_get_launch(h, l):
-    g, b, nu = C.c_int(), C.c_int(), C.c_int()
-    _check(lib().mls2mc_get_launch(h, l, C.byref(g), C.byref(b), C.byref(nu)), "mls2mc_get_launch")
-    return g.value, b.value, nu.value
+    g, b, nu, lds = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    _check(lib().mls2mc_get_launch(h, l, C.byref(g), C.byref(b), C.byref(nu), C.byref(lds)),
+           "mls2mc_get_launch")
+    return g.value, b.value, nu.value, lds.value
 
 
-def mls2mc_set_launch(h, l, grid, block, nu=0):
-    _check(lib().mls2mc_set_launch(h, l, grid, block, nu), "mls2mc_set_launch")
+def mls2mc_set_launch(h, l, grid, block, nu=0, lds_bytes=0):
+    _check(lib().mls2mc_set_launch(h, l, grid, block, nu, lds_bytes), "mls2mc_set_launch")
 
 
 def mls2mc_profile(h, enable):
@@ -483,8 +484,8 @@ class Context:
     def get_launch(self, l):
         return mls2mc_get_launch(self.h, l)
 
-    def set_launch(self, l, grid, block, nu=0):
-        mls2mc_set_launch(self.h, l, grid, block, nu)
+    def set_launch(self, l, grid, block, nu=0, lds_bytes=0):
+        mls2mc_set_launch(self.h, l, grid, block, nu, lds_bytes)
 
     def profile(self, enable=True):
         mls2mc_profile(self.h, enable)

@@ -110,6 +110,7 @@ struct mls2mc_ctx {
     int solver_grid[mls::kMaxLevel + 1] = {};  // persistent grid per level (0 = auto)
     int solver_block[mls::kMaxLevel + 1] = {};
     int solver_nu[mls::kMaxLevel + 1] = {};     // Gauss-Seidel sweeps per V-cycle side (0 = 1)
+    int solver_lds[mls::kMaxLevel + 1] = {};    // LDS budget in bytes (0 = 64 KiB, -1 = none)
     int list_grid = 0, list_block = 0;          // work-list launch shape (0 = auto)
     double rtol = 1e-11;
     int max_iters = 200;

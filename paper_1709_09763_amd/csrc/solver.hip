@@ -65,16 +65,79 @@ struct Lv {
     int n, lg, s;
 };
 
+// Where a particle's arrays live.  Coarse levels L <= lds_top keep their
+// five work arrays (WX WY XC BC RESC) in LDS, finest of them first; when
+// fine_lds is set the fine level's eight arrays follow them in LDS too.  The
+// per-triangle coefficients of coarse levels (setup only) and every array
+// of the remaining levels stay in the global slot.
 template <typename T>
-__device__ inline Lv<T> coarse_level(T* slot, int l, int L)
+struct Map {
+    T* slot;
+    T* lds;
+    int l;
+    int lds_top;
+    bool fine_lds;
+};
+
+__host__ __device__ inline int64_t lds_coarse_elems(int top)
+{
+    int64_t o = 0;
+    for (int k = 1; k <= top; ++k) o += 5 * pad_sz(k);
+    return o;
+}
+
+// the largest residency that fits `budget` elements
+__host__ __device__ inline void lds_policy(int l, int64_t budget, int* top, bool* fine)
+{
+    *fine = false;
+    *top = 0;
+    if (budget <= 0) return;
+    if (lds_coarse_elems(l - 1) + 8 * pad_sz(l) <= budget) {
+        *fine = true;
+        *top = l - 1;
+        return;
+    }
+    for (int t = l - 1; t >= 1; --t)
+        if (lds_coarse_elems(t) <= budget) { *top = t; return; }
+}
+
+__host__ __device__ inline int64_t lds_elems_used(int l, int64_t budget)
+{
+    int top;
+    bool fine;
+    lds_policy(l, budget, &top, &fine);
+    return lds_coarse_elems(top) + (fine ? 8 * pad_sz(l) : 0);
+}
+
+template <typename T>
+__device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems)
+{
+    Map<T> M;
+    M.slot = slot;
+    M.lds = lds;
+    M.l = l;
+    lds_policy(l, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_lds);
+    return M;
+}
+
+template <typename T>
+__device__ inline Lv<T> coarse_level(const Map<T>& M, int L)
 {
     Lv<T> v;
-    T* base = slot + coarse_off(l, L);
+    T* g = M.slot + coarse_off(M.l, L);
     const int64_t S = pad_sz(L);
+    T* base = (L <= M.lds_top) ? M.lds + (lds_coarse_elems(M.lds_top) - lds_coarse_elems(L)) : g;
     v.wx = base; v.wy = base + S; v.x = base + 2 * S; v.b = base + 3 * S; v.res = base + 4 * S;
-    v.kap = base + 5 * S;
+    v.kap = g + 5 * S;
     v.n = 1 << L; v.lg = L; v.s = v.n + 1;
     return v;
+}
+
+// base of the fine level's X R Z P Q WX WY RES
+template <typename T>
+__device__ inline T* fine_base(const Map<T>& M)
+{
+    return M.fine_lds ? M.lds + lds_coarse_elems(M.lds_top) : M.slot;
 }
 
 // ----------------------------------------------------------- stencils --
@@ -177,34 +240,48 @@ __device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __rest
     }
 }
 
+// One V-cycle z = V r.  pre_red_done: the caller has already done the first
+// red sweep of the fine level (fused with its vector updates).  With
+// want_dot the last red sweep of the fine level also returns (r, z) over all
+// interior nodes (black values are final there, so the pass can read them).
 template <int BS, typename T>
-__device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs, T* __restrict__ sol,
-                       int nu)
+__device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ rhs, T* __restrict__ sol,
+                         int nu, bool pre_red_done, bool want_dot, double* red)
 {
+    const int l = M.l;
     if (l == 1) {  // the fine level is the coarsest: one unknown, exact
         if (threadIdx.x == 0) {
             const int c = F.s + 1;
             sol[c] = T((double)rhs[c] / (double)diag_at(F.wx, F.wy, c, F.s));
         }
         __syncthreads();
-        return;
+        double d = 0.0;
+        if (want_dot) {
+            MLS_FOR_INTERIOR(F, { d += (double)rhs[c] * (double)sol[c]; })
+            d = block_sum<BS>(d, red);
+        }
+        return d;
     }
     // down
     for (int Lk = l; Lk >= 2; --Lk) {
-        const Lv<T> L = (Lk == l) ? F : coarse_level(slot, l, Lk);
+        const Lv<T> L = (Lk == l) ? F : coarse_level(M, Lk);
         const T* b = (Lk == l) ? rhs : L.b;
         T* x = (Lk == l) ? sol : L.x;
         for (int sw = 0; sw < nu; ++sw) {  // (red, black)^nu
-            smooth_colour<BS>(L, b, x, 0, sw == 0);
-            __syncthreads();
+            if (!(sw == 0 && Lk == l && pre_red_done)) {
+                smooth_colour<BS>(L, b, x, 0, sw == 0);
+                __syncthreads();
+            }
             smooth_colour<BS>(L, b, x, 1, false);
             __syncthreads();
         }
+        // residual, then its restriction (P^T of P1 interpolation); forming
+        // the residual inside the restriction loop instead was measured slower
         MLS_FOR_INTERIOR(L, {
             L.res[c] = b[c] - (diag_at(L.wx, L.wy, c, L.s) * x[c] - nb_sum(L.wx, L.wy, x, c, L.s));
         })
         __syncthreads();
-        const Lv<T> C = coarse_level(slot, l, Lk - 1);
+        const Lv<T> C = coarse_level(M, Lk - 1);
         const int s = L.s;
         const T* r = L.res;
         MLS_FOR_INTERIOR(C, {
@@ -214,7 +291,7 @@ __device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs
         __syncthreads();
     }
     {  // coarsest level, one unknown at (1,1)
-        const Lv<T> C = coarse_level(slot, l, 1);
+        const Lv<T> C = coarse_level(M, 1);
         if (threadIdx.x == 0) {
             const int c = C.s + 1;  // solved in FP64 for either working type
             C.x[c] = T((double)C.b[c] / (double)diag_at(C.wx, C.wy, c, C.s));
@@ -222,9 +299,10 @@ __device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs
         __syncthreads();
     }
     // up
+    double dot = 0.0;
     for (int Lk = 2; Lk <= l; ++Lk) {
-        const Lv<T> L = (Lk == l) ? F : coarse_level(slot, l, Lk);
-        const Lv<T> C = coarse_level(slot, l, Lk - 1);
+        const Lv<T> L = (Lk == l) ? F : coarse_level(M, Lk);
+        const Lv<T> C = coarse_level(M, Lk - 1);
         const T* b = (Lk == l) ? rhs : L.b;
         T* x = (Lk == l) ? sol : L.x;
         const int sc = C.s;
@@ -242,26 +320,45 @@ __device__ void vcycle(T* slot, int l, const Lv<T>& F, const T* __restrict__ rhs
         for (int sw = 0; sw < nu; ++sw) {  // (black, red)^nu: the adjoint order
             smooth_colour<BS>(L, b, x, 1, false);
             __syncthreads();
-            smooth_colour<BS>(L, b, x, 0, false);
-            __syncthreads();
+            if (Lk == l && sw == nu - 1 && want_dot) {
+                // last red sweep fused with (r, z): red nodes are updated from
+                // their black neighbours, black nodes are final
+                double d = 0.0;
+                MLS_FOR_INTERIOR(L, {
+                    T z;
+                    if (((i + j) & 1) == 0) {
+                        z = (b[c] + nb_sum(L.wx, L.wy, x, c, L.s)) / diag_at(L.wx, L.wy, c, L.s);
+                        x[c] = z;
+                    } else {
+                        z = x[c];
+                    }
+                    d += (double)b[c] * (double)z;
+                })
+                dot = block_sum<BS>(d, red);  // includes the barrier
+            } else {
+                smooth_colour<BS>(L, b, x, 0, false);
+                __syncthreads();
+            }
         }
     }
+    return dot;
 }
 
 // ------------------------------------------------------- setup & obs --
 template <int BS, typename T, typename KT>
-__device__ void setup_hierarchy(T* slot, int l, const Lv<T>& F, const KT* __restrict__ kap)
+__device__ void setup_hierarchy(const Map<T>& M, const Lv<T>& F, const KT* __restrict__ kap)
 {
+    const int l = M.l;
     edge_weights<BS>(kap, F.wx, F.wy, F.n, F.lg);
     if (l >= 2) {
-        Lv<T> C = coarse_level(slot, l, l - 1);
+        Lv<T> C = coarse_level(M, l - 1);
         coarsen_kappa<BS>(kap, C.kap, l - 1);
         __syncthreads();
         for (int L = l - 1; L >= 1; --L) {
-            Lv<T> V = coarse_level(slot, l, L);
+            Lv<T> V = coarse_level(M, L);
             edge_weights<BS>(V.kap, V.wx, V.wy, V.n, V.lg);
             zero_boundary<BS>(V.x, V.n);
-            if (L >= 2) coarsen_kappa<BS>(V.kap, coarse_level(slot, l, L - 1).kap, L - 1);
+            if (L >= 2) coarsen_kappa<BS>(V.kap, coarse_level(M, L - 1).kap, L - 1);
             __syncthreads();
         }
     }
@@ -321,7 +418,7 @@ __device__ void observe_and_store(const Job& J, const Common& C, const T* X, int
 }
 
 template <typename T>
-__device__ inline Lv<T> fine_level(T* slot, int l)
+__device__ inline Lv<T> fine_level(T* slot, int l)  // slot: the fine base
 {
     const int64_t S = pad_sz(l);
     Lv<T> F;
@@ -333,21 +430,22 @@ __device__ inline Lv<T> fine_level(T* slot, int l)
 
 // ---------------------------------------------------------- FP64 solve --
 template <int BS>
-__device__ void solve_one_f64(double* slot, const Job& J, const Common& C, double* red)
+__device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
     const int64_t S = pad_sz(l);
-    double *X = slot, *R = slot + S, *Z = slot + 2 * S, *Pv = slot + 3 * S, *Q = slot + 4 * S;
-    const Lv<double> F = fine_level(slot, l);
+    double* fb = fine_base(M);
+    double *X = fb, *R = fb + S, *Z = fb + 2 * S, *Pv = fb + 3 * S, *Q = fb + 4 * S;
+    const Lv<double> F = fine_level(fb, l);
     const double h2 = 1.0 / (double)(F.n * F.n);
     const double* kap = (const double*)J.kap;
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
     zero_boundary<BS>(Pv, F.n);
-    setup_hierarchy<BS>(slot, l, F, kap);
+    setup_hierarchy<BS>(M, F, kap);
     MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
     __syncthreads();
-    vcycle<BS>(slot, l, F, R, Z, C.nu);
+    vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
     double rz = 0.0;
     MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; Pv[c] = Z[c]; })
     rz = block_sum<BS>(rz, red);
@@ -364,15 +462,15 @@ __device__ void solve_one_f64(double* slot, const Job& J, const Common& C, doubl
         })
         pq = block_sum<BS>(pq, red);
         const double alpha = rz / pq;
+        // x and r updates fused with the first red sweep of the V-cycle
         MLS_FOR_INTERIOR(F, {
             X[c] += alpha * Pv[c];
-            R[c] -= alpha * Q[c];
+            const double rn = R[c] - alpha * Q[c];
+            R[c] = rn;
+            if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, F.s);
         })
         __syncthreads();
-        vcycle<BS>(slot, l, F, R, Z, C.nu);
-        double rzn = 0.0;
-        MLS_FOR_INTERIOR(F, { rzn += R[c] * Z[c]; })
-        rzn = block_sum<BS>(rzn, red);
+        const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
         ++it;
         if (!isfinite(rzn)) { st = 2; break; }
         if (rzn <= C.tol2 * rz0) { st = 0; break; }
@@ -392,14 +490,15 @@ __device__ void solve_one_f64(double* slot, const Job& J, const Common& C, doubl
 // like the FP64 solver's, on the preconditioned norm (r64, V r64) relative
 // to its first value.  The coarsest solve of the hierarchy is done in FP64.
 template <int BS>
-__device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, double* red)
+__device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
     const int64_t S = pad_sz(l);
-    float *X = slot, *R = slot + S, *Z = slot + 2 * S, *Pv = slot + 3 * S, *Q = slot + 4 * S;
-    const Lv<float> F = fine_level(slot, l);
+    float* fb = fine_base(M);
+    float *X = fb, *R = fb + S, *Z = fb + 2 * S, *Pv = fb + 3 * S, *Q = fb + 4 * S;
+    const Lv<float> F = fine_level(fb, l);
     const int64_t hier = slot_elems_hd(l, false);
-    double* X64 = (double*)(slot + ((hier + 1) & ~int64_t(1)));
+    double* X64 = (double*)(M.slot + ((hier + 1) & ~int64_t(1)));
     double* R64 = X64 + S;
     const double h2 = 1.0 / (double)(F.n * F.n);
     const double inner_tol2 = 1e-10;  // relative reduction 1e-5 per refinement sweep
@@ -409,7 +508,7 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
     zero_boundary<BS>(Z, F.n);
     zero_boundary<BS>(Pv, F.n);
     zero_boundary<BS>(X64, F.n);
-    setup_hierarchy<BS>(slot, l, F, kap);
+    setup_hierarchy<BS>(M, F, kap);
     MLS_FOR_INTERIOR(F, { X64[c] = 0.0; R64[c] = h2; })
     __syncthreads();
     int it = 0;
@@ -418,7 +517,7 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
     for (int outer = 0; outer < max_outer && st == 1; ++outer) {
         MLS_FOR_INTERIOR(F, { X[c] = 0.f; R[c] = (float)R64[c]; })
         __syncthreads();
-        vcycle<BS>(slot, l, F, R, Z, C.nu);
+        vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
         double rz = 0.0;
         MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; Pv[c] = Z[c]; })
         rz = block_sum<BS>(rz, red);
@@ -442,13 +541,12 @@ __device__ void solve_one_mixed(float* slot, const Job& J, const Common& C, doub
             const float alpha = (float)(rz / pq);
             MLS_FOR_INTERIOR(F, {
                 X[c] += alpha * Pv[c];
-                R[c] -= alpha * Q[c];
+                const float rn = R[c] - alpha * Q[c];
+                R[c] = rn;
+                if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, F.s);
             })
             __syncthreads();
-            vcycle<BS>(slot, l, F, R, Z, C.nu);
-            double rzn = 0.0;
-            MLS_FOR_INTERIOR(F, { rzn += (double)R[c] * (double)Z[c]; })
-            rzn = block_sum<BS>(rzn, red);
+            const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
             ++it;
             if (!isfinite(rzn)) { st = 2; break; }
             if (rzn <= inner_tol2 * rzi0) break;
@@ -488,8 +586,11 @@ struct SolveParams {
     double* phi;
     const int32_t* obs_idx;
     const double* obs_w;
+    int64_t lds_elems;  // LDS budget in elements of the working type
     Common C;
 };
+
+extern __shared__ __align__(16) char mls_lds[];
 
 template <int BS, bool MIXED>
 __global__ __launch_bounds__(BS) void solve_kernel(SolveParams P)
@@ -511,8 +612,12 @@ __global__ __launch_bounds__(BS) void solve_kernel(SolveParams P)
         J.phi = P.phi ? P.phi + q : nullptr;
         J.obs_idx = P.obs_idx;
         J.obs_w = P.obs_w;
-        if (MIXED) solve_one_mixed<BS>((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
-        else solve_one_f64<BS>((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
+        if (MIXED)
+            solve_one_mixed<BS>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
+                                         P.lds_elems), J, P.C, red);
+        else
+            solve_one_f64<BS>(make_map((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (double*)mls_lds, l,
+                                       P.lds_elems), J, P.C, red);
     }
 }
 
@@ -529,6 +634,7 @@ struct ListParams {
     int64_t slot_elems;
     const int32_t* obs_idx[kMaxLevel + 1];
     const double* obs_w[kMaxLevel + 1];
+    int64_t lds_elems;
     Common C;
 };
 
@@ -557,8 +663,12 @@ __global__ __launch_bounds__(BS) void solve_list_kernel(ListParams P)
         J.phi = it.phi ? it.phi + q : nullptr;
         J.obs_idx = P.obs_idx[l];
         J.obs_w = P.obs_w[l];
-        if (MIXED) solve_one_mixed<BS>((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
-        else solve_one_f64<BS>((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, J, P.C, red);
+        if (MIXED)
+            solve_one_mixed<BS>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
+                                         P.lds_elems), J, P.C, red);
+        else
+            solve_one_f64<BS>(make_map((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (double*)mls_lds, l,
+                                       P.lds_elems), J, P.C, red);
     }
 }
 
@@ -582,15 +692,27 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
     return C;
 }
 
-#define MLS_SWITCH_BS(bs, MIXED, KERNEL, grid, stream, params)                                   \
+#define MLS_SWITCH_BS(bs, MIXED, KERNEL, grid, lds, stream, params)                              \
     switch (bs) {                                                                                \
-        case 64: KERNEL<64, MIXED><<<grid, 64, 0, stream>>>(params); break;                       \
-        case 128: KERNEL<128, MIXED><<<grid, 128, 0, stream>>>(params); break;                    \
-        case 256: KERNEL<256, MIXED><<<grid, 256, 0, stream>>>(params); break;                    \
-        case 512: KERNEL<512, MIXED><<<grid, 512, 0, stream>>>(params); break;                    \
-        case 1024: KERNEL<1024, MIXED><<<grid, 1024, 0, stream>>>(params); break;                 \
+        case 64: KERNEL<64, MIXED><<<grid, 64, lds, stream>>>(params); break;                     \
+        case 128: KERNEL<128, MIXED><<<grid, 128, lds, stream>>>(params); break;                  \
+        case 256: KERNEL<256, MIXED><<<grid, 256, lds, stream>>>(params); break;                  \
+        case 512: KERNEL<512, MIXED><<<grid, 512, lds, stream>>>(params); break;                  \
+        case 1024: KERNEL<1024, MIXED><<<grid, 1024, lds, stream>>>(params); break;               \
         default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
     }
+
+// LDS bytes for level l under the level's budget (0 = no LDS residency).
+// *alloc_elems is what the launch allocates; kernels decide each particle's
+// residency with it as the budget, so no level uses more than is allocated
+// (the policy is monotone in the budget).
+static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* alloc_elems)
+{
+    const size_t esz = mixed ? sizeof(float) : sizeof(double);
+    const int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
+    *alloc_elems = lds_elems_used(l, (int64_t)(budget / esz));
+    return (size_t)*alloc_elems * esz;
+}
 
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
 {
@@ -614,6 +736,7 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
     P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w;
     P.C = make_common(ctx, l);
+    const size_t lds = lds_bytes_for(ctx, l, mixed, &P.lds_elems);
     ProfRec rec;
     if (ctx->prof_on) {
         if (!P.iters) {  // the iteration totals need per-particle counts
@@ -623,8 +746,8 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
         MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
     }
     dim3 g((unsigned)grid);
-    if (mixed) { MLS_SWITCH_BS(bs, true, solve_kernel, g, s, P) }
-    else { MLS_SWITCH_BS(bs, false, solve_kernel, g, s, P) }
+    if (mixed) { MLS_SWITCH_BS(bs, true, solve_kernel, g, lds, s, P) }
+    else { MLS_SWITCH_BS(bs, false, solve_kernel, g, lds, s, P) }
     MLS_CHECK_HIP(hipGetLastError());
     if (ctx->prof_on) {
         MLS_TRY(prof_end(ctx, MLS2MC_PROF_SOLVE, l, rec, s));
@@ -658,9 +781,10 @@ int launch_solve_list(mls2mc_ctx* ctx, const SolveItem* items_dev, int n_items, 
         P.obs_w[l] = ctx->obs[l].w;
     }
     P.C = make_common(ctx, lmax);
+    const size_t lds = lds_bytes_for(ctx, lmax, mixed, &P.lds_elems);
     dim3 g((unsigned)grid);
-    if (mixed) { MLS_SWITCH_BS(bs, true, solve_list_kernel, g, s, P) }
-    else { MLS_SWITCH_BS(bs, false, solve_list_kernel, g, s, P) }
+    if (mixed) { MLS_SWITCH_BS(bs, true, solve_list_kernel, g, lds, s, P) }
+    else { MLS_SWITCH_BS(bs, false, solve_list_kernel, g, lds, s, P) }
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
 }

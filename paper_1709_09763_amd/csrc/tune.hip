@@ -3,6 +3,7 @@
 // keeps the fastest.  The choice trades slot-workspace residency in the
 // caches (fewer slots) against latency hiding (more workgroups per CU).
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -34,7 +35,7 @@ static int time_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s, int re
 
 using namespace mls;
 
-extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu)
+extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu, int lds_bytes)
 {
     MLS_REQUIRE(ctx != nullptr, "null context");
     MLS_REQUIRE(l >= 1 && l <= kMaxLevel, "set_launch: bad level");
@@ -43,19 +44,23 @@ extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, in
                     block == 1024,
                 "set_launch: block must be 0 (auto), 64, 128, 256, 512 or 1024");
     MLS_REQUIRE(nu >= 0 && nu <= 4, "set_launch: nu must be 0 (default 1) .. 4");
+    MLS_REQUIRE(lds_bytes == -1 || (lds_bytes >= 0 && lds_bytes <= 65536),
+                "set_launch: lds_bytes must be -1 (none), 0 (default 64 KiB) or up to 65536");
     ctx->solver_grid[l] = grid;
     ctx->solver_block[l] = block;
     ctx->solver_nu[l] = nu;
+    ctx->solver_lds[l] = lds_bytes;
     return MLS2MC_OK;
 }
 
-extern "C" int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu)
+extern "C" int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu, int* lds_bytes)
 {
-    MLS_REQUIRE(ctx && grid && block && nu, "get_launch: null argument");
+    MLS_REQUIRE(ctx && grid && block && nu && lds_bytes, "get_launch: null argument");
     MLS_REQUIRE(l >= 1 && l <= kMaxLevel, "get_launch: bad level");
     *grid = ctx->solver_grid[l];
     *block = ctx->solver_block[l];
     *nu = ctx->solver_nu[l];
+    *lds_bytes = ctx->solver_lds[l];
     return MLS2MC_OK;
 }
 
@@ -87,27 +92,30 @@ extern "C" int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_m
     a.kappa_f32 = mixed;
     a.G = G.as<double>();
     const int cu = ctx->n_cu;
-    const int wpc[] = {1, 2, 3, 4, 6, 8, 12, 16};
-    const int blocks[] = {64, 128, 256, 512, 1024};
+    std::vector<int> wpc, blocks;
+    if (l <= 4) { wpc = {1, 2, 4, 8, 16}; blocks = {64, 128, 256}; }
+    else if (l <= 6) { wpc = {1, 2, 4, 8}; blocks = {128, 256, 512}; }
+    else { wpc = {1, 2, 4}; blocks = {256, 512, 1024}; }
     float best = 1e30f;
-    int bg = 0, bb = 0, bn = 1;
-    for (int nu = 1; nu <= 2; ++nu) {
-        ctx->solver_nu[l] = nu;
-        for (int b : blocks) {
-            if (rc != MLS2MC_OK) break;
-            if (l <= 3 && b > 256) continue;  // at most (n-1) n = 56 points per sweep
-            int64_t last_grid = -1;
-            for (int w : wpc) {
-                int64_t g = std::min<int64_t>((int64_t)w * cu, N);
-                if (b * w > 2048 * 4) continue;  // beyond 32 waves per CU
-                if (g == last_grid) continue;
-                last_grid = g;
-                ctx->solver_grid[l] = (int)g;
-                ctx->solver_block[l] = b;
-                float ms = 0.f;
-                rc = time_solve(ctx, a, s, 3, &ms);
+    int bg = 0, bb = 0, bn = 1, bl = 0;
+    for (int lds : {0, -1}) {
+        ctx->solver_lds[l] = lds;
+        for (int nu = 1; nu <= 2; ++nu) {
+            ctx->solver_nu[l] = nu;
+            for (int b : blocks) {
                 if (rc != MLS2MC_OK) break;
-                if (ms < best) { best = ms; bg = (int)g; bb = b; bn = nu; }
+                int64_t last_grid = -1;
+                for (int w : wpc) {
+                    int64_t g = std::min<int64_t>((int64_t)w * cu, N);
+                    if (g == last_grid) continue;
+                    last_grid = g;
+                    ctx->solver_grid[l] = (int)g;
+                    ctx->solver_block[l] = b;
+                    float ms = 0.f;
+                    rc = time_solve(ctx, a, s, 3, &ms);
+                    if (rc != MLS2MC_OK) break;
+                    if (ms < best) { best = ms; bg = (int)g; bb = b; bn = nu; bl = lds; }
+                }
             }
         }
     }
@@ -115,6 +123,7 @@ extern "C" int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_m
     ctx->solver_grid[l] = bg;
     ctx->solver_block[l] = bb;
     ctx->solver_nu[l] = bn;
+    ctx->solver_lds[l] = bl;
     th.release();
     kap.release();
     G.release();

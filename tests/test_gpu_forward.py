@@ -166,3 +166,27 @@ def test_mixed_bf16_field_error_bound():
     err = np.abs(np.log(kap32) - a)
     assert np.all(err <= bound)
     print(f"  max |a_bf16 - a| = {err.max():.3e}")
+
+
+def test_solver_schedules_give_identical_results():
+    """LDS residency and the persistent grid change where the arrays live and
+    which workgroup solves which particle, not the arithmetic: bitwise equal
+    results for a fixed block size.  Other block sizes split the reductions
+    differently (rounding only)."""
+    device()
+    l, N = 6, 50
+    ctx = P.Context(l, l, 20, 1.0, 0.3, 5, 0.01)
+    th = to_dev(inputs.theta_batch(61, N, 20))
+    for block in (256, 512):
+        outs = []
+        for grid, lds in [(0, 0), (7, -1), (50, 0), (13, -1)]:
+            case(f"schedule grid={grid} block={block} lds={lds}")
+            ctx.set_launch(l, grid, block, 1, lds)
+            G, st, it = ctx.forward(l, th, with_stats=True)
+            outs.append((host(G), host(it)))
+        for G, it in outs[1:]:
+            np.testing.assert_array_equal(G, outs[0][0])
+            np.testing.assert_array_equal(it, outs[0][1])
+        if block == 256:
+            G256 = outs[0][0]
+    assert rel_err(outs[0][0], G256) < 1e-12
