@@ -127,22 +127,24 @@ def leg_fast(args):
     out = {}
     tuned = tune_levels(ctx, range(lmin, lmax + 1), J)
     log(f"fast leg: tuned fp64 {tuned}")
-    r = ctx.run(y, J, seed=21)
+    r = ctx.run(y, J, seed=21, s_adapt=args.s_adapt)
     mp = r["theta"].cpu().numpy().mean(0)
     out["plain_fp64"] = dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
                              solves={str(i): v for i, v in enumerate(r["solves"]) if v},
-                             rel_err_vs_truth=rel_err_paper(mp, th_true, lam), log_Z=r["log_Z"])
+                             rel_err_vs_truth=rel_err_paper(mp, th_true, lam), log_Z=r["log_Z"],
+                             stage_acc_rate=[round(float(a), 4) for a in r["stage_acc_rate"]])
     log(f"plain {out['plain_fp64']}")
     ctxm = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn, precision=P.MIXED)
     tune_levels(ctxm, range(lmin, lmax + 1), J)
     rm = ctxm.run(y, J, seed=21, surrogate=True, sur_collect_max_level=6, sur_da_min_level=7,
-                  sur_pairs=20480, sur_epochs=30, sur_hidden=256)
+                  sur_pairs=20480, sur_epochs=30, sur_hidden=256, s_adapt=args.s_adapt)
     mf = rm["theta"].cpu().numpy().mean(0)
     out["mixed_surrogate"] = dict(seconds=round(rm["seconds"], 3), stages=rm["n_stages"],
                                   solves={str(i): v for i, v in enumerate(rm["solves"]) if v},
                                   rel_err_vs_truth=rel_err_paper(mf, th_true, lam), log_Z=rm["log_Z"],
                                   surrogate_train_s=round(rm["sur_train_seconds"], 3),
-                                  stage1_pass_frac=rm["stage1_passed"] / max(1, rm["da_proposed"]))
+                                  stage1_pass_frac=rm["stage1_passed"] / max(1, rm["da_proposed"]),
+                                  stage_acc_rate=[round(float(a), 4) for a in rm["stage_acc_rate"]])
     out["rel_err_between_forms"] = rel_err_paper(mf, mp, lam)
     log(f"fast {out['mixed_surrogate']}")
     print(json.dumps({
@@ -150,7 +152,8 @@ def leg_fast(args):
         "value": out["mixed_surrogate"]["seconds"], "unit": "s (mixed precision + surrogate)",
         "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "bf16/f32/f64",
         "data": "synthetic", "speedup_vs_plain_fp64": round(out["plain_fp64"]["seconds"] / out["mixed_surrogate"]["seconds"], 3),
-        "config": {"workload": "mls2mc h=1/8..1/256 K=100 Nobs=49 sigma_n=0.002 J=4096"}, **out}))
+        "config": {"workload": "mls2mc h=1/8..1/256 K=100 Nobs=49 sigma_n=0.002 J=4096",
+                   "pcn_step": "adapted" if args.s_adapt else "fixed 0.5"}, **out}))
 
 
 def leg_batched(args):
@@ -190,6 +193,51 @@ def leg_batched(args):
         "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "32 instances J~U{256..4096}, finest h in {1/64,1/128,1/256}, K=100, Nobs=49"},
         **res}))
+
+
+def leg_largest_run(args):
+    """h=1/16..1/512, K=200 (correlation length 0.1), 100 obs, sigma_n=0.001,
+    J=8192: full MLS^2MC, plain FP64 vs mixed precision + surrogate"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    K, m, sn, J, lmin, lmax = 200, 10, 0.001, 8192, 4, 9
+    rng = np.random.default_rng(99)
+    th_true = rng.standard_normal(K)
+    out = {}
+    for name, prec, sur in (("plain_fp64", P.FP64, False), ("mixed_surrogate", P.MIXED, True)):
+        ctx = P.Context(lmin, lmax, K, 1.0, 0.1, m, sn, precision=prec)
+        lam = ctx.kl_eigenvalues()
+        if name == "plain_fp64":
+            y = ctx.forward(lmax, torch.tensor(th_true[None, :], device=dev))[0]
+            y = (y + sn * torch.tensor(rng.standard_normal(m * m), device=dev)).contiguous()
+        tune_levels(ctx, range(lmin, lmax + 1), J)
+        kw = dict(surrogate=True, sur_collect_max_level=6, sur_da_min_level=7, sur_pairs=20480,
+                  sur_epochs=30, sur_hidden=256) if sur else {}
+        r = ctx.run(y, J, seed=31, s_adapt=args.s_adapt, **kw)
+        mean = r["theta"].cpu().numpy().mean(0)
+        out[name] = dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
+                         solves={str(i): v for i, v in enumerate(r["solves"]) if v},
+                         rel_err_vs_truth=rel_err_paper(mean, th_true, lam), log_Z=r["log_Z"],
+                         accept_rate=r["accepted"] / max(1, r["proposed"]),
+                         stage_levels=r["stage_level"].tolist(),
+                         stage_acc_rate=[round(float(a), 4) for a in r["stage_acc_rate"]])
+        if sur:
+            out[name].update(surrogate_train_s=round(r["sur_train_seconds"], 3),
+                             stage1_pass_frac=r["stage1_passed"] / max(1, r["da_proposed"]))
+        out[name]["mean"] = mean
+        log(f"{name} {dict((k, v) for k, v in out[name].items() if k != 'mean')}")
+        ctx.close()
+    out["rel_err_between_forms"] = rel_err_paper(out["mixed_surrogate"].pop("mean"), out["plain_fp64"].pop("mean"), lam)
+    print(json.dumps({
+        "metric": "MLS²MC time-to-posterior, plain vs surrogate+FP32", "value": out["mixed_surrogate"]["seconds"],
+        "unit": "s (mixed precision + surrogate)", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+        "dtype": "bf16/f32/f64", "data": "synthetic",
+        "speedup_vs_plain_fp64": round(out["plain_fp64"]["seconds"] / out["mixed_surrogate"]["seconds"], 3),
+        "config": {"workload": "mls2mc h=1/16..1/512 K=200 corr=0.1 Nobs=100 sigma_n=0.001 J=8192",
+                   "pcn_step": "adapted" if args.s_adapt else "fixed 0.5"}, **out}))
 
 
 def leg_largest(args):
@@ -250,8 +298,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
-    ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest"],
+    ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest", "largest-run"],
                     help="cfg1: the default stage benchmark; others: the extra workloads")
+    ap.add_argument("--s-adapt", action="store_true",
+                    help="fast / largest-run: adapt the pCN step between stages (an extension)")
     ap.add_argument("--batched-sequential", action="store_true",
                     help="batched workload: also time the instances one after another")
     args = ap.parse_args()
@@ -268,7 +318,8 @@ def main():
         copy_calibration()
         return
     if args.workload != "cfg1":
-        {"fast": leg_fast, "batched": leg_batched, "largest": leg_largest}[args.workload](args)
+        {"fast": leg_fast, "batched": leg_batched, "largest": leg_largest,
+         "largest-run": leg_largest_run}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     W = WL

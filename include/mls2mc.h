@@ -286,6 +286,10 @@ typedef struct {
     int sur_hidden;     /* 0 = 256                                          */
     int sur_batch;      /* 0 = 256                                          */
     double sur_lr;      /* 0 = 1e-3                                         */
+    /* optional pCN step adaptation, an extension that the paper does not
+     * use (0 = fixed s_pcn): after each stage s <- clamp(s exp(2 (a -
+     * 0.25)), 0.005, 1) with a the stage's acceptance rate.               */
+    int s_adapt;
 } mls2mc_run_config;
 
 typedef struct {

@@ -31,7 +31,7 @@ class Config(C.Structure):
         ("tau_ess", C.c_double), ("tau_lu", C.c_double), ("eps", C.c_double),
         ("n_mcmc", C.c_int), ("s_pcn", C.c_double), ("seed", C.c_uint64),
         ("max_stages", C.c_int), ("nthreads", C.c_int),
-        ("lin_A", _dp), ("lin_E", _dp), ("da_S", _dp),
+        ("lin_A", _dp), ("lin_E", _dp), ("da_S", _dp), ("s_adapt", C.c_int),
     ]
 
 
@@ -40,7 +40,8 @@ class Result(C.Structure):
         ("n_stages", C.c_int), ("log_Z", C.c_double), ("final_level", C.c_int),
         ("final_beta", C.c_double), ("solves", C.c_int64 * 16), ("accepted", C.c_int64),
         ("proposed", C.c_int64), ("stage1_passed", C.c_int64), ("stage_type", _ip), ("stage_level", _ip),
-        ("stage_beta", _dp), ("stage_zeta", _dp), ("stage_ess", _dp), ("max_stage_log", C.c_int),
+        ("stage_beta", _dp), ("stage_zeta", _dp), ("stage_ess", _dp), ("stage_step", _dp),
+        ("stage_acc_rate", _dp), ("max_stage_log", C.c_int),
     ]
 
 
@@ -274,7 +275,7 @@ def da_accept(psi_old, psi_new, psis_old, psis_new, u1, u2):
 def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=0.3, m=3,
                 nobs=None, sigma_n=0.01, J=200, J_tilde=None, tau_star=1.0, tau_lu=None,
                 eps=1e-6, n_mcmc=5, s_pcn=0.5, seed=0, max_stages=2000, nthreads=0,
-                lin_A=None, lin_E=None, da_S=None):
+                lin_A=None, lin_E=None, da_S=None, s_adapt=False):
     """Run the MLS^2MC sampler; returns a dict of results and final particles."""
     y = _f64(y)
     cfg = Config()
@@ -289,6 +290,7 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
     cfg.tau_lu = tau_lu if tau_lu is not None else tau_star
     cfg.eps, cfg.n_mcmc, cfg.s_pcn, cfg.seed = eps, n_mcmc, s_pcn, seed
     cfg.max_stages, cfg.nthreads = max_stages, nthreads
+    cfg.s_adapt = int(s_adapt)
     keep = []
     if lin_A is not None:
         A = _f64(lin_A)
@@ -307,6 +309,10 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
     sb = np.zeros(ms)
     sz = np.zeros(ms)
     se = np.zeros(ms)
+    ss = np.zeros(ms)
+    sa = np.zeros(ms)
+    res.stage_step = _d(ss)
+    res.stage_acc_rate = _d(sa)
     res.stage_type = st.ctypes.data_as(_ip)
     res.stage_level = sl.ctypes.data_as(_ip)
     res.stage_beta = _d(sb)
@@ -319,7 +325,8 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
     return dict(theta=theta, log_Z=res.log_Z, n_stages=res.n_stages, final_level=res.final_level,
                 final_beta=res.final_beta, solves=list(res.solves), accepted=res.accepted,
                 proposed=res.proposed, stage1_passed=res.stage1_passed, stage_type=st[:n].copy(), stage_level=sl[:n].copy(),
-                stage_beta=sb[:n].copy(), stage_zeta=sz[:n].copy(), stage_ess=se[:n].copy())
+                stage_beta=sb[:n].copy(), stage_zeta=sz[:n].copy(), stage_ess=se[:n].copy(),
+                stage_step=ss[:n].copy(), stage_acc_rate=sa[:n].copy())
 
 
 # ------------------------------------------------------------------- MLP --

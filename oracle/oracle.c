@@ -702,8 +702,8 @@ static double orc_sur_psi(const orc_config* cfg, int nobs, const double* th, con
 }
 
 static int orc_mutate(orc_model* md, const double* y, int stage, int l, int bridge, double beta,
-                      double zeta, orc_state* s, int64_t* solves, int64_t* acc, int64_t* prop,
-                      int64_t* pass1)
+                      double zeta, double s_pcn, orc_state* s, int64_t* solves, int64_t* acc,
+                      int64_t* prop, int64_t* pass1)
 {
     const orc_config* cfg = md->cfg;
     int64_t J = cfg->J;
@@ -720,7 +720,7 @@ static int orc_mutate(orc_model* md, const double* y, int stage, int l, int brid
     for (int mstep = 0; rc == 0 && mstep < cfg->n_mcmc; ++mstep) {
         for (int64_t i = 0; i < J * K; ++i)
             xi[i] = orc_normal(cfg->seed, ST_PCN_XI, (uint32_t)stage, (uint32_t)mstep, (uint32_t)i);
-        orc_pcn_propose(J, K, cfg->s_pcn, s->theta, xi, th);
+        orc_pcn_propose(J, K, s_pcn, s->theta, xi, th);
         if (need_lo) {
             rc = orc_model_eval(md, l, J, th, Gl);
             if (rc) break;
@@ -764,10 +764,21 @@ static int orc_mutate(orc_model* md, const double* y, int stage, int l, int brid
     return rc;
 }
 
-static void orc_log_stage(orc_result* r, int type, int level, double beta, double zeta, double ess)
+/* pCN step adaptation towards an acceptance rate of 1/4 (an extension) */
+static double orc_adapt_step(double s, int64_t acc, int64_t prop)
+{
+    double a = prop > 0 ? (double)acc / (double)prop : 0.25;
+    double t = s * exp(2.0 * (a - 0.25));
+    return t < 0.005 ? 0.005 : (t > 1.0 ? 1.0 : t);
+}
+
+static void orc_log_stage(orc_result* r, int type, int level, double beta, double zeta, double ess,
+                          double step, double acc_rate)
 {
     int s = r->n_stages;
     if (s < r->max_stage_log) {
+        if (r->stage_step) r->stage_step[s] = step;
+        if (r->stage_acc_rate) r->stage_acc_rate[s] = acc_rate;
         if (r->stage_type) r->stage_type[s] = type;
         if (r->stage_level) r->stage_level[s] = level;
         if (r->stage_beta) r->stage_beta[s] = beta;
@@ -817,6 +828,7 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
     for (int64_t i = 0; i < J * K; ++i) s.theta[i] = orc_normal(cfg->seed, ST_PRIOR, 0, 0, (uint32_t)i);
     int l = cfg->l_min;
     double beta = 0.0;
+    double s_pcn = cfg->s_pcn;
     int prev_lu = 1; /* u(-1) = (0,0): the first update is a tempering update */
     rc = orc_model_eval(&md, l, J, s.theta, s.Glo);
     if (rc == 0) { orc_potentials(&md, J, s.Glo, y, s.philo); res->solves[l] += J; }
@@ -849,11 +861,15 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
             rc = orc_resample(J, w, u, anc);
             if (rc) break;
             orc_gather(J, K, nobs, anc, &s, &tmp, 0);
-            rc = orc_mutate(&md, y, stage, l, 0, nb, 1.0, &s, res->solves, &res->accepted, &res->proposed,
-                            &res->stage1_passed);
+            const int64_t a0 = res->accepted;
+            const double s_used = s_pcn;
+            rc = orc_mutate(&md, y, stage, l, 0, nb, 1.0, s_pcn, &s, res->solves, &res->accepted,
+                            &res->proposed, &res->stage1_passed);
             if (rc) break;
+            if (cfg->s_adapt) s_pcn = orc_adapt_step(s_pcn, res->accepted - a0, J * cfg->n_mcmc);
             beta = nb;
-            orc_log_stage(res, checked ? 1 : 0, l, beta, 0.0, ess);
+            orc_log_stage(res, checked ? 1 : 0, l, beta, 0.0, ess, s_used,
+                          cfg->n_mcmc ? (double)(res->accepted - a0) / (double)(J * cfg->n_mcmc) : 0.0);
             ++stage;
             prev_lu = 0;
         } else {
@@ -878,11 +894,15 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
                 rc = orc_resample(J, w, u, anc);
                 if (rc) break;
                 orc_gather(J, K, nobs, anc, &s, &tmp, 1);
-                rc = orc_mutate(&md, y, stage, l, 1, beta, nz, &s, res->solves, &res->accepted, &res->proposed,
-                                &res->stage1_passed);
+                const int64_t a0 = res->accepted;
+                const double s_used = s_pcn;
+                rc = orc_mutate(&md, y, stage, l, 1, beta, nz, s_pcn, &s, res->solves, &res->accepted,
+                                &res->proposed, &res->stage1_passed);
                 if (rc) break;
+                if (cfg->s_adapt) s_pcn = orc_adapt_step(s_pcn, res->accepted - a0, J * cfg->n_mcmc);
                 zeta = nz;
-                orc_log_stage(res, first ? (checked ? 2 : 3) : 4, l + 1, beta, zeta, ess);
+                orc_log_stage(res, first ? (checked ? 2 : 3) : 4, l + 1, beta, zeta, ess, s_used,
+                              cfg->n_mcmc ? (double)(res->accepted - a0) / (double)(J * cfg->n_mcmc) : 0.0);
                 first = 0;
                 ++stage;
             }

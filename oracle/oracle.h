@@ -142,6 +142,10 @@ typedef struct {
      * (nobs x K, linear model only); NULL = plain pCN.  Uniforms of the
      * second stage come from stream 6.                                     */
     const double* da_S;
+    /* optional pCN step adaptation (not in the paper; 0 = fixed s_pcn):
+     * after each stage s <- clamp(s exp(2 (a - 0.25)), 0.005, 1), a the
+     * stage's acceptance rate.                                             */
+    int s_adapt;
 } orc_config;
 
 typedef struct {
@@ -161,6 +165,8 @@ typedef struct {
     double* stage_beta;
     double* stage_zeta;
     double* stage_ess;
+    double* stage_step;     /* pCN step used in the stage's mutation          */
+    double* stage_acc_rate; /* accepted / (J n_mcmc) in the stage's mutation  */
     int max_stage_log;
 } orc_result;
 

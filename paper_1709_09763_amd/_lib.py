@@ -35,7 +35,8 @@ class RunConfig(C.Structure):
                 ("s_pcn", C.c_double), ("seed", C.c_uint64), ("max_stages", C.c_int),
                 ("surrogate", C.c_int), ("sur_collect_max_level", C.c_int),
                 ("sur_da_min_level", C.c_int), ("sur_pairs", C.c_int64), ("sur_epochs", C.c_int),
-                ("sur_hidden", C.c_int), ("sur_batch", C.c_int), ("sur_lr", C.c_double)]
+                ("sur_hidden", C.c_int), ("sur_batch", C.c_int), ("sur_lr", C.c_double),
+                ("s_adapt", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -552,7 +553,7 @@ class Context:
         return acc
 
     def run_batch(self, instances, J_tilde=0, tau_star=1.0, n_mcmc=5, s_pcn=0.5, use_graphs=True):
-        cfg = RunConfig(0, J_tilde, tau_star, 0.0, 0.0, n_mcmc, s_pcn, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0)
+        cfg = RunConfig(0, J_tilde, tau_star, 0.0, 0.0, n_mcmc, s_pcn, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0)
         for d in instances:
             d.setdefault("theta_out", torch.empty((d["J"], self.K), dtype=torch.float64, device="cuda:0"))
         out = mls2mc_run_batch(self.h, cfg, instances, use_graphs)
@@ -562,10 +563,10 @@ class Context:
 
     def run(self, y, J, J_tilde=0, tau_star=1.0, tau_lu=0.0, eps=0.0, n_mcmc=5, s_pcn=0.5, seed=0,
             max_stages=0, surrogate=False, sur_collect_max_level=0, sur_da_min_level=0, sur_pairs=0,
-            sur_epochs=0, sur_hidden=0, sur_batch=0, sur_lr=0.0):
+            sur_epochs=0, sur_hidden=0, sur_batch=0, sur_lr=0.0, s_adapt=False):
         cfg = RunConfig(J, J_tilde, tau_star, tau_lu, eps, n_mcmc, s_pcn, seed, max_stages,
                         int(surrogate), sur_collect_max_level, sur_da_min_level, sur_pairs, sur_epochs,
-                        sur_hidden, sur_batch, sur_lr)
+                        sur_hidden, sur_batch, sur_lr, int(s_adapt))
         theta = torch.empty((J, self.K), dtype=torch.float64, device=y.device)
         out = mls2mc_run(self.h, cfg, y, theta)
         out["theta"] = theta

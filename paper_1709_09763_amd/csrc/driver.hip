@@ -136,13 +136,19 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         return MLS2MC_OK;
     };
     double acc_host = 0;
+    double s_cur = cfg->s_pcn;
+    auto adapt = [&](double acc_rate) {  // pCN step adaptation (optional extension)
+        if (!cfg->s_adapt) return;
+        const double t = s_cur * std::exp(2.0 * (acc_rate - 0.25));
+        s_cur = t < 0.005 ? 0.005 : (t > 1.0 ? 1.0 : t);
+    };
     auto mutate = [&](int stage, int l, bool bridge, double beta, double zeta) -> int {
         mls2mc_stage st;
         st.l_lo = l;
         st.l_hi = bridge ? l + 1 : l;
         st.beta = beta;
         st.zeta = bridge ? zeta : 1.0;
-        st.s = cfg->s_pcn;
+        st.s = s_cur;
         const bool da = sur_ready && l >= sur_da;
         for (int m = 0; m < cfg->n_mcmc; ++m) {
             MLS_TRY(launch_philox(cfg->seed, ST_PCN_XI, (uint32_t)stage, (uint32_t)m, J * K, 1, R.xi, s));
@@ -254,6 +260,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
             const double a0 = acc_host;
             MLS_TRY(mutate(stage, l, false, h[0], 1.0));
             acc_host = acc_count();
+            if (cfg->n_mcmc) adapt((acc_host - a0) / ((double)J * cfg->n_mcmc));
             beta = h[0];
             log_stage(checked ? 1 : 0, l, beta, 0.0, h[2]);
             if (res->stage_acc_rate && stage < res->max_stage_log)
@@ -280,6 +287,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
                 const double a0 = acc_host;
                 MLS_TRY(mutate(stage, l, true, beta, h[0]));
                 acc_host = acc_count();
+                if (cfg->n_mcmc) adapt((acc_host - a0) / ((double)J * cfg->n_mcmc));
                 zeta = h[0];
                 log_stage(first ? (checked ? 2 : 3) : 4, l + 1, beta, zeta, h[2]);
                 if (res->stage_acc_rate && stage < res->max_stage_log)

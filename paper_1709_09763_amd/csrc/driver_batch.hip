@@ -110,7 +110,8 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
 {
     MLS_REQUIRE(ctx && cfg && inst && res, "run_batch: null argument");
     MLS_REQUIRE(n_inst >= 1 && n_inst <= 4096, "run_batch: need 1 <= n_inst <= 4096");
-    MLS_REQUIRE(cfg->surrogate == 0, "run_batch: the surrogate form runs through mls2mc_run");
+    MLS_REQUIRE(cfg->surrogate == 0 && cfg->s_adapt == 0,
+                "run_batch: the surrogate form and pCN step adaptation run through mls2mc_run");
     MLS_REQUIRE(cfg->tau_star > 0 && cfg->n_mcmc >= 0 && cfg->s_pcn > 0 && cfg->s_pcn <= 1,
                 "run_batch: need tau_star > 0, n_mcmc >= 0, 0 < s_pcn <= 1");
     const int K = ctx->prob.K, nobs = ctx->nobs;

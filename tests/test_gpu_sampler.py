@@ -155,16 +155,20 @@ def _data(l, K, m, sn, seed=0):
 @pytest.mark.parametrize("cfg", [
     dict(name="single-level SMC h=1/16", l_min=4, l_max=4, K=10, m=3, sn=0.01, J=200),
     dict(name="MLS2MC h=1/8..1/32", l_min=3, l_max=5, K=10, m=3, sn=0.01, J=200),
+    dict(name="MLS2MC h=1/8..1/32, adapted pCN step", l_min=3, l_max=5, K=10, m=3, sn=0.002, J=200,
+         s_adapt=True),
 ])
 def test_run_matches_oracle(cfg):
     device()
     case(f"run {cfg['name']}")
     K, m, sn = cfg["K"], cfg["m"], cfg["sn"]
+    sa = cfg.get("s_adapt", False)
     y = _data(cfg["l_max"], K, m, sn)
     ctx = P.Context(cfg["l_min"], cfg["l_max"], K, 1.0, 0.3, m, sn)
-    g = ctx.run(to_dev(y), cfg["J"], J_tilde=min(100, cfg["J"]), tau_star=1.0, n_mcmc=5, s_pcn=0.5, seed=5)
+    g = ctx.run(to_dev(y), cfg["J"], J_tilde=min(100, cfg["J"]), tau_star=1.0, n_mcmc=5, s_pcn=0.5, seed=5,
+                s_adapt=sa)
     r = oracle.run_sampler(y, l_min=cfg["l_min"], l_max=cfg["l_max"], K=K, m=m, sigma_n=sn, J=cfg["J"],
-                           J_tilde=min(100, cfg["J"]), seed=5, n_mcmc=5, s_pcn=0.5)
+                           J_tilde=min(100, cfg["J"]), seed=5, n_mcmc=5, s_pcn=0.5, s_adapt=sa)
     print(f"  stages gpu {g['n_stages']} oracle {r['n_stages']}, gpu {g['seconds']:.2f}s")
     assert g["n_stages"] == r["n_stages"]
     np.testing.assert_array_equal(g["stage_type"], r["stage_type"])
@@ -173,6 +177,7 @@ def test_run_matches_oracle(cfg):
     np.testing.assert_allclose(g["stage_zeta"], r["stage_zeta"], rtol=1e-8, atol=1e-12)
     assert g["solves"] == r["solves"]
     assert g["accepted"] == r["accepted"]
+    np.testing.assert_array_equal(g["stage_acc_rate"], r["stage_acc_rate"])
     assert abs(g["log_Z"] - r["log_Z"]) < 1e-7 * max(1, abs(r["log_Z"]))
     th = host(g["theta"])
     assert rel_err(th.mean(0), r["theta"].mean(0)) < 1e-8

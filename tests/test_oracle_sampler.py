@@ -53,7 +53,10 @@ def _expected_solves(r, J, Jt, n_mcmc, l_min):
 
 
 @pytest.mark.slow
-def test_linear_gaussian_single_level_posterior_and_evidence():
+@pytest.mark.parametrize("s_adapt", [False, True])
+def test_linear_gaussian_single_level_posterior_and_evidence(s_adapt):
+    # the optional step adaptation changes the step only between stages, so
+    # every mutation kernel still leaves its tempered target invariant
     s = 0.2
     A, E, y = _lin_problem(s=s)
     m, C, logZ = _lin_posterior(A + 2.0 ** -6 * E, y, s)
@@ -61,7 +64,7 @@ def test_linear_gaussian_single_level_posterior_and_evidence():
     means, vars_, lz = [], [], []
     for seed in range(R):
         r = oracle.run_sampler(y, model="linear", l_min=3, l_max=3, K=3, nobs=4, sigma_n=s, J=J,
-                               seed=seed, lin_A=A, lin_E=E, n_mcmc=5)
+                               seed=seed, lin_A=A, lin_E=E, n_mcmc=5, s_adapt=s_adapt)
         assert np.all(r["stage_type"] == 0)  # single-level SMC
         means.append(r["theta"].mean(0))
         vars_.append(r["theta"].var(0))
@@ -114,6 +117,25 @@ def test_first_update_is_tempering_and_levels_monotone():
         if t[i] in (0, 1) and t[i - 1] in (2, 3, 4):
             assert t[i] == 0
     np.testing.assert_array_equal(np.array(r["solves"]), _expected_solves(r, 300, 50, 5, 1))
+
+
+def test_step_adaptation_schedule():
+    A, E, y = _lin_problem(seed=7)
+    kw = dict(model="linear", l_min=1, l_max=3, K=3, nobs=4, sigma_n=0.05, J=300, J_tilde=50,
+              seed=4, lin_A=A, lin_E=5 * E, s_pcn=0.9)
+    fixed = oracle.run_sampler(y, **kw)
+    np.testing.assert_array_equal(fixed["stage_step"], 0.9)
+    r = oracle.run_sampler(y, s_adapt=True, **kw)
+    st, a = r["stage_step"], r["stage_acc_rate"]
+    assert st[0] == 0.9 and len(st) > 3
+    # each stage's step follows from the previous stage's step and acceptance
+    # rate: it grows iff that rate exceeded 1/4, and stays in [0.005, 1]
+    for k in range(1, len(st)):
+        want = min(1.0, max(0.005, st[k - 1] * np.exp(2.0 * (a[k - 1] - 0.25))))
+        assert abs(st[k] - want) <= 1e-15 * want
+        assert (st[k] > st[k - 1]) == (a[k - 1] > 0.25) or st[k] in (0.005, 1.0)
+    # small noise: the fixed step's acceptance collapses, the adapted one stays nearer 1/4
+    assert abs(np.mean(a[-3:]) - 0.25) < abs(np.mean(fixed["stage_acc_rate"][-3:]) - 0.25)
 
 
 def test_deterministic_replay():
