@@ -111,7 +111,10 @@ def tune_levels(ctx, levels, J):
 
 def leg_fast(args):
     """h=1/8..1/256, K=100, 49 obs, sigma_n=0.002, J=4096: time-to-posterior of
-    the plain FP64 form and of the mixed-precision + surrogate form"""
+    the plain FP64 form and of the mixed-precision + surrogate form.  With
+    --seeds R > 1 each form runs R times; the posterior-mean error of every
+    run is then measured against the mean over all 2R runs as well as
+    against the true parameter."""
     import numpy as np
     import torch
 
@@ -124,36 +127,50 @@ def leg_fast(args):
     lam = ctx.kl_eigenvalues()
     y = ctx.forward(lmax, torch.tensor(th_true[None, :], device=dev))[0]
     y = (y + sn * torch.tensor(rng.standard_normal(m * m), device=dev)).contiguous()
-    out = {}
     tuned = tune_levels(ctx, range(lmin, lmax + 1), J)
     log(f"fast leg: tuned fp64 {tuned}")
-    r = ctx.run(y, J, seed=21, s_adapt=args.s_adapt)
-    mp = r["theta"].cpu().numpy().mean(0)
-    out["plain_fp64"] = dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
-                             solves={str(i): v for i, v in enumerate(r["solves"]) if v},
-                             rel_err_vs_truth=rel_err_paper(mp, th_true, lam), log_Z=r["log_Z"],
-                             stage_acc_rate=[round(float(a), 4) for a in r["stage_acc_rate"]])
-    log(f"plain {out['plain_fp64']}")
     ctxm = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn, precision=P.MIXED)
     tune_levels(ctxm, range(lmin, lmax + 1), J)
-    rm = ctxm.run(y, J, seed=21, surrogate=True, sur_collect_max_level=6, sur_da_min_level=7,
-                  sur_pairs=20480, sur_epochs=30, sur_hidden=256, s_adapt=args.s_adapt)
-    mf = rm["theta"].cpu().numpy().mean(0)
-    out["mixed_surrogate"] = dict(seconds=round(rm["seconds"], 3), stages=rm["n_stages"],
-                                  solves={str(i): v for i, v in enumerate(rm["solves"]) if v},
-                                  rel_err_vs_truth=rel_err_paper(mf, th_true, lam), log_Z=rm["log_Z"],
-                                  surrogate_train_s=round(rm["sur_train_seconds"], 3),
-                                  stage1_pass_frac=rm["stage1_passed"] / max(1, rm["da_proposed"]),
-                                  stage_acc_rate=[round(float(a), 4) for a in rm["stage_acc_rate"]])
-    out["rel_err_between_forms"] = rel_err_paper(mf, mp, lam)
-    log(f"fast {out['mixed_surrogate']}")
+    seeds = [21 + i for i in range(max(1, args.seeds))]
+    runs = {"plain_fp64": [], "mixed_surrogate": []}
+    for sd in seeds:
+        r = ctx.run(y, J, seed=sd, s_adapt=args.s_adapt)
+        runs["plain_fp64"].append(dict(
+            seconds=r["seconds"], stages=r["n_stages"], solves={str(i): v for i, v in enumerate(r["solves"]) if v},
+            mean=r["theta"].cpu().numpy().mean(0), log_Z=r["log_Z"],
+            stage_acc_rate=[round(float(a), 4) for a in r["stage_acc_rate"]]))
+        rm = ctxm.run(y, J, seed=sd, surrogate=True, sur_collect_max_level=6, sur_da_min_level=7,
+                      sur_pairs=20480, sur_epochs=30, sur_hidden=256, s_adapt=args.s_adapt)
+        runs["mixed_surrogate"].append(dict(
+            seconds=rm["seconds"], stages=rm["n_stages"], solves={str(i): v for i, v in enumerate(rm["solves"]) if v},
+            mean=rm["theta"].cpu().numpy().mean(0), log_Z=rm["log_Z"],
+            surrogate_train_s=round(rm["sur_train_seconds"], 3),
+            stage1_pass_frac=rm["stage1_passed"] / max(1, rm["da_proposed"]),
+            stage_acc_rate=[round(float(a), 4) for a in rm["stage_acc_rate"]]))
+        log(f"seed {sd}: plain {runs['plain_fp64'][-1]['seconds']:.3f} s, "
+            f"mixed+surrogate {runs['mixed_surrogate'][-1]['seconds']:.3f} s")
+    pooled = np.mean([d["mean"] for v in runs.values() for d in v], axis=0)
+    out = {}
+    for name, v in runs.items():
+        o = dict(v[0])
+        o.pop("mean")
+        o["seconds"] = round(float(np.median([d["seconds"] for d in v])), 3)
+        o["seconds_all"] = [round(d["seconds"], 3) for d in v]
+        o["rel_err_vs_truth"] = [rel_err_paper(d["mean"], th_true, lam) for d in v]
+        o["log_Z_all"] = [d["log_Z"] for d in v]
+        if len(v) > 1:
+            o["rel_err_vs_pooled_mean"] = [rel_err_paper(d["mean"], pooled, lam) for d in v]
+        out[name] = o
+        log(f"{name} {o}")
+    out["rel_err_between_forms"] = rel_err_paper(np.mean([d["mean"] for d in runs["mixed_surrogate"]], 0),
+                                                 np.mean([d["mean"] for d in runs["plain_fp64"]], 0), lam)
     print(json.dumps({
         "metric": "MLS²MC time-to-posterior, plain vs surrogate+FP32",
         "value": out["mixed_surrogate"]["seconds"], "unit": "s (mixed precision + surrogate)",
         "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "bf16/f32/f64",
         "data": "synthetic", "speedup_vs_plain_fp64": round(out["plain_fp64"]["seconds"] / out["mixed_surrogate"]["seconds"], 3),
         "config": {"workload": "mls2mc h=1/8..1/256 K=100 Nobs=49 sigma_n=0.002 J=4096",
-                   "pcn_step": "adapted" if args.s_adapt else "fixed 0.5"}, **out}))
+                   "pcn_step": "adapted" if args.s_adapt else "fixed 0.5", "seeds": seeds}, **out}))
 
 
 def leg_batched(args):
@@ -300,6 +317,7 @@ def main():
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
     ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest", "largest-run"],
                     help="cfg1: the default stage benchmark; others: the extra workloads")
+    ap.add_argument("--seeds", type=int, default=1, help="fast: independent runs per form")
     ap.add_argument("--s-adapt", action="store_true",
                     help="fast / largest-run: adapt the pCN step between stages (an extension)")
     ap.add_argument("--batched-sequential", action="store_true",

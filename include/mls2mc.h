@@ -361,14 +361,16 @@ int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint3
 /* Autotune the solver for level l on N prior draws: every candidate
  * (persistent workgroups = w x CUs capped at N; block size; V-cycle
  * Gauss-Seidel sweeps per side nu in {1,2}; LDS residency of the multigrid
- * hierarchy: none or a 64 KiB budget) solves the batch to the context's
+ * hierarchy and of the finest level's arrays: none, 64 KiB, 80 KiB or the
+ * device's LDS per workgroup less 1 KiB) solves the batch to the context's
  * tolerance, is timed with HIP events (best of 3), and the fastest is kept
  * in the context for level l.  best_ms (host, may be NULL) receives its
  * time.  Synchronous; allocates its own temporary buffers.                 */
 int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_ms, void* stream);
 /* Read / set the solver schedule of level l (grid 0, block 0, nu 0 or
  * lds_bytes 0 = built-in default; lds_bytes -1 = no LDS residency, else
- * the per-workgroup LDS budget, at most 65536), e.g. to restore tuned
+ * the per-workgroup LDS budget in bytes, at most the device's LDS per
+ * workgroup less 1 KiB; 160 KiB on gfx950), e.g. to restore tuned
  * schedules cached by the caller.                                          */
 int mls2mc_get_launch(const mls2mc_ctx* ctx, int l, int* grid, int* block, int* nu, int* lds_bytes);
 int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, int nu, int lds_bytes);

@@ -246,8 +246,11 @@ int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out)
     }
     {
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
-            ctx->n_cu = prop.multiProcessorCount;
+        if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) {
+            if (prop.multiProcessorCount > 0) ctx->n_cu = prop.multiProcessorCount;
+            // leave 1 KiB of the workgroup's LDS to the kernels' static reduction arrays
+            if (prop.sharedMemPerBlock > 65536 + 1024) ctx->max_lds = (int)(prop.sharedMemPerBlock - 1024);
+        }
     }
     ctx->rtol = p->rtol > 0 ? p->rtol : (p->precision == MLS2MC_MIXED ? 1e-10 : 1e-11);
     ctx->max_iters = p->max_iters > 0 ? p->max_iters : 200;

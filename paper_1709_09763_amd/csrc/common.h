@@ -64,6 +64,8 @@ inline int64_t n_pad(int l) { return (n_side(l) + 1) * (n_side(l) + 1); }
 
 // Per-particle solver workspace (elements of the working type), see solver.hip.
 int64_t solver_slot_elems(int l, bool mixed);
+// LDS elements the solver's residency policy uses at level l for a budget
+int64_t solver_lds_elems_used(int l, int64_t budget_elems);
 
 // ------------------------------------------------------- observation --
 // Three nodes (padded-grid offsets) and barycentric weights per observation.
@@ -111,6 +113,7 @@ struct mls2mc_ctx {
     int solver_block[mls::kMaxLevel + 1] = {};
     int solver_nu[mls::kMaxLevel + 1] = {};     // Gauss-Seidel sweeps per V-cycle side (0 = 1)
     int solver_lds[mls::kMaxLevel + 1] = {};    // LDS budget in bytes (0 = 64 KiB, -1 = none)
+    int max_lds = 65536;                        // largest LDS budget a launch may take (bytes)
     int list_grid = 0, list_block = 0;          // work-list launch shape (0 = auto)
     double rtol = 1e-11;
     int max_iters = 200;

@@ -22,14 +22,22 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // BF16 as the fragments are loaded (v_mfma_f32_16x16x32_bf16 lanes: A rows
 // lane%16, k = 8(lane/16)+0..7; B cols lane%16, same k; D[4(lane/16)+v][lane%16]).
 // Epilogues: 0 store; 1 +bias, store Z to C and GELU(Z) to C2; 2 +bias;
-// 3 multiply by GELU'(Zin[m][n]) (backward through the activation).
-enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_DGELU = 3 };
+// 3 multiply by GELU'(Zin[m][n]) (backward through the activation); 4 store,
+// and (TA only) also write the row sums over k of A, sum_k A(m,k), to C2[m]:
+// the bias gradient of a layer comes out of its weight-gradient product.
+enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_BIAS = 2, EPI_DGELU = 3, EPI_STORE_ASUM = 4 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float z)
 {
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
 }
+
+// Each wave owns one 16x16 tile of C, a workgroup 32x32.  The k loop loads
+// the fragments of MLP_U consecutive 32-wide k steps before it issues their
+// MFMAs, so one round of memory latency covers MLP_U steps (K <= 256 in the
+// surrogate: at most two rounds).
+constexpr int MLP_U = 4;
 
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void mlp_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
@@ -38,24 +46,38 @@ __global__ __launch_bounds__(256) void mlp_gemm(int M, int N, int K, const float
                                                 float* __restrict__ C2, const float* __restrict__ Zin,
                                                 int ldc)
 {
+    static_assert(EPI != EPI_STORE_ASUM || TA, "row sums of A are taken for the transposed-A form");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int m0 = blockIdx.y * 32 + 16 * (wv >> 1);
     const int n0 = blockIdx.x * 32 + 16 * (wv & 1);
+    const bool asum = EPI == EPI_STORE_ASUM && blockIdx.x == 0 && (wv & 1) == 0;
     flt4 acc = {0.f, 0.f, 0.f, 0.f};
+    float rs = 0.f;
     const int am = m0 + r, bn = n0 + r;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 a, b;
+    for (int k0 = 0; k0 < K; k0 += 32 * MLP_U) {
+        bf16x8 a[MLP_U], b[MLP_U];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int k = k0 + 8 * kq + t;
-            float av = 0.f, bv = 0.f;
-            if (am < M && k < K) av = TA ? A[(int64_t)k * lda + am] : A[(int64_t)am * lda + k];
-            if (bn < N && k < K) bv = TB ? B[(int64_t)bn * ldb + k] : B[(int64_t)k * ldb + bn];
-            a[t] = (__bf16)av;
-            b[t] = (__bf16)bv;
+        for (int u = 0; u < MLP_U; ++u) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int k = k0 + 32 * u + 8 * kq + t;
+                float av = 0.f, bv = 0.f;
+                if (am < M && k < K) av = TA ? A[(int64_t)k * lda + am] : A[(int64_t)am * lda + k];
+                if (bn < N && k < K) bv = TB ? B[(int64_t)bn * ldb + k] : B[(int64_t)k * ldb + bn];
+                if (EPI == EPI_STORE_ASUM) rs += av;
+                a[u][t] = (__bf16)av;
+                b[u][t] = (__bf16)bv;
+            }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < MLP_U; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[u], acc, 0, 0, 0);
+    }
+    if (EPI == EPI_STORE_ASUM) {
+        // lanes r, r+16, r+32, r+48 hold the partial sums of row am
+        rs += __shfl_xor(rs, 16);
+        rs += __shfl_xor(rs, 32);
+        if (asum && kq == 0 && am < M) C2[am] = rs;
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -89,15 +111,6 @@ static int gemm(int M, int N, int K, const float* A, int lda, const float* B, in
 }
 
 // ------------------------------------------------------- small kernels --
-__global__ void col_sum_kernel(int M, int N, const float* __restrict__ D, float* __restrict__ out)
-{
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.f;
-    for (int m = 0; m < M; ++m) s += D[(int64_t)m * N + n];
-    out[n] = s;
-}
-
 // delta = (out - t) * scale, loss = scale * sum (out - t)^2 / 2 (one workgroup)
 __global__ __launch_bounds__(1024) void loss_delta_kernel(int64_t n, const float* __restrict__ out,
                                                           const float* __restrict__ t, float scale,
@@ -258,17 +271,14 @@ static int sur_backward(Surrogate* S, int64_t B, hipStream_t s)
     MLS_CHECK_HIP(hipGetLastError());
     float *gW1 = S->g, *gb1 = gW1 + (int64_t)H * D, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)H * H,
           *gW3 = gb2 + H, *gb3 = gW3 + (int64_t)O * H;
-    // layer 3: dW3 = D3^T H2, db3 = colsum D3, dH2 = D3 W3 (then * GELU'(Z2))
-    MLS_TRY((gemm<true, false, EPI_STORE>(O, H, (int)B, S->D3, O, S->H2, H, nullptr, gW3, nullptr, nullptr, H, s)));
-    col_sum_kernel<<<(O + 255) / 256, 256, 0, s>>>((int)B, O, S->D3, gb3);
+    // layer 3: dW3 = D3^T H2 and db3 = colsum D3 in one product; dH2 = D3 W3 (then * GELU'(Z2))
+    MLS_TRY((gemm<true, false, EPI_STORE_ASUM>(O, H, (int)B, S->D3, O, S->H2, H, nullptr, gW3, gb3, nullptr, H, s)));
     MLS_TRY((gemm<false, false, EPI_DGELU>((int)B, H, O, S->D3, O, S->W3(), H, nullptr, S->D2, nullptr, S->Z2, H, s)));
     // layer 2
-    MLS_TRY((gemm<true, false, EPI_STORE>(H, H, (int)B, S->D2, H, S->H1, H, nullptr, gW2, nullptr, nullptr, H, s)));
-    col_sum_kernel<<<(H + 255) / 256, 256, 0, s>>>((int)B, H, S->D2, gb2);
+    MLS_TRY((gemm<true, false, EPI_STORE_ASUM>(H, H, (int)B, S->D2, H, S->H1, H, nullptr, gW2, gb2, nullptr, H, s)));
     MLS_TRY((gemm<false, false, EPI_DGELU>((int)B, H, H, S->D2, H, S->W2(), H, nullptr, S->D1, nullptr, S->Z1, H, s)));
     // layer 1
-    MLS_TRY((gemm<true, false, EPI_STORE>(H, D, (int)B, S->D1, H, S->X, D, nullptr, gW1, nullptr, nullptr, D, s)));
-    col_sum_kernel<<<(H + 255) / 256, 256, 0, s>>>((int)B, H, S->D1, gb1);
+    MLS_TRY((gemm<true, false, EPI_STORE_ASUM>(H, D, (int)B, S->D1, H, S->X, D, nullptr, gW1, gb1, nullptr, D, s)));
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
 }

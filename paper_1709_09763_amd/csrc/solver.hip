@@ -36,11 +36,11 @@ namespace mls {
 // Padded node grids (n+1)^2, node (i,j) at j(n+1)+i, boundary entries 0.
 // wx[j][i]: weight of edge (i,j)-(i+1,j); wy[j][i]: edge (i,j)-(i,j+1).
 // Slot layout (elements of T):
-//   fine level l:   X R Z P Q WX WY RES              8 S_l
-//   coarse L<l:     WX WY XC BC RESC                 5 S_L    then
+//   fine level l:   X R Z P Q WX WY P2               8 S_l
+//   coarse L<l:     WX WY XC BC                      4 S_L    then
 //                   KAP (per-triangle kappa)         2 n_L^2
 __host__ __device__ inline int64_t pad_sz(int L) { return ((int64_t(1) << L) + 1) * ((int64_t(1) << L) + 1); }
-__host__ __device__ inline int64_t coarse_sz(int L) { return 5 * pad_sz(L) + 2 * (int64_t(1) << (2 * L)); }
+__host__ __device__ inline int64_t coarse_sz(int L) { return 4 * pad_sz(L) + 2 * (int64_t(1) << (2 * L)); }
 
 __host__ __device__ inline int64_t coarse_off(int l, int L)
 {
@@ -61,53 +61,64 @@ int64_t solver_slot_elems(int l, bool mixed) { return slot_elems_hd(l, mixed); }
 
 template <typename T>
 struct Lv {
-    T *wx, *wy, *x, *b, *res, *kap;
+    T *wx, *wy, *x, *b, *kap;
     int n, lg, s;
 };
 
 // Where a particle's arrays live.  Coarse levels L <= lds_top keep their
-// five work arrays (WX WY XC BC RESC) in LDS, finest of them first; when
-// fine_lds is set the fine level's eight arrays follow them in LDS too.  The
-// per-triangle coefficients of coarse levels (setup only) and every array
-// of the remaining levels stay in the global slot.
+// four work arrays (WX WY XC BC) in LDS, finest of them first; after them
+// come the first fine_n of the fine level's arrays in the order of how many
+// passes of a PCG iteration touch them: WX WY (read by every pass), Z and R
+// (the V-cycle's unknown and right-hand side), the two search-direction
+// buffers, Q, X.  The per-triangle coefficients of coarse levels (setup
+// only) and every other array stay in the global slot.
+enum { FX = 0, FR, FZ, FP, FQ, FWX, FWY, FP2 };  // slot order of the fine arrays
+__host__ __device__ inline int fine_rank(int k)   // LDS priority of slot array k
+{
+    // X R Z P Q WX WY P2 -> 7 3 2 4 6 0 1 5
+    return (int)((0x51064237u >> (4 * k)) & 0xfu);
+}
+
 template <typename T>
 struct Map {
     T* slot;
     T* lds;
     int l;
     int lds_top;
-    bool fine_lds;
+    int fine_n;
 };
 
 __host__ __device__ inline int64_t lds_coarse_elems(int top)
 {
     int64_t o = 0;
-    for (int k = 1; k <= top; ++k) o += 5 * pad_sz(k);
+    for (int k = 1; k <= top; ++k) o += 4 * pad_sz(k);
     return o;
 }
 
-// the largest residency that fits `budget` elements
-__host__ __device__ inline void lds_policy(int l, int64_t budget, int* top, bool* fine)
+// The residency for a budget of `budget` elements: the finest coarse level
+// whose hierarchy fits, then as many fine arrays as fit in what is left.
+// Never uses more than the budget, and applied to its own usage it returns
+// the same residency (so a launch may pass the usage as the budget).
+__host__ __device__ inline void lds_policy(int l, int64_t budget, int* top, int* fine_n)
 {
-    *fine = false;
+    *fine_n = 0;
     *top = 0;
     if (budget <= 0) return;
-    if (lds_coarse_elems(l - 1) + 8 * pad_sz(l) <= budget) {
-        *fine = true;
-        *top = l - 1;
-        return;
-    }
     for (int t = l - 1; t >= 1; --t)
-        if (lds_coarse_elems(t) <= budget) { *top = t; return; }
+        if (lds_coarse_elems(t) <= budget) { *top = t; break; }
+    const int64_t rem = budget - lds_coarse_elems(*top);
+    const int64_t nf = rem / pad_sz(l);
+    *fine_n = (int)(nf < 8 ? nf : 8);
 }
 
 __host__ __device__ inline int64_t lds_elems_used(int l, int64_t budget)
 {
-    int top;
-    bool fine;
-    lds_policy(l, budget, &top, &fine);
-    return lds_coarse_elems(top) + (fine ? 8 * pad_sz(l) : 0);
+    int top, fine_n;
+    lds_policy(l, budget, &top, &fine_n);
+    return lds_coarse_elems(top) + fine_n * pad_sz(l);
 }
+
+int64_t solver_lds_elems_used(int l, int64_t budget_elems) { return lds_elems_used(l, budget_elems); }
 
 template <typename T>
 __device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems)
@@ -116,7 +127,7 @@ __device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_ele
     M.slot = slot;
     M.lds = lds;
     M.l = l;
-    lds_policy(l, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_lds);
+    lds_policy(l, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_n);
     return M;
 }
 
@@ -127,17 +138,19 @@ __device__ inline Lv<T> coarse_level(const Map<T>& M, int L)
     T* g = M.slot + coarse_off(M.l, L);
     const int64_t S = pad_sz(L);
     T* base = (L <= M.lds_top) ? M.lds + (lds_coarse_elems(M.lds_top) - lds_coarse_elems(L)) : g;
-    v.wx = base; v.wy = base + S; v.x = base + 2 * S; v.b = base + 3 * S; v.res = base + 4 * S;
-    v.kap = g + 5 * S;
+    v.wx = base; v.wy = base + S; v.x = base + 2 * S; v.b = base + 3 * S;
+    v.kap = g + 4 * S;
     v.n = 1 << L; v.lg = L; v.s = v.n + 1;
     return v;
 }
 
-// base of the fine level's X R Z P Q WX WY RES
+// fine array k (FX .. FP2) of the particle
 template <typename T>
-__device__ inline T* fine_base(const Map<T>& M)
+__device__ inline T* fine_array(const Map<T>& M, int k)
 {
-    return M.fine_lds ? M.lds + lds_coarse_elems(M.lds_top) : M.slot;
+    const int64_t S = pad_sz(M.l);
+    const int r = fine_rank(k);
+    return r < M.fine_n ? M.lds + lds_coarse_elems(M.lds_top) + r * S : M.slot + k * S;
 }
 
 // ----------------------------------------------------------- stencils --
@@ -240,6 +253,29 @@ __device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __rest
     }
 }
 
+// First black sweep after the coarse-grid correction x += P e.  A black
+// node's four neighbours are red, and the corrected red values are read only
+// by this sweep (the red sweep after it overwrites them), so the correction
+// is interpolated at the neighbours on the fly and never stored.  At a red
+// node (i', j') both indices are even (the coarse node itself) or both odd
+// (the middle of a coarse diagonal edge, from (i'-1, j'-1) to (i'+1, j'+1)).
+template <int BS, typename T>
+__device__ void smooth_black_corrected(const Lv<T>& L, const Lv<T>& C, const T* __restrict__ b,
+                                       T* __restrict__ x)
+{
+    const int s = L.s, sc = C.s;
+    const T* __restrict__ e = C.x;
+    auto pe = [&](int ii, int jj) -> T {
+        const int q = (jj >> 1) * sc + (ii >> 1);
+        return (ii & 1) ? T(0.5) * (e[q] + e[q + sc + 1]) : e[q];
+    };
+    MLS_FOR_COLOUR(L, 1, {
+        const T nb = L.wx[c - 1] * (x[c - 1] + pe(i - 1, j)) + L.wx[c] * (x[c + 1] + pe(i + 1, j))
+                   + L.wy[c - s] * (x[c - s] + pe(i, j - 1)) + L.wy[c] * (x[c + s] + pe(i, j + 1));
+        x[c] = (b[c] + nb) / diag_at(L.wx, L.wy, c, s);
+    })
+}
+
 // One V-cycle z = V r.  pre_red_done: the caller has already done the first
 // red sweep of the fine level (fused with its vector updates).  With
 // want_dot the last red sweep of the fine level also returns (r, z) over all
@@ -275,18 +311,18 @@ __device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ 
             smooth_colour<BS>(L, b, x, 1, false);
             __syncthreads();
         }
-        // residual, then its restriction (P^T of P1 interpolation); forming
-        // the residual inside the restriction loop instead was measured slower
-        MLS_FOR_INTERIOR(L, {
-            L.res[c] = b[c] - (diag_at(L.wx, L.wy, c, L.s) * x[c] - nb_sum(L.wx, L.wy, x, c, L.s));
-        })
-        __syncthreads();
+        // restriction of the residual (P^T of P1 interpolation), formed in
+        // the same pass.  The last sweep was black, and a Gauss-Seidel sweep
+        // satisfies the equations of the nodes it updates, so the black
+        // residuals vanish: of the seven fine nodes P^T gathers only the three
+        // red ones carry a residual, the coarse node itself and its two
+        // neighbours along the triangle diagonal.
         const Lv<T> C = coarse_level(M, Lk - 1);
         const int s = L.s;
-        const T* r = L.res;
+        auto res = [&](int q) { return b[q] - (diag_at(L.wx, L.wy, q, s) * x[q] - nb_sum(L.wx, L.wy, x, q, s)); };
         MLS_FOR_INTERIOR(C, {
             const int f = (2 * j) * s + 2 * i;
-            C.b[c] = r[f] + T(0.5) * (r[f - 1] + r[f + 1] + r[f - s] + r[f + s] + r[f + s + 1] + r[f - s - 1]);
+            C.b[c] = res(f) + T(0.5) * (res(f + s + 1) + res(f - s - 1));
         })
         __syncthreads();
     }
@@ -305,20 +341,9 @@ __device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ 
         const Lv<T> C = coarse_level(M, Lk - 1);
         const T* b = (Lk == l) ? rhs : L.b;
         T* x = (Lk == l) ? sol : L.x;
-        const int sc = C.s;
-        const T* xc = C.x;
-        MLS_FOR_INTERIOR(L, {
-            const int I = i >> 1, J = j >> 1;
-            T v;
-            if (!(i & 1) && !(j & 1)) v = xc[J * sc + I];
-            else if ((i & 1) && !(j & 1)) v = T(0.5) * (xc[J * sc + I] + xc[J * sc + I + 1]);
-            else if (!(i & 1) && (j & 1)) v = T(0.5) * (xc[J * sc + I] + xc[(J + 1) * sc + I]);
-            else v = T(0.5) * (xc[J * sc + I] + xc[(J + 1) * sc + I + 1]);
-            x[c] += v;
-        })
-        __syncthreads();
         for (int sw = 0; sw < nu; ++sw) {  // (black, red)^nu: the adjoint order
-            smooth_colour<BS>(L, b, x, 1, false);
+            if (sw == 0) smooth_black_corrected<BS>(L, C, b, x);  // prolongation folded in
+            else smooth_colour<BS>(L, b, x, 1, false);
             __syncthreads();
             if (Lk == l && sw == nu - 1 && want_dot) {
                 // last red sweep fused with (r, z): red nodes are updated from
@@ -418,13 +443,12 @@ __device__ void observe_and_store(const Job& J, const Common& C, const T* X, int
 }
 
 template <typename T>
-__device__ inline Lv<T> fine_level(T* slot, int l)  // slot: the fine base
+__device__ inline Lv<T> fine_level(const Map<T>& M)
 {
-    const int64_t S = pad_sz(l);
     Lv<T> F;
-    F.wx = slot + 5 * S; F.wy = slot + 6 * S; F.res = slot + 7 * S;
-    F.x = slot + 2 * S; F.b = slot + S; F.kap = nullptr;
-    F.n = 1 << l; F.lg = l; F.s = F.n + 1;
+    F.wx = fine_array(M, FWX); F.wy = fine_array(M, FWY);
+    F.x = fine_array(M, FZ); F.b = fine_array(M, FR); F.kap = nullptr;
+    F.n = 1 << M.l; F.lg = M.l; F.s = F.n + 1;
     return F;
 }
 
@@ -434,50 +458,63 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
 {
     const int l = J.l;
     const int64_t S = pad_sz(l);
-    double* fb = fine_base(M);
-    double *X = fb, *R = fb + S, *Z = fb + 2 * S, *Pv = fb + 3 * S, *Q = fb + 4 * S;
-    const Lv<double> F = fine_level(fb, l);
+    double *X = fine_array(M, FX), *R = fine_array(M, FR), *Z = fine_array(M, FZ), *Q = fine_array(M, FQ);
+    double* Pb[2] = {fine_array(M, FP), fine_array(M, FP2)};
+    const Lv<double> F = fine_level(M);
+    const int s = F.s;
     const double h2 = 1.0 / (double)(F.n * F.n);
     const double* kap = (const double*)J.kap;
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
-    zero_boundary<BS>(Pv, F.n);
+    zero_boundary<BS>(Pb[0], F.n);
+    zero_boundary<BS>(Pb[1], F.n);
     setup_hierarchy<BS>(M, F, kap);
     MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
     __syncthreads();
     vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
     double rz = 0.0;
-    MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; Pv[c] = Z[c]; })
+    MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; })
     rz = block_sum<BS>(rz, red);
     const double rz0 = rz;
     int it = 0;
     int8_t st = 1;
     if (!(rz0 > 0.0) || !isfinite(rz0)) st = 2;
+    // p_k = z_k + beta_k p_{k-1} (p_0 = z_0: beta = 0 with z as the old p)
+    const double* Po = Z;
+    double beta = 0.0;
     while (st == 1 && it < C.max_iters) {
+        double* Pn = Pb[it & 1];
+        // the p update and q = A p in one pass: the four neighbours' new p
+        // are formed from z and the old p on the fly (bitwise the values
+        // stored at those nodes), so the pass needs no barrier in between
         double pq = 0.0;
+        auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
         MLS_FOR_INTERIOR(F, {
-            const double v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
+            const double pc = pn(c);
+            const double v = diag_at(F.wx, F.wy, c, s) * pc
+                           - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
+                              + F.wy[c] * pn(c + s));
+            Pn[c] = pc;
             Q[c] = v;
-            pq += Pv[c] * v;
+            pq += pc * v;
         })
         pq = block_sum<BS>(pq, red);
         const double alpha = rz / pq;
         // x and r updates fused with the first red sweep of the V-cycle
         MLS_FOR_INTERIOR(F, {
-            X[c] += alpha * Pv[c];
+            X[c] += alpha * Pn[c];
             const double rn = R[c] - alpha * Q[c];
             R[c] = rn;
-            if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, F.s);
+            if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, s);
         })
         __syncthreads();
         const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
         ++it;
         if (!isfinite(rzn)) { st = 2; break; }
         if (rzn <= C.tol2 * rz0) { st = 0; break; }
-        const double beta = rzn / rz;
+        beta = rzn / rz;
         rz = rzn;
-        MLS_FOR_INTERIOR(F, { Pv[c] = Z[c] + beta * Pv[c]; })
-        __syncthreads();
+        Po = Pn;
     }
     observe_and_store<BS>(J, C, X, F.n, st, it, red);
 }
@@ -494,9 +531,10 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
 {
     const int l = J.l;
     const int64_t S = pad_sz(l);
-    float* fb = fine_base(M);
-    float *X = fb, *R = fb + S, *Z = fb + 2 * S, *Pv = fb + 3 * S, *Q = fb + 4 * S;
-    const Lv<float> F = fine_level(fb, l);
+    float *X = fine_array(M, FX), *R = fine_array(M, FR), *Z = fine_array(M, FZ), *Q = fine_array(M, FQ);
+    float* Pb[2] = {fine_array(M, FP), fine_array(M, FP2)};
+    const Lv<float> F = fine_level(M);
+    const int s = F.s;
     const int64_t hier = slot_elems_hd(l, false);
     double* X64 = (double*)(M.slot + ((hier + 1) & ~int64_t(1)));
     double* R64 = X64 + S;
@@ -506,7 +544,8 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
     const float* kap = (const float*)J.kap;
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
-    zero_boundary<BS>(Pv, F.n);
+    zero_boundary<BS>(Pb[0], F.n);
+    zero_boundary<BS>(Pb[1], F.n);
     zero_boundary<BS>(X64, F.n);
     setup_hierarchy<BS>(M, F, kap);
     MLS_FOR_INTERIOR(F, { X64[c] = 0.0; R64[c] = h2; })
@@ -519,7 +558,7 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         __syncthreads();
         vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
         double rz = 0.0;
-        MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; Pv[c] = Z[c]; })
+        MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; })
         rz = block_sum<BS>(rz, red);
         if (!isfinite(rz)) { st = 2; break; }
         if (outer == 0) {
@@ -530,39 +569,48 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
             break;
         }
         const double rzi0 = rz;
+        // p_k = z_k + beta_k p_{k-1}, formed inside the stencil pass as in
+        // the FP64 solver (p_0 = z_0 with beta = 0)
+        const float* Po = Z;
+        float beta = 0.f;
         for (int k = 0; k < C.max_iters; ++k) {
+            float* Pn = Pb[k & 1];
             double pq = 0.0;
+            auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
             MLS_FOR_INTERIOR(F, {
-                const float v = diag_at(F.wx, F.wy, c, F.s) * Pv[c] - nb_sum(F.wx, F.wy, Pv, c, F.s);
+                const float pc = pn(c);
+                const float v = diag_at(F.wx, F.wy, c, s) * pc
+                              - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
+                                 + F.wy[c] * pn(c + s));
+                Pn[c] = pc;
                 Q[c] = v;
-                pq += (double)Pv[c] * (double)v;
+                pq += (double)pc * (double)v;
             })
             pq = block_sum<BS>(pq, red);
             const float alpha = (float)(rz / pq);
             MLS_FOR_INTERIOR(F, {
-                X[c] += alpha * Pv[c];
+                X[c] += alpha * Pn[c];
                 const float rn = R[c] - alpha * Q[c];
                 R[c] = rn;
-                if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, F.s);
+                if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, s);
             })
             __syncthreads();
             const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
             ++it;
             if (!isfinite(rzn)) { st = 2; break; }
             if (rzn <= inner_tol2 * rzi0) break;
-            const float beta = (float)(rzn / rz);
+            beta = (float)(rzn / rz);
             rz = rzn;
-            MLS_FOR_INTERIOR(F, { Pv[c] = Z[c] + beta * Pv[c]; })
-            __syncthreads();
+            Po = Pn;
         }
         if (st == 2) break;
         // x64 += d; r64 = b - A x64 in FP64 with the FP32 weights promoted
         MLS_FOR_INTERIOR(F, { X64[c] += (double)X[c]; })
         __syncthreads();
         MLS_FOR_INTERIOR(F, {
-            const double d = (double)F.wx[c - 1] + (double)F.wx[c] + (double)F.wy[c - F.s] + (double)F.wy[c];
+            const double d = (double)F.wx[c - 1] + (double)F.wx[c] + (double)F.wy[c - s] + (double)F.wy[c];
             const double nb = (double)F.wx[c - 1] * X64[c - 1] + (double)F.wx[c] * X64[c + 1]
-                            + (double)F.wy[c - F.s] * X64[c - F.s] + (double)F.wy[c] * X64[c + F.s];
+                            + (double)F.wy[c - s] * X64[c - s] + (double)F.wy[c] * X64[c + s];
             R64[c] = h2 - (d * X64[c] - nb);
         })
         __syncthreads();
@@ -592,8 +640,13 @@ struct SolveParams {
 
 extern __shared__ __align__(16) char mls_lds[];
 
+// FP64 solver kernels: ask for registers that leave room for six waves per
+// SIMD (measured faster at h = 1/512 than the compiler's own choice, equal
+// at h = 1/64); the FP32 kernels measured best unconstrained
+#define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(MIXED ? 1 : 6)))
+
 template <int BS, bool MIXED>
-__global__ __launch_bounds__(BS) void solve_kernel(SolveParams P)
+__global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P)
 {
     __shared__ double red[BS / 64];
     const int l = P.l;
@@ -639,7 +692,7 @@ struct ListParams {
 };
 
 template <int BS, bool MIXED>
-__global__ __launch_bounds__(BS) void solve_list_kernel(ListParams P)
+__global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListParams P)
 {
     __shared__ double red[BS / 64];
     for (int64_t p = blockIdx.x; p < P.total; p += gridDim.x) {
@@ -709,7 +762,8 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
 static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* alloc_elems)
 {
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
-    const int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
+    int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
+    if (budget > ctx->max_lds) budget = ctx->max_lds;
     *alloc_elems = lds_elems_used(l, (int64_t)(budget / esz));
     return (size_t)*alloc_elems * esz;
 }

@@ -44,8 +44,9 @@ extern "C" int mls2mc_set_launch(mls2mc_ctx* ctx, int l, int grid, int block, in
                     block == 1024,
                 "set_launch: block must be 0 (auto), 64, 128, 256, 512 or 1024");
     MLS_REQUIRE(nu >= 0 && nu <= 4, "set_launch: nu must be 0 (default 1) .. 4");
-    MLS_REQUIRE(lds_bytes == -1 || (lds_bytes >= 0 && lds_bytes <= 65536),
-                "set_launch: lds_bytes must be -1 (none), 0 (default 64 KiB) or up to 65536");
+    MLS_REQUIRE(lds_bytes == -1 || (lds_bytes >= 0 && lds_bytes <= ctx->max_lds),
+                "set_launch: lds_bytes must be -1 (none), 0 (default 64 KiB) or up to the device's "
+                "LDS per workgroup less 1 KiB");
     ctx->solver_grid[l] = grid;
     ctx->solver_block[l] = block;
     ctx->solver_nu[l] = nu;
@@ -96,9 +97,22 @@ extern "C" int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_m
     if (l <= 4) { wpc = {1, 2, 4, 8, 16}; blocks = {64, 128, 256}; }
     else if (l <= 6) { wpc = {1, 2, 4, 8}; blocks = {128, 256, 512}; }
     else { wpc = {1, 2, 4}; blocks = {256, 512, 1024}; }
+    // LDS budgets: none, the default 64 KiB, 80 KiB (still two workgroups per
+    // CU on a 160 KiB LDS) and the device maximum; a budget that gives the
+    // same residency as a smaller one is skipped
+    std::vector<int> ldsc = {-1, 0};
+    {
+        const int64_t esz_ = (int64_t)esz;
+        int64_t last = solver_lds_elems_used(l, 65536 / esz_);
+        for (int b : {81920, ctx->max_lds}) {
+            if (b > ctx->max_lds || b <= 65536) continue;
+            const int64_t u = solver_lds_elems_used(l, b / esz_);
+            if (u > last) { ldsc.push_back(b); last = u; }
+        }
+    }
     float best = 1e30f;
     int bg = 0, bb = 0, bn = 1, bl = 0;
-    for (int lds : {0, -1}) {
+    for (int lds : ldsc) {
         ctx->solver_lds[l] = lds;
         for (int nu = 1; nu <= 2; ++nu) {
             ctx->solver_nu[l] = nu;
