@@ -40,21 +40,31 @@ def b_iter(nu, fp32=False):
 B_ITER_FP64 = b_iter(1)
 B_ITER_MIXED = b_iter(1, True)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "solve_h64_K50_J1000_pmc.md")
+TUNED_DEFAULT = os.path.join(ROOT, "paper_1709_09763_amd", "tuned", "mi355x_h8-64_K50_J1000.json")
 
 
-def measured_traffic():
-    """HBM bytes per solver launch from the committed rocprofv3 counter
-    summary, or None once the solver source differs from the one measured"""
+def solver_sha():
+    """first 16 hex digits of sha256 over the solver's sources"""
     import hashlib
+    h = hashlib.sha256()
+    for f in ("solver.hip", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1709_09763_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(shape):
+    """HBM bytes per solver launch from the committed rocprofv3 counter
+    summary, or None once the solver source or the launch shape
+    (grid, block, nu, lds) differs from the one measured"""
     try:
         txt = open(PMC_SUMMARY).read()
     except OSError:
         return None
-    vals = dict(ln.split(":", 1) for ln in txt.splitlines() if ln.startswith(("traffic_bytes", "solver_source")))
-    h = hashlib.sha256()
-    for f in ("solver.hip", "common.h"):
-        h.update(open(os.path.join(ROOT, "paper_1709_09763_amd", "csrc", f), "rb").read())
-    if vals.get("solver_source_sha256_16", "").strip() != h.hexdigest()[:16]:
+    vals = dict(ln.split(":", 1) for ln in txt.splitlines()
+                if ln.startswith(("traffic_bytes", "solver_source", "launch_shape")))
+    if vals.get("solver_source_sha256_16", "").strip() != solver_sha():
+        return None
+    if vals.get("launch_shape", "").strip() != ",".join(str(v) for v in shape):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -313,6 +323,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip per-level and time-to-posterior")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune even when the committed shapes match this device and solver")
     ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
     ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest", "largest-run"],
@@ -350,23 +362,38 @@ def main():
     y = y.contiguous()
 
     extras = {}
-    shapes = {}
-    if args.tuned:
-        shapes = {int(k): v for k, v in json.load(open(args.tuned))["fp64"].items()}
-        for lv, sh in shapes.items():
-            ctx.set_launch(lv, sh["grid"], sh["block"], sh.get("nu", 0), sh.get("lds", 0))
+    shapes, shapes_m = {}, {}
+    tuned_file = args.tuned
+    if tuned_file is None and not args.retune and not args.no_autotune and os.path.exists(TUNED_DEFAULT):
+        rec = json.load(open(TUNED_DEFAULT))
+        if rec.get("device") == torch.cuda.get_device_name(0) and rec.get("solver_source_sha256_16") == solver_sha():
+            tuned_file = TUNED_DEFAULT  # the committed shapes were tuned on this device for this solver
+    ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
+    if tuned_file:
+        rec = json.load(open(tuned_file))
+        shapes = {int(k): v for k, v in rec["fp64"].items()}
+        shapes_m = {int(k): v for k, v in rec.get("mixed", {}).items()}
+        for c, sh_ in ((ctx, shapes), (ctxm, shapes_m)):
+            for lv, sh in sh_.items():
+                c.set_launch(lv, sh["grid"], sh["block"], sh.get("nu", 0), sh.get("lds", 0))
         extras["solver_launch"] = {f"h=1/{1 << lv}": sh for lv, sh in shapes.items()}
+        extras["solver_launch_source"] = os.path.relpath(tuned_file, ROOT)
+        log(f"solver launch shapes from {tuned_file}")
     elif not args.no_autotune:
         tuned = {}
-        for lv in range(W["l_min"], W["l_max"] + 1):
-            ms, (g, b, nu, lds) = ctx.autotune(lv, J)
-            shapes[lv] = dict(grid=g, block=b, nu=nu, lds=lds)
-            tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, lds=lds, ms=round(ms, 4))
+        for c, sh_, key in ((ctx, shapes, "fp64"), (ctxm, shapes_m, "mixed")):
+            for lv in range(W["l_min"], W["l_max"] + 1):
+                ms, (g, b, nu, lds) = c.autotune(lv, J)
+                sh_[lv] = dict(grid=g, block=b, nu=nu, lds=lds)
+                if key == "fp64":
+                    tuned[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, lds=lds, ms=round(ms, 4))
         extras["autotuned_solver_launch"] = tuned
         log(f"autotuned {tuned}")
         if args.save_tuned:
             json.dump({"device": torch.cuda.get_device_name(0), "workload": W["name"],
-                       "fp64": {str(k): v for k, v in shapes.items()}}, open(args.save_tuned, "w"), indent=1)
+                       "solver_source_sha256_16": solver_sha(),
+                       "fp64": {str(k): v for k, v in shapes.items()},
+                       "mixed": {str(k): v for k, v in shapes_m.items()}}, open(args.save_tuned, "w"), indent=1)
     if not args.no_extras:
         # time-to-posterior, plain FP64 (one untimed warm run first)
         ctx.run(y, 200, seed=1)
@@ -378,10 +405,6 @@ def main():
                                   log_Z=r["log_Z"], mean_pcg_iters=r["iters_total"] / max(1, sum(r["solves"])),
                                   accept_rate=r["accepted"] / max(1, r["proposed"]))
         log(f"time-to-posterior fp64 {r['seconds']:.3f}s stages {r['n_stages']}")
-        ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
-        if not args.no_autotune and not args.tuned:
-            for lv in range(W["l_min"], W["l_max"] + 1):
-                ctxm.autotune(lv, J)
         ctxm.run(y, 200, seed=1)
         rm = ctxm.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=11)
         extras["time_to_posterior_mixed_s"] = round(rm["seconds"], 4)
@@ -390,7 +413,6 @@ def main():
                                    posterior_mean_rel_diff_vs_fp64=float(
                                        np.abs(thm.mean(0) - thp.mean(0)).sum() / np.abs(thp.mean(0)).sum()))
         log(f"time-to-posterior mixed {rm['seconds']:.3f}s")
-        ctxm.close()
         # per-level throughput of plain forward batches (J particles)
         per = {}
         th = torch.tensor(rng.standard_normal((J, K)), device=dev)
@@ -455,7 +477,7 @@ def main():
     extras["kl_gemm"] = dict(launches=pg["launches"], avg_ms=round(pg["ms"] / max(1, pg["launches"]), 4),
                              tflops=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12, 3),
                              frac_of_fp64_peak=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12 / FP64_PEAK_TFLOPS, 4))
-    traffic = measured_traffic()
+    traffic = measured_traffic(ctx.get_launch(l))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(l, K, m, W["corr"])
@@ -475,7 +497,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "algorithmic_bytes_per_launch": round(alg / max(1, ps["launches"]), 0),
-                     "kernel": "solve_kernel (h=1/64, FP64)", "vcycle_nu": nu_l},
+                     "kernel": "solve_kernel (h=1/64, FP64)", "launch_shape": list(ctx.get_launch(l))},
         "cpu_baseline": cpu,
         **extras,
     }
