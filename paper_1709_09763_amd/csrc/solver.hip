@@ -246,10 +246,22 @@ template <int BS, typename T>
 __device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __restrict__ x, int col,
                               bool first)
 {
-    if (first) {  // the other colour is still zero
-        MLS_FOR_COLOUR(L, col, { x[c] = b[c] / diag_at(L.wx, L.wy, c, L.s); })
+    // Each thread also stores its east neighbour (the other colour, value
+    // unchanged), so the stores of a wave cover whole lines: a store of
+    // every other double costs more than a full one.
+    const int s = L.s;
+    if (first) {  // the other colour is taken as zero
+        MLS_FOR_COLOUR(L, col, {
+            x[c] = b[c] / diag_at(L.wx, L.wy, c, s);
+            x[c + 1] = T(0);
+        })
     } else {
-        MLS_FOR_COLOUR(L, col, { x[c] = (b[c] + nb_sum(L.wx, L.wy, x, c, L.s)) / diag_at(L.wx, L.wy, c, L.s); })
+        MLS_FOR_COLOUR(L, col, {
+            const T xe = x[c + 1];
+            const T nb = L.wx[c - 1] * x[c - 1] + L.wx[c] * xe + L.wy[c - s] * x[c - s] + L.wy[c] * x[c + s];
+            x[c] = (b[c] + nb) / diag_at(L.wx, L.wy, c, s);
+            x[c + 1] = xe;
+        })
     }
 }
 
@@ -270,9 +282,11 @@ __device__ void smooth_black_corrected(const Lv<T>& L, const Lv<T>& C, const T* 
         return (ii & 1) ? T(0.5) * (e[q] + e[q + sc + 1]) : e[q];
     };
     MLS_FOR_COLOUR(L, 1, {
-        const T nb = L.wx[c - 1] * (x[c - 1] + pe(i - 1, j)) + L.wx[c] * (x[c + 1] + pe(i + 1, j))
+        const T xe = x[c + 1];
+        const T nb = L.wx[c - 1] * (x[c - 1] + pe(i - 1, j)) + L.wx[c] * (xe + pe(i + 1, j))
                    + L.wy[c - s] * (x[c - s] + pe(i, j - 1)) + L.wy[c] * (x[c + s] + pe(i, j + 1));
         x[c] = (b[c] + nb) / diag_at(L.wx, L.wy, c, s);
+        x[c + 1] = xe;  // whole-line stores, as in smooth_colour (the red values are dead here)
     })
 }
 
@@ -353,10 +367,10 @@ __device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ 
                     T z;
                     if (((i + j) & 1) == 0) {
                         z = (b[c] + nb_sum(L.wx, L.wy, x, c, L.s)) / diag_at(L.wx, L.wy, c, L.s);
-                        x[c] = z;
                     } else {
                         z = x[c];
                     }
+                    x[c] = z;  // black nodes store their own value: whole-line stores
                     d += (double)b[c] * (double)z;
                 })
                 dot = block_sum<BS>(d, red);  // includes the barrier
@@ -505,7 +519,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
             X[c] += alpha * Pn[c];
             const double rn = R[c] - alpha * Q[c];
             R[c] = rn;
-            if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, s);
+            Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.0;  // black: taken as zero
         })
         __syncthreads();
         const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
@@ -592,7 +606,7 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
                 X[c] += alpha * Pn[c];
                 const float rn = R[c] - alpha * Q[c];
                 R[c] = rn;
-                if (((i + j) & 1) == 0) Z[c] = rn / diag_at(F.wx, F.wy, c, s);
+                Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.f;  // black: taken as zero
             })
             __syncthreads();
             const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
