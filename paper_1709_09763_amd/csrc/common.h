@@ -65,7 +65,7 @@ inline int64_t n_pad(int l) { return (n_side(l) + 1) * (n_side(l) + 1); }
 // Per-particle solver workspace (elements of the working type), see solver.hip.
 int64_t solver_slot_elems(int l, bool mixed);
 // LDS elements the solver's residency policy uses at level l for a budget
-int64_t solver_lds_elems_used(int l, int64_t budget_elems);
+int64_t solver_lds_elems_used(int l, bool mixed, int64_t budget_elems);
 
 // ------------------------------------------------------- observation --
 // Three nodes (padded-grid offsets) and barycentric weights per observation.

@@ -37,46 +37,79 @@ namespace mls {
 // wx[j][i]: weight of edge (i,j)-(i+1,j); wy[j][i]: edge (i,j)-(i,j+1).
 // Slot layout (elements of T):
 //   fine level l:   X R Z P Q WX WY P2               8 S_l
+//                   FP64 solver only: FP32 copies of WX WY for the
+//                   V-cycle                          2 ceil(S_l / 2)
 //   coarse L<l:     WX WY XC BC                      4 S_L    then
 //                   KAP (per-triangle kappa)         2 n_L^2
+//   mixed solver:   FP64 X and R after the hierarchy (see solve_one_mixed)
+// The FP64 solver preconditions with a V-cycle whose finest-level weights
+// are the FP32-rounded edge weights: the preconditioner only has to be a
+// fixed symmetric positive definite operator close to A, and the stencil
+// apply and the residual of CG keep the FP64 weights, so the iterates still
+// converge to the FP64 system's solution.  The V-cycle then reads half the
+// weight bytes per pass.
+enum { FX = 0, FR, FZ, FP, FQ, FWX, FWY, FP2, FWX32, FWY32 };  // fine arrays
 __host__ __device__ inline int64_t pad_sz(int L) { return ((int64_t(1) << L) + 1) * ((int64_t(1) << L) + 1); }
+__host__ __device__ inline int64_t half_sz(int L) { return (pad_sz(L) + 1) / 2; }  // FP32 grid in FP64 elements
 __host__ __device__ inline int64_t coarse_sz(int L) { return 4 * pad_sz(L) + 2 * (int64_t(1) << (2 * L)); }
+__host__ __device__ inline int64_t fine_sz(int l, bool split) { return 8 * pad_sz(l) + (split ? 2 * half_sz(l) : 0); }
 
-__host__ __device__ inline int64_t coarse_off(int l, int L)
+__host__ __device__ inline int64_t coarse_off(int l, int L, bool split)
 {
-    int64_t o = 8 * pad_sz(l);
+    int64_t o = fine_sz(l, split);
     for (int k = l - 1; k > L; --k) o += coarse_sz(k);
+    return o;
+}
+
+// fine level and coarse hierarchy
+__host__ __device__ inline int64_t hier_elems(int l, bool mixed)
+{
+    int64_t o = fine_sz(l, !mixed);
+    for (int k = l - 1; k >= 1; --k) o += coarse_sz(k);
     return o;
 }
 
 __host__ __device__ inline int64_t slot_elems_hd(int l, bool mixed)
 {
-    int64_t o = 8 * pad_sz(l);
-    for (int k = l - 1; k >= 1; --k) o += coarse_sz(k);
-    if (mixed) o += 4 * pad_sz(l) + 2;  // float slot: + FP64 X64 and R64 (2 floats each)
-    return o;
+    // float slot: + FP64 X64 and R64 (2 floats each) after an even offset
+    return hier_elems(l, mixed) + (mixed ? 4 * pad_sz(l) + 2 : 0);
 }
 
 int64_t solver_slot_elems(int l, bool mixed) { return slot_elems_hd(l, mixed); }
 
-template <typename T>
+template <typename T, typename W = T>
 struct Lv {
-    T *wx, *wy, *x, *b, *kap;
+    W *wx, *wy;
+    T *x, *b, *kap;
     int n, lg, s;
 };
 
 // Where a particle's arrays live.  Coarse levels L <= lds_top keep their
 // four work arrays (WX WY XC BC) in LDS, finest of them first; after them
 // come the first fine_n of the fine level's arrays in the order of how many
-// passes of a PCG iteration touch them: WX WY (read by every pass), Z and R
-// (the V-cycle's unknown and right-hand side), the two search-direction
-// buffers, Q, X.  The per-triangle coefficients of coarse levels (setup
-// only) and every other array stay in the global slot.
-enum { FX = 0, FR, FZ, FP, FQ, FWX, FWY, FP2 };  // slot order of the fine arrays
-__host__ __device__ inline int fine_rank(int k)   // LDS priority of slot array k
+// passes of a PCG iteration touch them: the V-cycle's weights (read by five
+// passes; the FP32 copies in the FP64 solver), Z and R (the V-cycle's
+// unknown and right-hand side), the two search-direction buffers, Q, X, and
+// last the FP64 weights of the FP64 solver (read by the stencil pass only).
+// The per-triangle coefficients of coarse levels (setup only) and every
+// other array stay in the global slot.
+__host__ __device__ inline int fine_rank(int k, bool split)  // LDS priority of fine array k
 {
-    // X R Z P Q WX WY P2 -> 7 3 2 4 6 0 1 5
-    return (int)((0x51064237u >> (4 * k)) & 0xfu);
+    // X R Z P Q WX WY P2 WX32 WY32 -> split: 7 3 2 4 6 8 9 5 0 1; else 7 3 2 4 6 0 1 5
+    const uint64_t t = split ? 0x1059864237ull : 0x51064237ull;
+    return (int)((t >> (4 * k)) & 0xfu);
+}
+__host__ __device__ inline int fine_count(bool split) { return split ? 10 : 8; }
+// elements before rank r in the LDS order
+__host__ __device__ inline int64_t fine_prefix(int l, bool split, int r)
+{
+    if (!split) return r * pad_sz(l);
+    return r <= 2 ? r * half_sz(l) : 2 * half_sz(l) + (r - 2) * pad_sz(l);
+}
+// offset of fine array k in the global slot
+__host__ __device__ inline int64_t fine_slot_off(int l, int k)
+{
+    return k < FWX32 ? k * pad_sz(l) : 8 * pad_sz(l) + (k - FWX32) * half_sz(l);
 }
 
 template <typename T>
@@ -99,7 +132,7 @@ __host__ __device__ inline int64_t lds_coarse_elems(int top)
 // whose hierarchy fits, then as many fine arrays as fit in what is left.
 // Never uses more than the budget, and applied to its own usage it returns
 // the same residency (so a launch may pass the usage as the budget).
-__host__ __device__ inline void lds_policy(int l, int64_t budget, int* top, int* fine_n)
+__host__ __device__ inline void lds_policy(int l, bool split, int64_t budget, int* top, int* fine_n)
 {
     *fine_n = 0;
     *top = 0;
@@ -107,18 +140,22 @@ __host__ __device__ inline void lds_policy(int l, int64_t budget, int* top, int*
     for (int t = l - 1; t >= 1; --t)
         if (lds_coarse_elems(t) <= budget) { *top = t; break; }
     const int64_t rem = budget - lds_coarse_elems(*top);
-    const int64_t nf = rem / pad_sz(l);
-    *fine_n = (int)(nf < 8 ? nf : 8);
+    int n = 0;
+    while (n < fine_count(split) && fine_prefix(l, split, n + 1) <= rem) ++n;
+    *fine_n = n;
 }
 
-__host__ __device__ inline int64_t lds_elems_used(int l, int64_t budget)
+__host__ __device__ inline int64_t lds_elems_used(int l, bool split, int64_t budget)
 {
     int top, fine_n;
-    lds_policy(l, budget, &top, &fine_n);
-    return lds_coarse_elems(top) + fine_n * pad_sz(l);
+    lds_policy(l, split, budget, &top, &fine_n);
+    return lds_coarse_elems(top) + fine_prefix(l, split, fine_n);
 }
 
-int64_t solver_lds_elems_used(int l, int64_t budget_elems) { return lds_elems_used(l, budget_elems); }
+int64_t solver_lds_elems_used(int l, bool mixed, int64_t budget_elems)
+{
+    return lds_elems_used(l, !mixed, budget_elems);
+}
 
 template <typename T>
 __device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems)
@@ -127,7 +164,7 @@ __device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_ele
     M.slot = slot;
     M.lds = lds;
     M.l = l;
-    lds_policy(l, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_n);
+    lds_policy(l, sizeof(T) == 8, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_n);
     return M;
 }
 
@@ -135,7 +172,7 @@ template <typename T>
 __device__ inline Lv<T> coarse_level(const Map<T>& M, int L)
 {
     Lv<T> v;
-    T* g = M.slot + coarse_off(M.l, L);
+    T* g = M.slot + coarse_off(M.l, L, sizeof(T) == 8);
     const int64_t S = pad_sz(L);
     T* base = (L <= M.lds_top) ? M.lds + (lds_coarse_elems(M.lds_top) - lds_coarse_elems(L)) : g;
     v.wx = base; v.wy = base + S; v.x = base + 2 * S; v.b = base + 3 * S;
@@ -144,13 +181,14 @@ __device__ inline Lv<T> coarse_level(const Map<T>& M, int L)
     return v;
 }
 
-// fine array k (FX .. FP2) of the particle
+// fine array k (FX .. FWY32) of the particle, in elements of T
 template <typename T>
 __device__ inline T* fine_array(const Map<T>& M, int k)
 {
-    const int64_t S = pad_sz(M.l);
-    const int r = fine_rank(k);
-    return r < M.fine_n ? M.lds + lds_coarse_elems(M.lds_top) + r * S : M.slot + k * S;
+    const bool split = sizeof(T) == 8;
+    const int r = fine_rank(k, split);
+    return r < M.fine_n ? M.lds + lds_coarse_elems(M.lds_top) + fine_prefix(M.l, split, r)
+                        : M.slot + fine_slot_off(M.l, k);
 }
 
 // ----------------------------------------------------------- stencils --
@@ -165,6 +203,21 @@ __device__ __forceinline__ T nb_sum(const T* __restrict__ wx, const T* __restric
                                     const T* __restrict__ x, int c, int s)
 {
     return wx[c - 1] * x[c - 1] + wx[c] * x[c + 1] + wy[c - s] * x[c - s] + wy[c] * x[c + s];
+}
+
+// the same on a level whose weights may be stored in a narrower type W
+// (converted exactly to T before use)
+template <typename T, typename W>
+__device__ __forceinline__ T ldiag(const Lv<T, W>& L, int c)
+{
+    return T(L.wx[c - 1]) + T(L.wx[c]) + T(L.wy[c - L.s]) + T(L.wy[c]);
+}
+
+template <typename T, typename W>
+__device__ __forceinline__ T lnb(const Lv<T, W>& L, const T* __restrict__ x, int c)
+{
+    return T(L.wx[c - 1]) * x[c - 1] + T(L.wx[c]) * x[c + 1] + T(L.wy[c - L.s]) * x[c - L.s]
+         + T(L.wy[c]) * x[c + L.s];
 }
 
 // loops over interior nodes: t in [0, (n-1) n), i = t mod n (skip 0)
@@ -202,7 +255,7 @@ __device__ void zero_boundary(T* a, int n)
 // 2(jn+i) is the lower, 2(jn+i)+1 the upper triangle of cell (i,j)
 template <int BS, typename T, typename KT>
 __device__ void edge_weights(const KT* __restrict__ kap, T* __restrict__ wx, T* __restrict__ wy,
-                             int n, int lg)
+                             int n, int lg, float* __restrict__ wx32 = nullptr, float* __restrict__ wy32 = nullptr)
 {
     const int s = n + 1;
     for (int t = threadIdx.x; t < s * s; t += BS) {
@@ -220,6 +273,10 @@ __device__ void edge_weights(const KT* __restrict__ kap, T* __restrict__ wx, T* 
         }
         wx[t] = vx;
         wy[t] = vy;
+        if (wx32) {  // FP32-rounded copies for the V-cycle of the FP64 solver
+            wx32[t] = (float)vx;
+            wy32[t] = (float)vy;
+        }
     }
 }
 
@@ -242,8 +299,8 @@ __device__ void coarsen_kappa(const KT* __restrict__ kf, T* __restrict__ kc, int
 }
 
 // ------------------------------------------------------------ V-cycle --
-template <int BS, typename T>
-__device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __restrict__ x, int col,
+template <int BS, typename T, typename W>
+__device__ void smooth_colour(const Lv<T, W>& L, const T* __restrict__ b, T* __restrict__ x, int col,
                               bool first)
 {
     // Each thread also stores its east neighbour (the other colour, value
@@ -252,14 +309,15 @@ __device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __rest
     const int s = L.s;
     if (first) {  // the other colour is taken as zero
         MLS_FOR_COLOUR(L, col, {
-            x[c] = b[c] / diag_at(L.wx, L.wy, c, s);
+            x[c] = b[c] / ldiag(L, c);
             x[c + 1] = T(0);
         })
     } else {
         MLS_FOR_COLOUR(L, col, {
             const T xe = x[c + 1];
-            const T nb = L.wx[c - 1] * x[c - 1] + L.wx[c] * xe + L.wy[c - s] * x[c - s] + L.wy[c] * x[c + s];
-            x[c] = (b[c] + nb) / diag_at(L.wx, L.wy, c, s);
+            const T nb = T(L.wx[c - 1]) * x[c - 1] + T(L.wx[c]) * xe + T(L.wy[c - s]) * x[c - s]
+                       + T(L.wy[c]) * x[c + s];
+            x[c] = (b[c] + nb) / ldiag(L, c);
             x[c + 1] = xe;
         })
     }
@@ -271,8 +329,8 @@ __device__ void smooth_colour(const Lv<T>& L, const T* __restrict__ b, T* __rest
 // is interpolated at the neighbours on the fly and never stored.  At a red
 // node (i', j') both indices are even (the coarse node itself) or both odd
 // (the middle of a coarse diagonal edge, from (i'-1, j'-1) to (i'+1, j'+1)).
-template <int BS, typename T>
-__device__ void smooth_black_corrected(const Lv<T>& L, const Lv<T>& C, const T* __restrict__ b,
+template <int BS, typename T, typename W>
+__device__ void smooth_black_corrected(const Lv<T, W>& L, const Lv<T>& C, const T* __restrict__ b,
                                        T* __restrict__ x)
 {
     const int s = L.s, sc = C.s;
@@ -283,26 +341,89 @@ __device__ void smooth_black_corrected(const Lv<T>& L, const Lv<T>& C, const T* 
     };
     MLS_FOR_COLOUR(L, 1, {
         const T xe = x[c + 1];
-        const T nb = L.wx[c - 1] * (x[c - 1] + pe(i - 1, j)) + L.wx[c] * (xe + pe(i + 1, j))
-                   + L.wy[c - s] * (x[c - s] + pe(i, j - 1)) + L.wy[c] * (x[c + s] + pe(i, j + 1));
-        x[c] = (b[c] + nb) / diag_at(L.wx, L.wy, c, s);
+        const T nb = T(L.wx[c - 1]) * (x[c - 1] + pe(i - 1, j)) + T(L.wx[c]) * (xe + pe(i + 1, j))
+                   + T(L.wy[c - s]) * (x[c - s] + pe(i, j - 1)) + T(L.wy[c]) * (x[c + s] + pe(i, j + 1));
+        x[c] = (b[c] + nb) / ldiag(L, c);
         x[c + 1] = xe;  // whole-line stores, as in smooth_colour (the red values are dead here)
     })
 }
 
-// One V-cycle z = V r.  pre_red_done: the caller has already done the first
-// red sweep of the fine level (fused with its vector updates).  With
-// want_dot the last red sweep of the fine level also returns (r, z) over all
-// interior nodes (black values are final there, so the pass can read them).
-template <int BS, typename T>
-__device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ rhs, T* __restrict__ sol,
+// Down-leg on level L: (red, black)^nu, then the restriction of the residual
+// into the coarser level's right-hand side C.b.  pre_red_done: the caller
+// has already done the first red sweep (fused with its vector updates).
+template <int BS, typename T, typename W>
+__device__ void down_step(const Lv<T, W>& L, const Lv<T>& C, const T* __restrict__ b, T* __restrict__ x,
+                          int nu, bool pre_red_done)
+{
+    for (int sw = 0; sw < nu; ++sw) {
+        if (!(sw == 0 && pre_red_done)) {
+            smooth_colour<BS>(L, b, x, 0, sw == 0);
+            __syncthreads();
+        }
+        smooth_colour<BS>(L, b, x, 1, false);
+        __syncthreads();
+    }
+    // restriction of the residual (P^T of P1 interpolation), formed in the
+    // same pass.  The last sweep was black, and a Gauss-Seidel sweep
+    // satisfies the equations of the nodes it updates, so the black
+    // residuals vanish: of the seven fine nodes P^T gathers only the three
+    // red ones carry a residual, the coarse node itself and its two
+    // neighbours along the triangle diagonal.
+    const int s = L.s;
+    auto res = [&](int q) { return b[q] - (ldiag(L, q) * x[q] - lnb(L, x, q)); };
+    MLS_FOR_INTERIOR(C, {
+        const int f = (2 * j) * s + 2 * i;
+        C.b[c] = res(f) + T(0.5) * (res(f + s + 1) + res(f - s - 1));
+    })
+    __syncthreads();
+}
+
+// Up-leg on level L after the coarser level C was solved: (black, red)^nu
+// with the coarse correction folded into the first black sweep.  With
+// want_dot the last red sweep also returns (b, x) over all interior nodes
+// (black values are final there, so the pass can read them).
+template <int BS, typename T, typename W>
+__device__ double up_step(const Lv<T, W>& L, const Lv<T>& C, const T* __restrict__ b, T* __restrict__ x,
+                          int nu, bool want_dot, double* red)
+{
+    double dot = 0.0;
+    for (int sw = 0; sw < nu; ++sw) {
+        if (sw == 0) smooth_black_corrected<BS>(L, C, b, x);
+        else smooth_colour<BS>(L, b, x, 1, false);
+        __syncthreads();
+        if (sw == nu - 1 && want_dot) {
+            double d = 0.0;
+            MLS_FOR_INTERIOR(L, {
+                T z;
+                if (((i + j) & 1) == 0) {
+                    z = (b[c] + lnb(L, x, c)) / ldiag(L, c);
+                } else {
+                    z = x[c];
+                }
+                x[c] = z;  // black nodes store their own value: whole-line stores
+                d += (double)b[c] * (double)z;
+            })
+            dot = block_sum<BS>(d, red);  // includes the barrier
+        } else {
+            smooth_colour<BS>(L, b, x, 0, false);
+            __syncthreads();
+        }
+    }
+    return dot;
+}
+
+// One V-cycle z = V r on the hierarchy of M whose finest level is F (its
+// weights of type W).  See down_step and up_step for pre_red_done and
+// want_dot.
+template <int BS, typename T, typename W>
+__device__ double vcycle(const Map<T>& M, const Lv<T, W>& F, const T* __restrict__ rhs, T* __restrict__ sol,
                          int nu, bool pre_red_done, bool want_dot, double* red)
 {
     const int l = M.l;
     if (l == 1) {  // the fine level is the coarsest: one unknown, exact
         if (threadIdx.x == 0) {
             const int c = F.s + 1;
-            sol[c] = T((double)rhs[c] / (double)diag_at(F.wx, F.wy, c, F.s));
+            sol[c] = T((double)rhs[c] / (double)ldiag(F, c));
         }
         __syncthreads();
         double d = 0.0;
@@ -312,33 +433,10 @@ __device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ 
         }
         return d;
     }
-    // down
-    for (int Lk = l; Lk >= 2; --Lk) {
-        const Lv<T> L = (Lk == l) ? F : coarse_level(M, Lk);
-        const T* b = (Lk == l) ? rhs : L.b;
-        T* x = (Lk == l) ? sol : L.x;
-        for (int sw = 0; sw < nu; ++sw) {  // (red, black)^nu
-            if (!(sw == 0 && Lk == l && pre_red_done)) {
-                smooth_colour<BS>(L, b, x, 0, sw == 0);
-                __syncthreads();
-            }
-            smooth_colour<BS>(L, b, x, 1, false);
-            __syncthreads();
-        }
-        // restriction of the residual (P^T of P1 interpolation), formed in
-        // the same pass.  The last sweep was black, and a Gauss-Seidel sweep
-        // satisfies the equations of the nodes it updates, so the black
-        // residuals vanish: of the seven fine nodes P^T gathers only the three
-        // red ones carry a residual, the coarse node itself and its two
-        // neighbours along the triangle diagonal.
-        const Lv<T> C = coarse_level(M, Lk - 1);
-        const int s = L.s;
-        auto res = [&](int q) { return b[q] - (diag_at(L.wx, L.wy, q, s) * x[q] - nb_sum(L.wx, L.wy, x, q, s)); };
-        MLS_FOR_INTERIOR(C, {
-            const int f = (2 * j) * s + 2 * i;
-            C.b[c] = res(f) + T(0.5) * (res(f + s + 1) + res(f - s - 1));
-        })
-        __syncthreads();
+    down_step<BS>(F, coarse_level(M, l - 1), rhs, sol, nu, pre_red_done);
+    for (int Lk = l - 1; Lk >= 2; --Lk) {
+        const Lv<T> L = coarse_level(M, Lk);
+        down_step<BS>(L, coarse_level(M, Lk - 1), L.b, L.x, nu, false);
     }
     {  // coarsest level, one unknown at (1,1)
         const Lv<T> C = coarse_level(M, 1);
@@ -348,47 +446,20 @@ __device__ double vcycle(const Map<T>& M, const Lv<T>& F, const T* __restrict__ 
         }
         __syncthreads();
     }
-    // up
-    double dot = 0.0;
-    for (int Lk = 2; Lk <= l; ++Lk) {
-        const Lv<T> L = (Lk == l) ? F : coarse_level(M, Lk);
-        const Lv<T> C = coarse_level(M, Lk - 1);
-        const T* b = (Lk == l) ? rhs : L.b;
-        T* x = (Lk == l) ? sol : L.x;
-        for (int sw = 0; sw < nu; ++sw) {  // (black, red)^nu: the adjoint order
-            if (sw == 0) smooth_black_corrected<BS>(L, C, b, x);  // prolongation folded in
-            else smooth_colour<BS>(L, b, x, 1, false);
-            __syncthreads();
-            if (Lk == l && sw == nu - 1 && want_dot) {
-                // last red sweep fused with (r, z): red nodes are updated from
-                // their black neighbours, black nodes are final
-                double d = 0.0;
-                MLS_FOR_INTERIOR(L, {
-                    T z;
-                    if (((i + j) & 1) == 0) {
-                        z = (b[c] + nb_sum(L.wx, L.wy, x, c, L.s)) / diag_at(L.wx, L.wy, c, L.s);
-                    } else {
-                        z = x[c];
-                    }
-                    x[c] = z;  // black nodes store their own value: whole-line stores
-                    d += (double)b[c] * (double)z;
-                })
-                dot = block_sum<BS>(d, red);  // includes the barrier
-            } else {
-                smooth_colour<BS>(L, b, x, 0, false);
-                __syncthreads();
-            }
-        }
+    for (int Lk = 2; Lk <= l - 1; ++Lk) {
+        const Lv<T> L = coarse_level(M, Lk);
+        up_step<BS>(L, coarse_level(M, Lk - 1), L.b, L.x, nu, false, red);
     }
-    return dot;
+    return up_step<BS>(F, coarse_level(M, l - 1), rhs, sol, nu, want_dot, red);
 }
 
 // ------------------------------------------------------- setup & obs --
 template <int BS, typename T, typename KT>
-__device__ void setup_hierarchy(const Map<T>& M, const Lv<T>& F, const KT* __restrict__ kap)
+__device__ void setup_hierarchy(const Map<T>& M, const Lv<T>& F, const KT* __restrict__ kap,
+                                float* wx32 = nullptr, float* wy32 = nullptr)
 {
     const int l = M.l;
-    edge_weights<BS>(kap, F.wx, F.wy, F.n, F.lg);
+    edge_weights<BS>(kap, F.wx, F.wy, F.n, F.lg, wx32, wy32);
     if (l >= 2) {
         Lv<T> C = coarse_level(M, l - 1);
         coarsen_kappa<BS>(kap, C.kap, l - 1);
@@ -474,7 +545,12 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
     const int64_t S = pad_sz(l);
     double *X = fine_array(M, FX), *R = fine_array(M, FR), *Z = fine_array(M, FZ), *Q = fine_array(M, FQ);
     double* Pb[2] = {fine_array(M, FP), fine_array(M, FP2)};
-    const Lv<double> F = fine_level(M);
+    const Lv<double> F = fine_level(M);  // FP64 weights: stencil apply of CG
+    Lv<double, float> FV;                // FP32 weights: the V-cycle
+    FV.wx = reinterpret_cast<float*>(fine_array(M, FWX32));
+    FV.wy = reinterpret_cast<float*>(fine_array(M, FWY32));
+    FV.x = Z; FV.b = R; FV.kap = nullptr;
+    FV.n = F.n; FV.lg = F.lg; FV.s = F.s;
     const int s = F.s;
     const double h2 = 1.0 / (double)(F.n * F.n);
     const double* kap = (const double*)J.kap;
@@ -482,10 +558,10 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
     zero_boundary<BS>(Z, F.n);
     zero_boundary<BS>(Pb[0], F.n);
     zero_boundary<BS>(Pb[1], F.n);
-    setup_hierarchy<BS>(M, F, kap);
+    setup_hierarchy<BS>(M, F, kap, FV.wx, FV.wy);
     MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
     __syncthreads();
-    vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
+    vcycle<BS>(M, FV, R, Z, C.nu, false, false, red);
     double rz = 0.0;
     MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; })
     rz = block_sum<BS>(rz, red);
@@ -519,10 +595,10 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
             X[c] += alpha * Pn[c];
             const double rn = R[c] - alpha * Q[c];
             R[c] = rn;
-            Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.0;  // black: taken as zero
+            Z[c] = (((i + j) & 1) == 0) ? rn / ldiag(FV, c) : 0.0;  // black: taken as zero
         })
         __syncthreads();
-        const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
+        const double rzn = vcycle<BS>(M, FV, R, Z, C.nu, l > 1, true, red);
         ++it;
         if (!isfinite(rzn)) { st = 2; break; }
         if (rzn <= C.tol2 * rz0) { st = 0; break; }
@@ -549,7 +625,7 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
     float* Pb[2] = {fine_array(M, FP), fine_array(M, FP2)};
     const Lv<float> F = fine_level(M);
     const int s = F.s;
-    const int64_t hier = slot_elems_hd(l, false);
+    const int64_t hier = hier_elems(l, true);
     double* X64 = (double*)(M.slot + ((hier + 1) & ~int64_t(1)));
     double* R64 = X64 + S;
     const double h2 = 1.0 / (double)(F.n * F.n);
@@ -778,7 +854,7 @@ static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* a
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
     if (budget > ctx->max_lds) budget = ctx->max_lds;
-    *alloc_elems = lds_elems_used(l, (int64_t)(budget / esz));
+    *alloc_elems = lds_elems_used(l, !mixed, (int64_t)(budget / esz));
     return (size_t)*alloc_elems * esz;
 }
 

@@ -103,10 +103,10 @@ extern "C" int mls2mc_autotune(mls2mc_ctx* ctx, int l, int64_t N, double* best_m
     std::vector<int> ldsc = {-1, 0};
     {
         const int64_t esz_ = (int64_t)esz;
-        int64_t last = solver_lds_elems_used(l, 65536 / esz_);
+        int64_t last = solver_lds_elems_used(l, mixed, 65536 / esz_);
         for (int b : {81920, ctx->max_lds}) {
             if (b > ctx->max_lds || b <= 65536) continue;
-            const int64_t u = solver_lds_elems_used(l, b / esz_);
+            const int64_t u = solver_lds_elems_used(l, mixed, b / esz_);
             if (u > last) { ldsc.push_back(b); last = u; }
         }
     }
