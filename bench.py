@@ -143,6 +143,8 @@ def leg_fast(args):
     tune_levels(ctxm, range(lmin, lmax + 1), J)
     seeds = [21 + i for i in range(max(1, args.seeds))]
     runs = {"plain_fp64": [], "mixed_surrogate": []}
+    if args.fp64_surrogate:
+        runs["fp64_surrogate"] = []
     for sd in seeds:
         r = ctx.run(y, J, seed=sd, s_adapt=args.s_adapt)
         runs["plain_fp64"].append(dict(
@@ -150,15 +152,26 @@ def leg_fast(args):
             mean=r["theta"].cpu().numpy().mean(0), log_Z=r["log_Z"],
             stage_acc_rate=[round(float(a), 4) for a in r["stage_acc_rate"]]))
         rm = ctxm.run(y, J, seed=sd, surrogate=True, sur_collect_max_level=6, sur_da_min_level=7,
-                      sur_pairs=20480, sur_epochs=30, sur_hidden=256, s_adapt=args.s_adapt)
+                      sur_pairs=20480, sur_epochs=15, sur_hidden=256, s_adapt=args.s_adapt)
         runs["mixed_surrogate"].append(dict(
             seconds=rm["seconds"], stages=rm["n_stages"], solves={str(i): v for i, v in enumerate(rm["solves"]) if v},
             mean=rm["theta"].cpu().numpy().mean(0), log_Z=rm["log_Z"],
             surrogate_train_s=round(rm["sur_train_seconds"], 3),
             stage1_pass_frac=rm["stage1_passed"] / max(1, rm["da_proposed"]),
             stage_acc_rate=[round(float(a), 4) for a in rm["stage_acc_rate"]]))
+        if args.fp64_surrogate:
+            rs = ctx.run(y, J, seed=sd, surrogate=True, sur_collect_max_level=6, sur_da_min_level=7,
+                         sur_pairs=20480, sur_epochs=15, sur_hidden=256, s_adapt=args.s_adapt)
+            runs["fp64_surrogate"].append(dict(
+                seconds=rs["seconds"], stages=rs["n_stages"],
+                solves={str(i): v for i, v in enumerate(rs["solves"]) if v},
+                mean=rs["theta"].cpu().numpy().mean(0), log_Z=rs["log_Z"],
+                surrogate_train_s=round(rs["sur_train_seconds"], 3),
+                stage1_pass_frac=rs["stage1_passed"] / max(1, rs["da_proposed"]),
+                stage_acc_rate=[round(float(a), 4) for a in rs["stage_acc_rate"]]))
         log(f"seed {sd}: plain {runs['plain_fp64'][-1]['seconds']:.3f} s, "
-            f"mixed+surrogate {runs['mixed_surrogate'][-1]['seconds']:.3f} s")
+            f"mixed+surrogate {runs['mixed_surrogate'][-1]['seconds']:.3f} s"
+            + (f", fp64+surrogate {runs['fp64_surrogate'][-1]['seconds']:.3f} s" if args.fp64_surrogate else ""))
     pooled = np.mean([d["mean"] for v in runs.values() for d in v], axis=0)
     out = {}
     for name, v in runs.items():
@@ -242,7 +255,7 @@ def leg_largest_run(args):
             y = (y + sn * torch.tensor(rng.standard_normal(m * m), device=dev)).contiguous()
         tune_levels(ctx, range(lmin, lmax + 1), J)
         kw = dict(surrogate=True, sur_collect_max_level=6, sur_da_min_level=7, sur_pairs=20480,
-                  sur_epochs=30, sur_hidden=256) if sur else {}
+                  sur_epochs=15, sur_hidden=256) if sur else {}
         r = ctx.run(y, J, seed=31, s_adapt=args.s_adapt, **kw)
         mean = r["theta"].cpu().numpy().mean(0)
         out[name] = dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
@@ -330,6 +343,8 @@ def main():
     ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest", "largest-run"],
                     help="cfg1: the default stage benchmark; others: the extra workloads")
     ap.add_argument("--seeds", type=int, default=1, help="fast: independent runs per form")
+    ap.add_argument("--fp64-surrogate", action="store_true",
+                    help="fast: also run the surrogate form with the FP64 solver")
     ap.add_argument("--s-adapt", action="store_true",
                     help="fast / largest-run: adapt the pCN step between stages (an extension)")
     ap.add_argument("--batched-sequential", action="store_true",

@@ -282,7 +282,7 @@ typedef struct {
     int sur_collect_max_level;
     int sur_da_min_level;
     int64_t sur_pairs;  /* ring capacity (0 = 20480)                        */
-    int sur_epochs;     /* 0 = 30                                           */
+    int sur_epochs;     /* 0 = 15                                           */
     int sur_hidden;     /* 0 = 256                                          */
     int sur_batch;      /* 0 = 256                                          */
     double sur_lr;      /* 0 = 1e-3                                         */

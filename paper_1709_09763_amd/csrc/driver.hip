@@ -224,7 +224,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         if (beta == 1.0 && l == ctx->prob.l_max) break;
         if (use_sur && !sur_ready && l >= sur_da && mls2mc_surrogate_n_pairs(ctx) >= 256) {
             const auto ts = std::chrono::steady_clock::now();
-            const int epochs = cfg->sur_epochs > 0 ? cfg->sur_epochs : 30;
+            const int epochs = cfg->sur_epochs > 0 ? cfg->sur_epochs : 15;
             std::vector<float> losses(epochs);
             MLS_TRY(mls2mc_surrogate_train(ctx, epochs, cfg->sur_batch > 0 ? cfg->sur_batch : 256,
                                            cfg->sur_lr > 0 ? cfg->sur_lr : 1e-3, cfg->seed ^ 0x7a11u,
