@@ -205,11 +205,12 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         MLS_CHECK_HIP(hipStreamSynchronize(s));
         return MLS2MC_OK;
     };
-    auto acc_count = [&]() -> double {
+    auto acc_count = [&](double* out) -> int {  // accepted proposals so far
         int64_t c3[3];
-        if (hipMemcpyAsync(c3, R.counters, sizeof(c3), hipMemcpyDeviceToHost, s) != hipSuccess) return 0;
-        if (hipStreamSynchronize(s) != hipSuccess) return 0;
-        return (double)c3[2];
+        MLS_CHECK_HIP(hipMemcpyAsync(c3, R.counters, sizeof(c3), hipMemcpyDeviceToHost, s));
+        MLS_CHECK_HIP(hipStreamSynchronize(s));
+        *out = (double)c3[2];
+        return MLS2MC_OK;
     };
 
     // ---- prior draw and first evaluation
@@ -259,7 +260,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
             MLS_TRY(gather_state(false));
             const double a0 = acc_host;
             MLS_TRY(mutate(stage, l, false, h[0], 1.0));
-            acc_host = acc_count();
+            MLS_TRY(acc_count(&acc_host));
             if (cfg->n_mcmc) adapt((acc_host - a0) / ((double)J * cfg->n_mcmc));
             beta = h[0];
             log_stage(checked ? 1 : 0, l, beta, 0.0, h[2]);
@@ -286,7 +287,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
                 MLS_TRY(gather_state(true));
                 const double a0 = acc_host;
                 MLS_TRY(mutate(stage, l, true, beta, h[0]));
-                acc_host = acc_count();
+                MLS_TRY(acc_count(&acc_host));
                 if (cfg->n_mcmc) adapt((acc_host - a0) / ((double)J * cfg->n_mcmc));
                 zeta = h[0];
                 log_stage(first ? (checked ? 2 : 3) : 4, l + 1, beta, zeta, h[2]);
