@@ -41,7 +41,7 @@ namespace mls {
 //                   V-cycle                          2 ceil(S_l / 2)
 //   coarse L<l:     WX WY XC BC                      4 S_L    then
 //                   KAP (per-triangle kappa)         2 n_L^2
-//   mixed solver:   FP64 X and R after the hierarchy (see solve_one_mixed)
+//   mixed solver:   FP64 X after the hierarchy (see solve_one_mixed)
 // The FP64 solver preconditions with a V-cycle whose finest-level weights
 // are the FP32-rounded edge weights: the preconditioner only has to be a
 // fixed symmetric positive definite operator close to A, and the stencil
@@ -71,8 +71,8 @@ __host__ __device__ inline int64_t hier_elems(int l, bool mixed)
 
 __host__ __device__ inline int64_t slot_elems_hd(int l, bool mixed)
 {
-    // float slot: + FP64 X64 and R64 (2 floats each) after an even offset
-    return hier_elems(l, mixed) + (mixed ? 4 * pad_sz(l) + 2 : 0);
+    // float slot: + FP64 X64 (2 floats per node) after an even offset
+    return hier_elems(l, mixed) + (mixed ? 2 * pad_sz(l) + 2 : 0);
 }
 
 int64_t solver_slot_elems(int l, bool mixed) { return slot_elems_hd(l, mixed); }
@@ -610,27 +610,31 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
 }
 
 // --------------------------------------------------------- mixed solve --
-// FP32 multigrid-PCG inside FP64 iterative refinement: the system matrix is
+// FP32 multigrid-PCG with residual replacement in FP64: the system matrix is
 // the one defined by the FP32 edge weights (promoted exactly to FP64 for the
-// residual), r64 = b - A x64 in FP64, the correction A d = r64 is solved
-// with FP32 MG-PCG to a loose tolerance, x64 += d.  Convergence is measured
-// like the FP64 solver's, on the preconditioned norm (r64, V r64) relative
-// to its first value.  The coarsest solve of the hierarchy is done in FP64.
+// residual).  The CG recurrence runs in FP32 on the correction x32 since the
+// last replacement; whenever (r, z) has fallen by kDrift2 since then, x32 is
+// folded into the FP64 iterate x64 and r is replaced by the FP64 residual
+// b - A x64 rounded to FP32, and the recurrence goes on with the same search
+// direction.  This bounds the drift between the recursive and the true
+// residual without restarting CG, so the iteration count stays near the
+// FP64 solver's.  Convergence is decided like the FP64 solver's, on the
+// preconditioned norm (r, V r) relative to its first value, and confirmed
+// on a freshly replaced residual.  The coarsest solve of the hierarchy is
+// done in FP64.
+constexpr double kDrift2 = 1e-6;  // replace r after (r, z) fell by this factor (1e-3 in norm)
+
 template <int BS>
 __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
-    const int64_t S = pad_sz(l);
     float *X = fine_array(M, FX), *R = fine_array(M, FR), *Z = fine_array(M, FZ), *Q = fine_array(M, FQ);
     float* Pb[2] = {fine_array(M, FP), fine_array(M, FP2)};
     const Lv<float> F = fine_level(M);
     const int s = F.s;
     const int64_t hier = hier_elems(l, true);
     double* X64 = (double*)(M.slot + ((hier + 1) & ~int64_t(1)));
-    double* R64 = X64 + S;
     const double h2 = 1.0 / (double)(F.n * F.n);
-    const double inner_tol2 = 1e-10;  // relative reduction 1e-5 per refinement sweep
-    const int max_outer = 16;
     const float* kap = (const float*)J.kap;
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
@@ -638,71 +642,86 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
     zero_boundary<BS>(Pb[1], F.n);
     zero_boundary<BS>(X64, F.n);
     setup_hierarchy<BS>(M, F, kap);
-    MLS_FOR_INTERIOR(F, { X64[c] = 0.0; R64[c] = h2; })
+    MLS_FOR_INTERIOR(F, { X64[c] = 0.0; X[c] = 0.f; R[c] = (float)h2; })
     __syncthreads();
-    int it = 0;
-    int8_t st = 1;
-    double rz_first = 0.0;
-    for (int outer = 0; outer < max_outer && st == 1; ++outer) {
-        MLS_FOR_INTERIOR(F, { X[c] = 0.f; R[c] = (float)R64[c]; })
-        __syncthreads();
-        vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
-        double rz = 0.0;
-        MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; })
-        rz = block_sum<BS>(rz, red);
-        if (!isfinite(rz)) { st = 2; break; }
-        if (outer == 0) {
-            rz_first = rz;
-            if (!(rz > 0.0)) { st = 2; break; }
-        } else if (rz <= C.tol2 * rz_first) {
-            st = 0;
-            break;
-        }
-        const double rzi0 = rz;
-        // p_k = z_k + beta_k p_{k-1}, formed inside the stencil pass as in
-        // the FP64 solver (p_0 = z_0 with beta = 0)
-        const float* Po = Z;
-        float beta = 0.f;
-        for (int k = 0; k < C.max_iters; ++k) {
-            float* Pn = Pb[k & 1];
-            double pq = 0.0;
-            auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
-            MLS_FOR_INTERIOR(F, {
-                const float pc = pn(c);
-                const float v = diag_at(F.wx, F.wy, c, s) * pc
-                              - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
-                                 + F.wy[c] * pn(c + s));
-                Pn[c] = pc;
-                Q[c] = v;
-                pq += (double)pc * (double)v;
-            })
-            pq = block_sum<BS>(pq, red);
-            const float alpha = (float)(rz / pq);
-            MLS_FOR_INTERIOR(F, {
-                X[c] += alpha * Pn[c];
-                const float rn = R[c] - alpha * Q[c];
-                R[c] = rn;
-                Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.f;  // black: taken as zero
-            })
-            __syncthreads();
-            const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
-            ++it;
-            if (!isfinite(rzn)) { st = 2; break; }
-            if (rzn <= inner_tol2 * rzi0) break;
-            beta = (float)(rzn / rz);
-            rz = rzn;
-            Po = Pn;
-        }
-        if (st == 2) break;
-        // x64 += d; r64 = b - A x64 in FP64 with the FP32 weights promoted
-        MLS_FOR_INTERIOR(F, { X64[c] += (double)X[c]; })
+    // x64 += x32, x32 = 0, then r = b - A x64 in FP64 (rounded to FP32)
+    auto replace_residual = [&]() {
+        MLS_FOR_INTERIOR(F, {
+            X64[c] += (double)X[c];
+            X[c] = 0.f;
+        })
         __syncthreads();
         MLS_FOR_INTERIOR(F, {
             const double d = (double)F.wx[c - 1] + (double)F.wx[c] + (double)F.wy[c - s] + (double)F.wy[c];
             const double nb = (double)F.wx[c - 1] * X64[c - 1] + (double)F.wx[c] * X64[c + 1]
                             + (double)F.wy[c - s] * X64[c - s] + (double)F.wy[c] * X64[c + s];
-            R64[c] = h2 - (d * X64[c] - nb);
+            R[c] = (float)(h2 - (d * X64[c] - nb));
         })
+        __syncthreads();
+    };
+    auto precondition = [&]() {  // z = V r and (r, z)
+        vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
+        double rz = 0.0;
+        MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; })
+        return block_sum<BS>(rz, red);
+    };
+    double rz = precondition();
+    const double rz0 = rz;
+    int it = 0;
+    int8_t st = 1;
+    if (!(rz0 > 0.0) || !isfinite(rz0)) st = 2;
+    double rz_upd = rz0;  // (r, z) at the last replacement
+    // p_k = z_k + beta_k p_{k-1}, formed inside the stencil pass as in the
+    // FP64 solver (p_0 = z_0 with beta = 0)
+    const float* Po = Z;
+    float beta = 0.f;
+    while (st == 1 && it < C.max_iters) {
+        float* Pn = Pb[it & 1];
+        double pq = 0.0;
+        auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
+        MLS_FOR_INTERIOR(F, {
+            const float pc = pn(c);
+            const float v = diag_at(F.wx, F.wy, c, s) * pc
+                          - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
+                             + F.wy[c] * pn(c + s));
+            Pn[c] = pc;
+            Q[c] = v;
+            pq += (double)pc * (double)v;
+        })
+        pq = block_sum<BS>(pq, red);
+        const float alpha = (float)(rz / pq);
+        MLS_FOR_INTERIOR(F, {
+            X[c] += alpha * Pn[c];
+            const float rn = R[c] - alpha * Q[c];
+            R[c] = rn;
+            Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.f;  // black: taken as zero
+        })
+        __syncthreads();
+        const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
+        ++it;
+        if (!isfinite(rzn)) { st = 2; break; }
+        const bool conv = rzn <= C.tol2 * rz0;
+        if (conv || rzn <= kDrift2 * rz_upd) {
+            replace_residual();
+            if (conv) {  // confirm on the replaced residual
+                const double rzt = precondition();
+                if (!isfinite(rzt)) { st = 2; break; }
+                if (rzt <= C.tol2 * rz0) { st = 0; break; }
+                // not there yet: go on from the true residual, directions restarted
+                rz = rzt;
+                rz_upd = rzt;
+                Po = Z;
+                beta = 0.f;
+                continue;
+            }
+            rz_upd = rzn;
+        }
+        beta = (float)(rzn / rz);
+        rz = rzn;
+        Po = Pn;
+    }
+    if (st != 0) {  // fold what the recurrence gathered since the last replacement
+        MLS_FOR_INTERIOR(F, { X64[c] += (double)X[c]; })
         __syncthreads();
     }
     observe_and_store<BS>(J, C, X64, F.n, st, it, red);
