@@ -189,21 +189,31 @@ int mls2mc_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u
 int mls2mc_gather(mls2mc_ctx* ctx, int64_t N, int64_t ncols, const int32_t* anc,
                   int64_t n_src, const double* src, double* dst, void* stream);
 
-/* One pCN Metropolis-Hastings step (Markov move of Sec. 2.4; pCN as cited in
- * Secs. 1 and 5) for the target exp(-Psi) times the N(0, I) prior,
- * Psi = beta [(1 - zeta) Phi_{l_lo} + zeta Phi_{l_hi}].  Tempering: l_lo ==
- * l_hi (zeta ignored).  Bridging: l_hi = l_lo + 1; the coarse level is
- * evaluated only while zeta < 1.
- * theta' = sqrt(1 - s^2) theta + s xi;  accept iff log u < -(Psi' - Psi).
+/* One Metropolis-Hastings step (Markov move of Sec. 2.4) for the target
+ * exp(-Psi) times the N(0, I) prior, Psi = beta [(1 - zeta) Phi_{l_lo} +
+ * zeta Phi_{l_hi}].  Tempering: l_lo == l_hi (zeta ignored).  Bridging:
+ * l_hi = l_lo + 1; the coarse level is evaluated only while zeta < 1.
+ * kernel MLS2MC_KERNEL_PCN (pCN, cited in Secs. 1 and 5):
+ *   theta' = sqrt(1 - s^2) theta + s xi;  accept iff log u < -(Psi' - Psi)
+ *   (0 < s <= 1).
+ * kernel MLS2MC_KERNEL_RWM (the random walk of the paper's Sec. 5 runs, whose
+ * proposal covariance is 2.38^2 / K times the identity: pass s = 2.38 /
+ * sqrt(K)):
+ *   theta' = theta + s xi;  accept iff log u < -(Psi' + |theta'|^2 / 2 -
+ *   Psi - |theta|^2 / 2)   (0 < s <= 10).
  * In/out state (device, double): theta N x K, G_lo / G_hi N x N_obs,
  * phi_lo / phi_hi N (caches of the current state; G_hi/phi_hi may be NULL
  * for tempering).  y: N_obs data.  xi: N x K normals; u: N uniforms in
  * (0,1).  accepted_out: N uint8 (may be NULL).  A proposal whose solve
  * fails (status != 0) is rejected.                                         */
+#define MLS2MC_KERNEL_PCN 0
+#define MLS2MC_KERNEL_RWM 1
+
 typedef struct {
     int l_lo, l_hi;
     double beta, zeta;
-    double s;          /* pCN step size, 0 < s <= 1 */
+    double s;          /* step size (see above)                            */
+    int kernel;        /* MLS2MC_KERNEL_PCN or MLS2MC_KERNEL_RWM           */
 } mls2mc_stage;
 
 int mls2mc_pcn_step(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, double* theta,
@@ -290,7 +300,20 @@ typedef struct {
      * use (0 = fixed s_pcn): after each stage s <- clamp(s exp(2 (a -
      * 0.25)), 0.005, 1) with a the stage's acceptance rate.               */
     int s_adapt;
+    /* update scheme: MLS2MC_SCHEME_MLS2MC, the adaptive scheme of Sec. 4.4,
+     * or MLS2MC_SCHEME_MLB, multilevel bridging (Example in Sec. 4): temper
+     * on l_min up to beta = 1, then bridge level by level.                 */
+    int scheme;
+    /* adaptive maximum level (the modified scheme u' of Sec. 4.5; 0 = off):
+     * at beta = 1 and l < l_max, cv^LU is estimated on the first J_tilde
+     * particles and the run stops at level l when cv^LU < tau_min (the
+     * paper uses 0.001); otherwise the look-ahead solves are reused.      */
+    double tau_min;
+    int kernel;         /* MLS2MC_KERNEL_PCN (default) or MLS2MC_KERNEL_RWM */
 } mls2mc_run_config;
+
+#define MLS2MC_SCHEME_MLS2MC 0
+#define MLS2MC_SCHEME_MLB 1
 
 typedef struct {
     int n_stages;

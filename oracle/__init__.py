@@ -31,7 +31,8 @@ class Config(C.Structure):
         ("tau_ess", C.c_double), ("tau_lu", C.c_double), ("eps", C.c_double),
         ("n_mcmc", C.c_int), ("s_pcn", C.c_double), ("seed", C.c_uint64),
         ("max_stages", C.c_int), ("nthreads", C.c_int),
-        ("lin_A", _dp), ("lin_E", _dp), ("da_S", _dp), ("s_adapt", C.c_int),
+        ("lin_A", _dp), ("lin_E", _dp), ("da_S", _dp), ("s_adapt", C.c_int), ("scheme", C.c_int),
+        ("tau_min", C.c_double), ("kernel", C.c_int),
     ]
 
 
@@ -72,6 +73,7 @@ def lib():
         L.orc_kl_field.argtypes = [C.c_int, C.c_int, C.c_int64, _dp, _dp, _dp]
         L.orc_resample.argtypes = [C.c_int64, _dp, _dp, _i32p]
         L.orc_pcn_propose.argtypes = [C.c_int64, C.c_int, C.c_double, _dp, _dp, _dp]
+        L.orc_rwm_propose.argtypes = [C.c_int64, C.c_int, C.c_double, _dp, _dp, _dp]
         L.orc_run_sampler.argtypes = [C.POINTER(Config), _dp, _dp, C.POINTER(Result)]
         L.orc_mlp_forward.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int64, _dp, _dp]
         L.orc_mlp_loss_grad.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, C.c_int64, _dp,
@@ -262,6 +264,14 @@ def pcn_propose(theta, xi, s):
     return out
 
 
+def rwm_propose(s, theta, xi):
+    theta = _f64(theta)
+    out = np.zeros_like(theta)
+    N, K = theta.shape
+    lib().orc_rwm_propose(N, K, s, _d(theta), _d(_f64(xi)), _d(out))
+    return out
+
+
 def mh_accept(psi_old, psi_new, u):
     return bool(lib().orc_mh_accept(psi_old, psi_new, u))
 
@@ -275,7 +285,7 @@ def da_accept(psi_old, psi_new, psis_old, psis_new, u1, u2):
 def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=0.3, m=3,
                 nobs=None, sigma_n=0.01, J=200, J_tilde=None, tau_star=1.0, tau_lu=None,
                 eps=1e-6, n_mcmc=5, s_pcn=0.5, seed=0, max_stages=2000, nthreads=0,
-                lin_A=None, lin_E=None, da_S=None, s_adapt=False):
+                lin_A=None, lin_E=None, da_S=None, s_adapt=False, scheme=0, tau_min=0.0, kernel=0):
     """Run the MLS^2MC sampler; returns a dict of results and final particles."""
     y = _f64(y)
     cfg = Config()
@@ -291,6 +301,7 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
     cfg.eps, cfg.n_mcmc, cfg.s_pcn, cfg.seed = eps, n_mcmc, s_pcn, seed
     cfg.max_stages, cfg.nthreads = max_stages, nthreads
     cfg.s_adapt = int(s_adapt)
+    cfg.scheme, cfg.tau_min, cfg.kernel = int(scheme), float(tau_min), int(kernel)
     keep = []
     if lin_A is not None:
         A = _f64(lin_A)

@@ -594,6 +594,12 @@ void orc_pcn_propose(int64_t N, int K, double s, const double* theta, const doub
     for (int64_t i = 0; i < N * K; ++i) theta_new[i] = a * theta[i] + s * xi[i];
 }
 
+void orc_rwm_propose(int64_t N, int K, double s, const double* theta, const double* xi,
+                     double* theta_new)
+{
+    for (int64_t i = 0; i < N * K; ++i) theta_new[i] = theta[i] + s * xi[i];
+}
+
 int orc_mh_accept(double psi_old, double psi_new, double u)
 {
     return log(u) < -(psi_new - psi_old);
@@ -720,7 +726,8 @@ static int orc_mutate(orc_model* md, const double* y, int stage, int l, int brid
     for (int mstep = 0; rc == 0 && mstep < cfg->n_mcmc; ++mstep) {
         for (int64_t i = 0; i < J * K; ++i)
             xi[i] = orc_normal(cfg->seed, ST_PCN_XI, (uint32_t)stage, (uint32_t)mstep, (uint32_t)i);
-        orc_pcn_propose(J, K, s_pcn, s->theta, xi, th);
+        if (cfg->kernel == 1) orc_rwm_propose(J, K, s_pcn, s->theta, xi, th);
+        else orc_pcn_propose(J, K, s_pcn, s->theta, xi, th);
         if (need_lo) {
             rc = orc_model_eval(md, l, J, th, Gl);
             if (rc) break;
@@ -740,6 +747,15 @@ static int orc_mutate(orc_model* md, const double* y, int stage, int l, int brid
                 psi_old = beta * ((1.0 - zeta) * s->philo[j] + zeta * s->phihi[j]);
                 psi_new = beta * ((1.0 - zeta) * pl[j] + zeta * ph[j]);
             } else { psi_old = beta * s->phihi[j]; psi_new = beta * ph[j]; }
+            if (cfg->kernel == 1) {  /* random walk: the N(0, I) prior does not cancel */
+                double qo = 0.0, qn = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    qo += s->theta[j * K + k] * s->theta[j * K + k];
+                    qn += th[j * K + k] * th[j * K + k];
+                }
+                psi_old += 0.5 * qo;
+                psi_new += 0.5 * qn;
+            }
             double u = orc_uniform(cfg->seed, ST_PCN_U, (uint32_t)stage, (uint32_t)mstep, (uint32_t)j);
             ++*prop;
             int ok;
@@ -837,20 +853,35 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
         if (beta == 1.0 && l == cfg->l_max) break;
         if (stage >= cfg->max_stages) { rc = ORC_ESING; break; }
         int do_lu, checked = 0;
-        if (beta == 1.0) do_lu = 1;
-        else if (l == cfg->l_max || prev_lu) do_lu = 0;
-        else {
-            /* look-ahead on the first J_tilde particles (Sec. 4.4) */
-            rc = orc_model_eval(&md, l + 1, Jt, s.theta, s.Ghi);
+        double cv = 0.0;
+        /* look-ahead: cv^LU of a level update at the current beta, from the
+         * first J_tilde particles (Sec. 4.4) */
+#define ORC_LOOK_AHEAD()                                                                  \
+        do {                                                                              \
+            rc = orc_model_eval(&md, l + 1, Jt, s.theta, s.Ghi);                          \
+            if (rc) break;                                                                \
+            orc_potentials(&md, Jt, s.Ghi, y, s.phihi);                                   \
+            res->solves[l + 1] += Jt;                                                     \
+            for (int64_t j = 0; j < Jt; ++j) d[j] = s.phihi[j] - s.philo[j];             \
+            double ess_ = orc_ess(Jt, d, beta, 1.0);                                      \
+            cv = sqrt((double)Jt / ess_ - 1.0 > 0 ? (double)Jt / ess_ - 1.0 : 0.0);       \
+            checked = 1;                                                                  \
+        } while (0)
+        if (beta == 1.0) {
+            if (cfg->tau_min > 0.0) {  /* scheme u' (Sec. 4.5) */
+                ORC_LOOK_AHEAD();
+                if (rc) break;
+                if (cv < cfg->tau_min) break;  /* terminate on level l */
+            }
+            do_lu = 1;
+        } else if (cfg->scheme == 1 || l == cfg->l_max || prev_lu) {
+            do_lu = 0;
+        } else {
+            ORC_LOOK_AHEAD();
             if (rc) break;
-            orc_potentials(&md, Jt, s.Ghi, y, s.phihi);
-            res->solves[l + 1] += Jt;
-            for (int64_t j = 0; j < Jt; ++j) d[j] = s.phihi[j] - s.philo[j];
-            double ess = orc_ess(Jt, d, beta, 1.0);
-            double cv = sqrt((double)Jt / ess - 1.0 > 0 ? (double)Jt / ess - 1.0 : 0.0);
-            checked = 1;
             do_lu = !(cv < cfg->tau_lu);
         }
+#undef ORC_LOOK_AHEAD
         if (!do_lu) {
             /* tempering update (Sec. 3.1) */
             double nb, dlz, ess;

@@ -101,6 +101,9 @@ int orc_next_step(int64_t N, const double* d, double scale, double cur,
 int orc_resample(int64_t N, const double* w, const double* u, int32_t* anc);
 
 /* ---- pCN proposal and Metropolis-Hastings acceptance ---- */
+/* Gaussian random-walk proposal theta' = theta + s xi                    */
+void orc_rwm_propose(int64_t N, int K, double s, const double* theta, const double* xi,
+                     double* theta_new);
 void orc_pcn_propose(int64_t N, int K, double s, const double* theta,
                      const double* xi, double* theta_new);
 /* returns 1 if accepted: log u < -(psi_new - psi_old)                     */
@@ -146,6 +149,16 @@ typedef struct {
      * after each stage s <- clamp(s exp(2 (a - 0.25)), 0.005, 1), a the
      * stage's acceptance rate.                                             */
     int s_adapt;
+    /* update scheme: 0 the adaptive scheme u of Sec. 4.4; 1 multilevel
+     * bridging (the Sec. 4 example: temper on l_min to beta = 1, then
+     * bridge level by level)                                               */
+    int scheme;
+    /* the modified scheme u' of Sec. 4.5 (0 = off): at beta = 1 and
+     * l < l_max stop when cv^LU < tau_min                                  */
+    double tau_min;
+    /* Markov kernel: 0 pCN; 1 Gaussian random walk theta + s xi with the
+     * N(0, I) prior ratio in the acceptance (the kernel of the Sec. 5 runs) */
+    int kernel;
 } orc_config;
 
 typedef struct {

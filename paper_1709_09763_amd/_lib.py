@@ -9,6 +9,8 @@ library_path = os.path.join(_HERE, "libmls2mc.so")
 
 FP64, MIXED = 0, 1
 FIELD_LOG_F64, FIELD_KAPPA_F64, FIELD_KAPPA_F32 = 0, 1, 2
+KERNEL_PCN, KERNEL_RWM = 0, 1
+SCHEME_MLS2MC, SCHEME_MLB = 0, 1
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV", 5: "ESINGULAR"}
 
 
@@ -26,7 +28,7 @@ class Problem(C.Structure):
 
 class Stage(C.Structure):
     _fields_ = [("l_lo", C.c_int), ("l_hi", C.c_int), ("beta", C.c_double), ("zeta", C.c_double),
-                ("s", C.c_double)]
+                ("s", C.c_double), ("kernel", C.c_int)]
 
 
 class RunConfig(C.Structure):
@@ -36,7 +38,7 @@ class RunConfig(C.Structure):
                 ("surrogate", C.c_int), ("sur_collect_max_level", C.c_int),
                 ("sur_da_min_level", C.c_int), ("sur_pairs", C.c_int64), ("sur_epochs", C.c_int),
                 ("sur_hidden", C.c_int), ("sur_batch", C.c_int), ("sur_lr", C.c_double),
-                ("s_adapt", C.c_int)]
+                ("s_adapt", C.c_int), ("scheme", C.c_int), ("tau_min", C.c_double), ("kernel", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -277,9 +279,9 @@ def mls2mc_philox_fill(h, seed, stream_id, stage, sub, out, normal):
 
 
 def mls2mc_pcn_step(h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u,
-                    accepted_out=None):
+                    accepted_out=None, kernel=0):
     N = theta.shape[0]
-    st = Stage(l_lo, l_hi, beta, zeta, s)
+    st = Stage(l_lo, l_hi, beta, zeta, s, kernel)
     f64 = torch.float64
     _check(lib().mls2mc_pcn_step(
         h, C.byref(st), N, _ptr(theta, f64, name="theta"), _ptr(G_lo, f64, name="G_lo", optional=True),
@@ -413,7 +415,7 @@ def mls2mc_surrogate_loss_grad(h, x, t, loss_out, grad_out):
 
 def mls2mc_pcn_step_da(h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u1, u2,
                        accepted_out, stage1_out=None, n_solved_lo=None, n_solved_hi=None):
-    st = Stage(l_lo, l_hi, beta, zeta, s)
+    st = Stage(l_lo, l_hi, beta, zeta, s, 0)
     f64 = torch.float64
     _check(lib().mls2mc_pcn_step_da(
         h, C.byref(st), theta.shape[0], _ptr(theta, f64, name="theta"),
@@ -546,14 +548,15 @@ class Context:
         mls2mc_philox_fill(self.h, seed, stream_id, stage, sub, out, normal)
         return out
 
-    def pcn_step(self, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u):
+    def pcn_step(self, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y, xi, u, kernel=0):
         acc = torch.empty(theta.shape[0], dtype=torch.uint8, device=theta.device)
         mls2mc_pcn_step(self.h, l_lo, l_hi, beta, zeta, s, theta, G_lo, G_hi, phi_lo, phi_hi, y,
-                        xi, u, acc)
+                        xi, u, acc, kernel)
         return acc
 
     def run_batch(self, instances, J_tilde=0, tau_star=1.0, n_mcmc=5, s_pcn=0.5, use_graphs=True):
-        cfg = RunConfig(0, J_tilde, tau_star, 0.0, 0.0, n_mcmc, s_pcn, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0)
+        cfg = RunConfig(0, J_tilde, tau_star, 0.0, 0.0, n_mcmc, s_pcn, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0, 0,
+                        0, 0.0, 0)
         for d in instances:
             d.setdefault("theta_out", torch.empty((d["J"], self.K), dtype=torch.float64, device="cuda:0"))
         out = mls2mc_run_batch(self.h, cfg, instances, use_graphs)
@@ -563,10 +566,13 @@ class Context:
 
     def run(self, y, J, J_tilde=0, tau_star=1.0, tau_lu=0.0, eps=0.0, n_mcmc=5, s_pcn=0.5, seed=0,
             max_stages=0, surrogate=False, sur_collect_max_level=0, sur_da_min_level=0, sur_pairs=0,
-            sur_epochs=0, sur_hidden=0, sur_batch=0, sur_lr=0.0, s_adapt=False):
+            sur_epochs=0, sur_hidden=0, sur_batch=0, sur_lr=0.0, s_adapt=False, scheme=0, tau_min=0.0,
+            kernel=0):
+        """scheme: SCHEME_MLS2MC or SCHEME_MLB; tau_min > 0: adaptive maximum level;
+        kernel: KERNEL_PCN or KERNEL_RWM (s_pcn is then the random-walk step)"""
         cfg = RunConfig(J, J_tilde, tau_star, tau_lu, eps, n_mcmc, s_pcn, seed, max_stages,
                         int(surrogate), sur_collect_max_level, sur_da_min_level, sur_pairs, sur_epochs,
-                        sur_hidden, sur_batch, sur_lr, int(s_adapt))
+                        sur_hidden, sur_batch, sur_lr, int(s_adapt), int(scheme), float(tau_min), int(kernel))
         theta = torch.empty((J, self.K), dtype=torch.float64, device=y.device)
         out = mls2mc_run(self.h, cfg, y, theta)
         out["theta"] = theta

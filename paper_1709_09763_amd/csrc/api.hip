@@ -376,7 +376,10 @@ int mls2mc_pcn_step(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, double* 
         MLS_TRY(check_level(ctx, st->l_hi));
         MLS_REQUIRE(st->zeta >= 0.0 && st->zeta <= 1.0, "pcn_step: need 0 <= zeta <= 1");
     }
-    MLS_REQUIRE(st->s > 0.0 && st->s <= 1.0, "pcn_step: need 0 < s <= 1");
+    MLS_REQUIRE(st->kernel == MLS2MC_KERNEL_PCN || st->kernel == MLS2MC_KERNEL_RWM,
+                "pcn_step: kernel must be MLS2MC_KERNEL_PCN or MLS2MC_KERNEL_RWM");
+    MLS_REQUIRE(st->s > 0.0 && st->s <= (st->kernel == MLS2MC_KERNEL_RWM ? 10.0 : 1.0),
+                "pcn_step: need 0 < s <= 1 (pCN) or 0 < s <= 10 (random walk)");
     MLS_REQUIRE(st->beta >= 0.0 && st->beta <= 1.0, "pcn_step: need 0 <= beta <= 1");
     MLS_REQUIRE(N >= 0, "pcn_step: N < 0");
     if (N == 0) return MLS2MC_OK;
@@ -400,11 +403,12 @@ int mls2mc_pcn_step(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, double* 
     int32_t* ith = itl + N;
     int8_t* stl = reinterpret_cast<int8_t*>(ith + N);
     int8_t* sth = stl + N;
-    MLS_TRY(launch_pcn_propose(N, K, st->s, theta, xi, thn, s));
+    MLS_TRY(launch_pcn_propose(N, K, st->s, st->kernel, theta, xi, thn, s));
     if (need_lo) MLS_TRY(forward_theta(ctx, st->l_lo, N, thn, Gln, stl, itl, y, pln, s));
     if (need_hi) MLS_TRY(forward_theta(ctx, st->l_hi, N, thn, Ghn, sth, ith, y, phn, s));
     const int mode = !bridge ? 0 : (st->zeta < 1.0 ? 1 : 2);
-    return launch_pcn_accept(N, K, nobs, mode, st->beta, st->zeta, u, thn, Gln, Ghn, pln, phn,
+    return launch_pcn_accept(N, K, nobs, mode, st->kernel == MLS2MC_KERNEL_RWM, st->beta, st->zeta, u, thn,
+                             Gln, Ghn, pln, phn,
                              need_lo ? stl : nullptr, need_hi ? sth : nullptr, theta, G_lo, G_hi,
                              phi_lo, phi_hi, accepted_out, s);
 }

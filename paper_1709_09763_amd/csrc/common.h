@@ -213,9 +213,9 @@ int launch_gather(int64_t N, int64_t ncols, const int32_t* anc, int64_t n_src, c
                   double* dst, hipStream_t s);
 int launch_philox(uint64_t seed, uint32_t stream_id, uint32_t stage, uint32_t sub, int64_t n,
                   int normal, double* out, hipStream_t s);
-int launch_pcn_propose(int64_t N, int K, double s_pcn, const double* theta, const double* xi,
+int launch_pcn_propose(int64_t N, int K, double s_pcn, int kernel, const double* theta, const double* xi,
                        double* out, hipStream_t s);
-int launch_pcn_accept(int64_t N, int K, int nobs, int mode, double beta, double zeta,
+int launch_pcn_accept(int64_t N, int K, int nobs, int mode, int rwm, double beta, double zeta,
                       const double* u, const double* th_new, const double* Glo_new,
                       const double* Ghi_new, const double* plo_new, const double* phi_new,
                       const int8_t* st_lo, const int8_t* st_hi, double* theta, double* Glo,

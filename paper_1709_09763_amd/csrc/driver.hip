@@ -63,7 +63,11 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     const int64_t Jt = cfg->J_tilde > 0 ? cfg->J_tilde : (J < 100 ? J : 100);
     MLS_REQUIRE(Jt >= 1 && Jt <= J, "run: need 1 <= J_tilde <= J");
     MLS_REQUIRE(cfg->tau_star > 0 && cfg->n_mcmc >= 0, "run: need tau_star > 0, n_mcmc >= 0");
-    MLS_REQUIRE(cfg->s_pcn > 0 && cfg->s_pcn <= 1, "run: need 0 < s_pcn <= 1");
+    MLS_REQUIRE(cfg->kernel == MLS2MC_KERNEL_PCN || cfg->kernel == MLS2MC_KERNEL_RWM, "run: unknown kernel");
+    MLS_REQUIRE(cfg->s_pcn > 0 && cfg->s_pcn <= (cfg->kernel == MLS2MC_KERNEL_RWM ? 10.0 : 1.0),
+                "run: need 0 < s_pcn <= 1 (pCN) or <= 10 (random walk)");
+    MLS_REQUIRE(cfg->scheme == MLS2MC_SCHEME_MLS2MC || cfg->scheme == MLS2MC_SCHEME_MLB, "run: unknown scheme");
+    MLS_REQUIRE(cfg->tau_min >= 0.0, "run: need tau_min >= 0");
     const double tau_ess = (double)J / (1.0 + cfg->tau_star * cfg->tau_star);
     const double tau_lu = cfg->tau_lu > 0 ? cfg->tau_lu : cfg->tau_star;
     const double eps = cfg->eps > 0 ? cfg->eps : 1e-6;
@@ -82,6 +86,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     if (use_sur) {
         MLS_REQUIRE(sur_da > ctx->prob.l_min && sur_da <= ctx->prob.l_max && sur_collect < sur_da,
                     "run: surrogate needs l_min < sur_da_min_level <= l_max and sur_collect_max_level < sur_da_min_level");
+        MLS_REQUIRE(cfg->kernel == MLS2MC_KERNEL_PCN, "run: delayed acceptance is built for the pCN kernel");
     }
     MLS_TRY(ctx->ws_run.ensure(bytes));
     RunState R;
@@ -149,6 +154,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         st.beta = beta;
         st.zeta = bridge ? zeta : 1.0;
         st.s = s_cur;
+        st.kernel = cfg->kernel;
         const bool da = sur_ready && l >= sur_da;
         for (int m = 0; m < cfg->n_mcmc; ++m) {
             MLS_TRY(launch_philox(cfg->seed, ST_PCN_XI, (uint32_t)stage, (uint32_t)m, J * K, 1, R.xi, s));
@@ -236,16 +242,30 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         }
         if (stage >= max_stages) { set_error("run: stage cap reached"); rc = MLS2MC_ESINGULAR; break; }
         bool do_lu, checked = false;
-        if (beta == 1.0) do_lu = true;
-        else if (l == ctx->prob.l_max || prev_lu) do_lu = false;
-        else {
+        // cv^LU of a level update at the current beta, from the first J_tilde particles
+        auto look_ahead = [&](double* cv) -> int {
             MLS_TRY(fwd(l + 1, Jt, R.theta, R.Ghi, R.phi));
             MLS_TRY(launch_ess_cv(Jt, R.plo, R.phi, beta, R.cv, s));
             double ess;
             MLS_CHECK_HIP(hipMemcpyAsync(&ess, R.cv, sizeof(double), hipMemcpyDeviceToHost, s));
             MLS_CHECK_HIP(hipStreamSynchronize(s));
-            double c2 = (double)Jt / ess - 1.0;
-            const double cv = std::sqrt(c2 > 0 ? c2 : 0.0);
+            const double c2 = (double)Jt / ess - 1.0;
+            *cv = std::sqrt(c2 > 0 ? c2 : 0.0);
+            return MLS2MC_OK;
+        };
+        if (beta == 1.0) {
+            if (cfg->tau_min > 0.0) {  // scheme u': stop when the level update would gain too little
+                double cv;
+                MLS_TRY(look_ahead(&cv));
+                checked = true;
+                if (cv < cfg->tau_min) break;
+            }
+            do_lu = true;
+        } else if (cfg->scheme == MLS2MC_SCHEME_MLB || l == ctx->prob.l_max || prev_lu) {
+            do_lu = false;
+        } else {
+            double cv;
+            MLS_TRY(look_ahead(&cv));
             checked = true;
             do_lu = !(cv < tau_lu);
         }

@@ -110,8 +110,10 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
 {
     MLS_REQUIRE(ctx && cfg && inst && res, "run_batch: null argument");
     MLS_REQUIRE(n_inst >= 1 && n_inst <= 4096, "run_batch: need 1 <= n_inst <= 4096");
-    MLS_REQUIRE(cfg->surrogate == 0 && cfg->s_adapt == 0,
-                "run_batch: the surrogate form and pCN step adaptation run through mls2mc_run");
+    MLS_REQUIRE(cfg->surrogate == 0 && cfg->s_adapt == 0 && cfg->scheme == MLS2MC_SCHEME_MLS2MC &&
+                    cfg->tau_min == 0.0 && cfg->kernel == MLS2MC_KERNEL_PCN,
+                "run_batch: the surrogate form, pCN step adaptation, other schemes and kernels, and the "
+                "adaptive maximum level run through mls2mc_run");
     MLS_REQUIRE(cfg->tau_star > 0 && cfg->n_mcmc >= 0 && cfg->s_pcn > 0 && cfg->s_pcn <= 1,
                 "run_batch: need tau_star > 0, n_mcmc >= 0, 0 < s_pcn <= 1");
     const int K = ctx->prob.K, nobs = ctx->nobs;
@@ -280,7 +282,7 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
                 Inst& q = I[i];
                 if (erc == MLS2MC_OK) erc = launch_philox(q.seed, ST_PCN_XI, (uint32_t)q.stage, (uint32_t)m, q.J * K, 1, q.xi, s);
                 if (erc == MLS2MC_OK) erc = launch_philox(q.seed, ST_PCN_U, (uint32_t)q.stage, (uint32_t)m, q.J, 0, q.upcn, s);
-                if (erc == MLS2MC_OK) erc = launch_pcn_propose(q.J, K, cfg->s_pcn, q.theta, q.xi, q.thn, s);
+                if (erc == MLS2MC_OK) erc = launch_pcn_propose(q.J, K, cfg->s_pcn, MLS2MC_KERNEL_PCN, q.theta, q.xi, q.thn, s);
             }
             if (erc == MLS2MC_OK) erc = enqueue_list(ctx, chunks, s);
             for (int i : act) {
@@ -288,7 +290,7 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
                 const int mode = !q.in_lu ? 0 : (q.t_next < 1.0 ? 1 : 2);
                 const double beta = q.in_lu ? q.beta : q.t_next;
                 if (erc == MLS2MC_OK)
-                    erc = launch_pcn_accept(q.J, K, nobs, mode, beta, q.t_next, q.upcn, q.thn, q.Gnl, q.Gnh, q.pnl,
+                    erc = launch_pcn_accept(q.J, K, nobs, mode, 0, beta, q.t_next, q.upcn, q.thn, q.Gnl, q.Gnh, q.pnl,
                                             q.pnh, mode != 2 ? q.stl : nullptr, mode != 0 ? q.sth : nullptr, q.theta,
                                             q.Glo, q.Ghi, q.plo, q.phi, q.acc, s);
                 if (erc == MLS2MC_OK) {

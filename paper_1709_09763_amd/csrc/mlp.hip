@@ -591,6 +591,7 @@ int mls2mc_pcn_step_da(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, doubl
 {
     MLS_REQUIRE(ctx != nullptr && st != nullptr, "pcn_step_da: null argument");
     MLS_REQUIRE(ctx->sur != nullptr, "pcn_step_da: no surrogate (mls2mc_surrogate_init)");
+    MLS_REQUIRE(st->kernel == MLS2MC_KERNEL_PCN, "pcn_step_da: delayed acceptance is built for the pCN kernel");
     MLS_REQUIRE(st->l_lo >= ctx->prob.l_min && st->l_lo <= ctx->prob.l_max, "pcn_step_da: level outside the context");
     const bool bridge = st->l_hi != st->l_lo;
     if (bridge) {
@@ -628,7 +629,7 @@ int mls2mc_pcn_step_da(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, doubl
     int8_t* stl = reinterpret_cast<int8_t*>(ith + N);
     int8_t* sth = stl + N;
     const double inv_sigma = 1.0 / ctx->prob.sigma_n;
-    MLS_TRY(launch_pcn_propose(N, K, st->s, theta, xi, thn, s));
+    MLS_TRY(launch_pcn_propose(N, K, st->s, MLS2MC_KERNEL_PCN, theta, xi, thn, s));
     MLS_TRY(mls2mc_surrogate_predict(ctx, N, theta, Gs, stream));
     MLS_TRY(mls2mc_surrogate_predict(ctx, N, thn, Gs2, stream));
     const unsigned gN = (unsigned)((N + 255) / 256);

@@ -306,20 +306,22 @@ __global__ void pcn_propose_kernel(int64_t n, double a, double s, const double* 
     if (t < n) out[t] = a * th[t] + s * xi[t];
 }
 
-int launch_pcn_propose(int64_t N, int K, double s_pcn, const double* theta, const double* xi,
+// pCN: theta' = sqrt(1 - s^2) theta + s xi; random walk: theta' = theta + s xi
+int launch_pcn_propose(int64_t N, int K, double s_pcn, int kernel, const double* theta, const double* xi,
                        double* out, hipStream_t s)
 {
     const int64_t n = N * K;
     if (n == 0) return MLS2MC_OK;
-    pcn_propose_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, std::sqrt(1.0 - s_pcn * s_pcn),
-                                                                   s_pcn, theta, xi, out);
+    const double a = kernel == MLS2MC_KERNEL_RWM ? 1.0 : std::sqrt(1.0 - s_pcn * s_pcn);
+    pcn_propose_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, a, s_pcn, theta, xi, out);
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
 }
 
 // mode 0: tempering (Psi = beta Phi_lo); 1: bridging with zeta < 1; 2:
-// bridging at zeta = 1 (Psi = beta Phi_hi).
-__global__ void pcn_accept_kernel(int64_t N, int K, int nobs, int mode, double beta, double zeta,
+// bridging at zeta = 1 (Psi = beta Phi_hi).  rwm: the random-walk kernel,
+// whose ratio also carries the N(0, I) prior term |theta|^2 / 2.
+__global__ void pcn_accept_kernel(int64_t N, int K, int nobs, int mode, int rwm, double beta, double zeta,
                                   const double* __restrict__ u, const double* __restrict__ thn,
                                   const double* __restrict__ Gln, const double* __restrict__ Ghn,
                                   const double* __restrict__ pln, const double* __restrict__ phn,
@@ -342,6 +344,15 @@ __global__ void pcn_accept_kernel(int64_t N, int K, int nobs, int mode, double b
         psi_old = beta * ph[j];
         psi_new = beta * phn[j];
     }
+    if (rwm) {
+        double qo = 0.0, qn = 0.0;
+        for (int k = 0; k < K; ++k) {
+            qo += th[j * K + k] * th[j * K + k];
+            qn += thn[j * K + k] * thn[j * K + k];
+        }
+        psi_old += 0.5 * qo;
+        psi_new += 0.5 * qn;
+    }
     bool ok = true;
     if (need_lo && stl && stl[j] != 0) ok = false;
     if (need_hi && sth && sth[j] != 0) ok = false;
@@ -360,7 +371,7 @@ __global__ void pcn_accept_kernel(int64_t N, int K, int nobs, int mode, double b
     if (acc) acc[j] = a ? 1 : 0;
 }
 
-int launch_pcn_accept(int64_t N, int K, int nobs, int mode, double beta, double zeta,
+int launch_pcn_accept(int64_t N, int K, int nobs, int mode, int rwm, double beta, double zeta,
                       const double* u, const double* th_new, const double* Glo_new,
                       const double* Ghi_new, const double* plo_new, const double* phi_new,
                       const int8_t* st_lo, const int8_t* st_hi, double* theta, double* Glo,
@@ -368,7 +379,7 @@ int launch_pcn_accept(int64_t N, int K, int nobs, int mode, double beta, double 
 {
     if (N == 0) return MLS2MC_OK;
     pcn_accept_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
-        N, K, nobs, mode, beta, zeta, u, th_new, Glo_new, Ghi_new, plo_new, phi_new, st_lo, st_hi,
+        N, K, nobs, mode, rwm, beta, zeta, u, th_new, Glo_new, Ghi_new, plo_new, phi_new, st_lo, st_hi,
         theta, Glo, Ghi, plo, phi, acc);
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;

@@ -104,9 +104,12 @@ def test_philox_matches_oracle(ctx):
     assert np.abs(z - zo).max() < 1e-13
 
 
-@pytest.mark.parametrize("mode", ["temper", "bridge", "bridge_end"])
+@pytest.mark.parametrize("mode", ["temper", "bridge", "bridge_end", "temper_rwm", "bridge_rwm"])
 def test_pcn_step_parity(ctx, mode):
     case(f"pcn_step {mode}")
+    rwm = mode.endswith("_rwm")
+    mode = mode.replace("_rwm", "")
+    step = 2.38 / np.sqrt(10) if rwm else 0.5
     K, N, m, sn = 10, 150, 3, 0.01
     l_lo, l_hi = (4, 4) if mode == "temper" else (4, 5)
     beta, zeta = 0.2, (0.4 if mode == "bridge" else 1.0)
@@ -119,7 +122,7 @@ def test_pcn_step_parity(ctx, mode):
     xi = inputs.theta_batch(13, N, K)
     u = 1.0 - inputs.uniforms53(14, N)  # (0, 1]
     # oracle step
-    thp = oracle.pcn_propose(th, xi, 0.5)
+    thp = oracle.rwm_propose(step, th, xi) if rwm else oracle.pcn_propose(th, xi, step)
     Glp = oracle.forward(l_lo, K, 1.0, 0.3, m, thp)
     Ghp = oracle.forward(l_hi, K, 1.0, 0.3, m, thp)
     plp = np.array([oracle.potential(g, y, sn) for g in Glp])
@@ -131,12 +134,16 @@ def test_pcn_step_parity(ctx, mode):
         new = beta * ((1 - zeta) * plp + zeta * php)
     else:
         old, new = beta * phi, beta * php
+    if rwm:  # the random walk carries the N(0, I) prior ratio
+        old = old + 0.5 * (th * th).sum(1)
+        new = new + 0.5 * (thp * thp).sum(1)
     acc_ref = np.array([oracle.mh_accept(o, n_, uu) for o, n_, uu in zip(old, new, u)])
     # GPU step
     T, GL, GH = to_dev(th), to_dev(Glo), to_dev(Ghi)
     PL, PH = to_dev(plo), to_dev(phi)
-    acc = host(ctx.pcn_step(l_lo, l_hi, beta, zeta, 0.5, T, GL, GH if l_hi != l_lo else None, PL,
-                            PH if l_hi != l_lo else None, to_dev(y), to_dev(xi), to_dev(u)))
+    acc = host(ctx.pcn_step(l_lo, l_hi, beta, zeta, step, T, GL, GH if l_hi != l_lo else None, PL,
+                            PH if l_hi != l_lo else None, to_dev(y), to_dev(xi), to_dev(u),
+                            kernel=P.KERNEL_RWM if rwm else P.KERNEL_PCN))
     np.testing.assert_array_equal(acc.astype(bool), acc_ref)
     assert 0 < acc_ref.sum() < N  # both outcomes exercised
     th_ref = np.where(acc_ref[:, None], thp, th)
@@ -157,20 +164,31 @@ def _data(l, K, m, sn, seed=0):
     dict(name="MLS2MC h=1/8..1/32", l_min=3, l_max=5, K=10, m=3, sn=0.01, J=200),
     dict(name="MLS2MC h=1/8..1/32, adapted pCN step", l_min=3, l_max=5, K=10, m=3, sn=0.002, J=200,
          s_adapt=True),
+    dict(name="multilevel bridging h=1/8..1/32", l_min=3, l_max=5, K=10, m=3, sn=0.01, J=200, scheme=1),
+    dict(name="adaptive maximum level h=1/8..1/64", l_min=3, l_max=6, K=10, m=3, sn=0.01, J=200,
+         tau_min=0.2),
+    dict(name="random-walk kernel h=1/8..1/32", l_min=3, l_max=5, K=10, m=3, sn=0.01, J=200, kernel=1,
+         s=2.38 / np.sqrt(10)),
 ])
 def test_run_matches_oracle(cfg):
     device()
     case(f"run {cfg['name']}")
     K, m, sn = cfg["K"], cfg["m"], cfg["sn"]
-    sa = cfg.get("s_adapt", False)
+    kw = dict(s_adapt=cfg.get("s_adapt", False), scheme=cfg.get("scheme", 0), tau_min=cfg.get("tau_min", 0.0),
+              kernel=cfg.get("kernel", 0))
+    step = cfg.get("s", 0.5)
     y = _data(cfg["l_max"], K, m, sn)
     ctx = P.Context(cfg["l_min"], cfg["l_max"], K, 1.0, 0.3, m, sn)
-    g = ctx.run(to_dev(y), cfg["J"], J_tilde=min(100, cfg["J"]), tau_star=1.0, n_mcmc=5, s_pcn=0.5, seed=5,
-                s_adapt=sa)
+    g = ctx.run(to_dev(y), cfg["J"], J_tilde=min(100, cfg["J"]), tau_star=1.0, n_mcmc=5, s_pcn=step, seed=5,
+                **kw)
     r = oracle.run_sampler(y, l_min=cfg["l_min"], l_max=cfg["l_max"], K=K, m=m, sigma_n=sn, J=cfg["J"],
-                           J_tilde=min(100, cfg["J"]), seed=5, n_mcmc=5, s_pcn=0.5, s_adapt=sa)
-    print(f"  stages gpu {g['n_stages']} oracle {r['n_stages']}, gpu {g['seconds']:.2f}s")
+                           J_tilde=min(100, cfg["J"]), seed=5, n_mcmc=5, s_pcn=step, **kw)
+    print(f"  stages gpu {g['n_stages']} oracle {r['n_stages']}, final level {g['final_level']}, "
+          f"gpu {g['seconds']:.2f}s")
     assert g["n_stages"] == r["n_stages"]
+    assert g["final_level"] == r["final_level"] and g["final_beta"] == r["final_beta"]
+    if cfg.get("tau_min"):
+        assert g["final_level"] < cfg["l_max"]  # this case stops early (cv^LU < tau_min at beta = 1)
     np.testing.assert_array_equal(g["stage_type"], r["stage_type"])
     np.testing.assert_array_equal(g["stage_level"], r["stage_level"])
     np.testing.assert_allclose(g["stage_beta"], r["stage_beta"], rtol=1e-8)

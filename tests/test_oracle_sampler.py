@@ -53,18 +53,21 @@ def _expected_solves(r, J, Jt, n_mcmc, l_min):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("s_adapt", [False, True])
-def test_linear_gaussian_single_level_posterior_and_evidence(s_adapt):
+@pytest.mark.parametrize("s_adapt,kernel", [(False, 0), (True, 0), (False, 1)])
+def test_linear_gaussian_single_level_posterior_and_evidence(s_adapt, kernel):
     # the optional step adaptation changes the step only between stages, so
-    # every mutation kernel still leaves its tempered target invariant
+    # every mutation kernel still leaves its tempered target invariant; the
+    # random-walk kernel (kernel 1) needs the prior ratio in its acceptance
     s = 0.2
     A, E, y = _lin_problem(s=s)
     m, C, logZ = _lin_posterior(A + 2.0 ** -6 * E, y, s)
     R, J = 8, 2000
     means, vars_, lz = [], [], []
+    step = 2.38 / np.sqrt(3) if kernel == 1 else 0.5
     for seed in range(R):
         r = oracle.run_sampler(y, model="linear", l_min=3, l_max=3, K=3, nobs=4, sigma_n=s, J=J,
-                               seed=seed, lin_A=A, lin_E=E, n_mcmc=5, s_adapt=s_adapt)
+                               seed=seed, lin_A=A, lin_E=E, n_mcmc=5, s_adapt=s_adapt, kernel=kernel,
+                               s_pcn=step)
         assert np.all(r["stage_type"] == 0)  # single-level SMC
         means.append(r["theta"].mean(0))
         vars_.append(r["theta"].var(0))
@@ -77,17 +80,22 @@ def test_linear_gaussian_single_level_posterior_and_evidence(s_adapt):
 
 
 @pytest.mark.slow
-def test_linear_gaussian_multilevel_posterior():
+@pytest.mark.parametrize("scheme,dep", [(0, 30.0), (1, 3.0)])
+def test_linear_gaussian_multilevel_posterior(scheme, dep):
+    # scheme 0: the adaptive MLS^2MC scheme, with strong level dependence
+    # (coarse levels are poor models); scheme 1: multilevel bridging, with
+    # moderate dependence (with strong dependence its evidence estimate is
+    # heavy-tailed, see test_mlb_evidence_spread)
     s = 0.15
     A, E, y = _lin_problem(K=2, nobs=3, s=s, seed=3)
-    E = 30.0 * E  # strong level dependence: coarse levels are poor models
+    E = dep * E
     m, C, logZ = _lin_posterior(A + 2.0 ** -10 * E, y, s)
     R, J = 8, 2000
     means, lz = [], []
     kinds = set()
     for seed in range(R):
         r = oracle.run_sampler(y, model="linear", l_min=2, l_max=5, K=2, nobs=3, sigma_n=s, J=J,
-                               J_tilde=100, seed=100 + seed, lin_A=A, lin_E=E)
+                               J_tilde=100, seed=100 + seed, lin_A=A, lin_E=E, scheme=scheme)
         assert r["final_level"] == 5 and r["final_beta"] == 1.0
         kinds |= set(r["stage_type"].tolist())
         means.append(r["theta"].mean(0))
@@ -100,6 +108,8 @@ def test_linear_gaussian_multilevel_posterior():
     assert np.all(np.abs(means.mean(0) - m) < 4 * se + 0.03 * np.sqrt(np.diag(C))), (means.mean(0), m)
     assert abs(lz.mean() - logZ) < 4 * lz.std(ddof=1) / np.sqrt(R) + 0.1
     assert 0 in kinds and (2 in kinds or 3 in kinds)
+    if scheme == 1:
+        assert kinds <= {0, 3, 4}  # no look-ahead in multilevel bridging
 
 
 def test_first_update_is_tempering_and_levels_monotone():
@@ -117,6 +127,70 @@ def test_first_update_is_tempering_and_levels_monotone():
         if t[i] in (0, 1) and t[i - 1] in (2, 3, 4):
             assert t[i] == 0
     np.testing.assert_array_equal(np.array(r["solves"]), _expected_solves(r, 300, 50, 5, 1))
+
+
+@pytest.mark.slow
+def test_mlb_evidence_spread():
+    # When the coarse levels are poor models, bridging at beta = 1 (MLB)
+    # spreads the log-evidence estimate far more than MLS^2MC, which bridges
+    # at the smaller temperatures its look-ahead picks (the paper's Sec. 5
+    # comparison); both stay consistent where the levels agree better.
+    s = 0.15
+    A, E, y = _lin_problem(K=2, nobs=3, s=s, seed=3)
+    spread = {}
+    for scheme in (0, 1):
+        lz = [oracle.run_sampler(y, model="linear", l_min=2, l_max=5, K=2, nobs=3, sigma_n=s, J=2000,
+                                 J_tilde=100, seed=100 + sd, lin_A=A, lin_E=30.0 * E, scheme=scheme)["log_Z"]
+              for sd in range(16)]
+        spread[scheme] = np.std(lz, ddof=1)
+    assert spread[1] > 4 * spread[0], spread
+
+
+def test_mlb_scheme_path_and_solves():
+    # multilevel bridging: temper on l_min up to beta = 1, then bridge level
+    # by level at beta = 1 (no look-ahead solves)
+    A, E, y = _lin_problem(seed=8)
+    J, Jt = 300, 50
+    r = oracle.run_sampler(y, model="linear", l_min=1, l_max=4, K=3, nobs=4, sigma_n=0.3, J=J, J_tilde=Jt,
+                           seed=2, lin_A=A, lin_E=10 * E, scheme=1)
+    t, lv, b = r["stage_type"], r["stage_level"], r["stage_beta"]
+    k = int(np.argmax(b == 1.0))
+    assert np.all(t[:k + 1] == 0) and np.all(lv[:k + 1] == 1)
+    assert np.all(np.isin(t[k + 1:], (3, 4))) and np.all(b[k:] == 1.0)
+    assert r["final_level"] == 4 and r["final_beta"] == 1.0
+    np.testing.assert_array_equal(np.array(r["solves"]), _expected_solves(r, J, Jt, 5, 1))
+
+
+def test_adaptive_max_level():
+    # scheme u' (tau_min > 0): at beta = 1 the run stops once a level update
+    # would change the measure by cv^LU < tau_min
+    A, E, y = _lin_problem(seed=9)
+    J, Jt = 300, 50
+    kw = dict(model="linear", l_min=1, l_max=4, K=3, nobs=4, sigma_n=0.3, J=J, J_tilde=Jt, seed=3, lin_A=A)
+    # identical levels: cv^LU = 0, so u tempers on l_min and u' stops there
+    r0 = oracle.run_sampler(y, lin_E=0 * E, **kw)
+    r1 = oracle.run_sampler(y, lin_E=0 * E, tau_min=1e-3, **kw)
+    assert r0["final_level"] == 4 and r1["final_level"] == 1 and r1["final_beta"] == 1.0
+    ex = _expected_solves(r1, J, Jt, 5, 1)
+    ex[2] += Jt  # the look-ahead that decided to stop
+    np.testing.assert_array_equal(np.array(r1["solves"]), ex)
+    # strongly different levels and a tiny tau_min: the same path as u, with
+    # the level updates at beta = 1 opened by a look-ahead
+    r0 = oracle.run_sampler(y, lin_E=20 * E, **kw)
+    r1 = oracle.run_sampler(y, lin_E=20 * E, tau_min=1e-12, **kw)
+    assert r0["final_level"] == r1["final_level"] == 4
+    np.testing.assert_array_equal(r0["stage_level"], r1["stage_level"])
+    np.testing.assert_array_equal(r0["stage_beta"], r1["stage_beta"])
+    np.testing.assert_array_equal(r0["theta"], r1["theta"])
+    forced = (r0["stage_type"] == 3)
+    np.testing.assert_array_equal(r1["stage_type"][forced], 2)
+    np.testing.assert_array_equal(np.array(r1["solves"]), _expected_solves(r1, J, Jt, 5, 1))
+
+
+def test_random_walk_proposal():
+    th = inputs.rng(5).standard_normal((4, 3))
+    xi = inputs.rng(6).standard_normal((4, 3))
+    np.testing.assert_array_equal(oracle.rwm_propose(0.7, th, xi), th + 0.7 * xi)
 
 
 def test_step_adaptation_schedule():
