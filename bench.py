@@ -196,6 +196,103 @@ def leg_fast(args):
                    "pcn_step": "adapted" if args.s_adapt else "fixed 0.5", "seeds": seeds}, **out}))
 
 
+def leg_compare(args):
+    """The paper's comparison on the h=1/8..1/64, K=50, 25 obs, J=1000
+    workload: MLS^2MC, MLS^2MC with the adaptive maximum level (tau_min =
+    0.001), multilevel bridging, and single-level SMC on h=1/64, each with
+    pCN and with the random-walk kernel (step 2.38/sqrt(K)); cost in the
+    paper's normalised units C_l = 4^(l - 6), over --seeds runs"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    W = WL
+    K, m, J = W["K"], W["m"], W["J"]
+    rng = np.random.default_rng(2024)
+    ctx = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"])
+    th_true = rng.standard_normal(K)
+    y = ctx.forward(W["l_max"], torch.tensor(th_true[None, :], device=dev))[0]
+    y = (y + W["sigma_n"] * torch.tensor(rng.standard_normal(ctx.nobs), device=dev)).contiguous()
+    ctx1 = P.Context(W["l_max"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"])
+    lam = ctx.kl_eigenvalues()
+    forms = {"mls2mc": (ctx, {}), "mls2mc_adaptive_max_level": (ctx, dict(tau_min=1e-3)),
+             "multilevel_bridging": (ctx, dict(scheme=P.SCHEME_MLB)), "single_level_smc": (ctx1, {})}
+    seeds = [11 + i for i in range(max(1, args.seeds))]
+    out = {}
+    for kname, kern, step in (("pcn", P.KERNEL_PCN, 0.5), ("rwm", P.KERNEL_RWM, 2.38 / np.sqrt(K))):
+        for name, (c, kw) in forms.items():
+            rows = []
+            for sd in seeds:
+                r = c.run(y, J, J_tilde=100, seed=sd, kernel=kern, s_pcn=step, **kw)
+                cost = sum(v * 4.0 ** (lv - W["l_max"]) for lv, v in enumerate(r["solves"]))
+                rows.append(dict(seconds=r["seconds"], cost=cost, log_Z=r["log_Z"], final_level=r["final_level"],
+                                 stages=r["n_stages"], accept=r["accepted"] / max(1, r["proposed"]),
+                                 rel_err=rel_err_paper(r["theta"].cpu().numpy().mean(0), th_true, lam)))
+            agg = {k: float(np.mean([q[k] for q in rows])) for k in rows[0]}
+            agg["log_Z_sd"] = float(np.std([q["log_Z"] for q in rows], ddof=1)) if len(rows) > 1 else None
+            out[f"{name}_{kname}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in agg.items()}
+            log(f"compare {name} {kname}: {out[f'{name}_{kname}']}")
+    base = out["single_level_smc_pcn"]["cost"]
+    print(json.dumps({
+        "metric": "MLS²MC vs comparison schemes (cost in normalised solves C_l = 4^(l-6))",
+        "value": round(base / out["mls2mc_pcn"]["cost"], 3), "unit": "cost ratio single-level SMC / MLS²MC (pCN)",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["name"], "seeds": seeds}, **out}))
+
+
+def leg_levels(args):
+    """Forward solves/s for every level h=1/8..1/512 at N = 1024 and 8192,
+    K=100, corr 0.3, 49 obs, FP64 and mixed, on prior draws and on
+    posterior particles of an h=1/8..1/256 run (sigma_n=0.002); launch
+    shapes autotuned per level on 512 prior draws"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    K, m, sn, lmin, lmax = 100, 7, 0.002, 3, 9
+    rng = np.random.default_rng(4)
+    prior = torch.tensor(rng.standard_normal((8192, K)), device=dev)
+    ctx = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn)
+    th_true = torch.tensor(rng.standard_normal((1, K)), device=dev)
+    y = (ctx.forward(8, th_true)[0] + sn * torch.tensor(rng.standard_normal(m * m), device=dev)).contiguous()
+    ctx_run = P.Context(lmin, 8, K, 1.0, 0.3, m, sn)
+    post = ctx_run.run(y, 4096, seed=5, s_adapt=True)["theta"]
+    post = torch.cat([post, post]).contiguous()  # 8192 posterior particles (two copies of 4096)
+    res = {}
+    for pname, prec in (("fp64", P.FP64), ("mixed", P.MIXED)):
+        c = P.Context(lmin, lmax, K, 1.0, 0.3, m, sn, precision=prec)
+        for lv in range(lmin, lmax + 1):
+            c.autotune(lv, 512)
+            row = {}
+            for src, th in (("prior", prior), ("posterior", post)):
+                for N in (1024, 8192):
+                    x = th[:N].contiguous()
+                    c.forward(lv, x[:256].contiguous())
+                    torch.cuda.synchronize()
+                    c.profile(True)
+                    t0 = time.perf_counter()
+                    G, st, it = c.forward(lv, x, with_stats=True)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    c.profile(False)
+                    ps = c.profile_read(P.PROF_SOLVE, lv)
+                    alg = solve_bytes(lv, m * m, ps["items"], ps["iters"], b_iter(c.get_launch(lv)[2], prec == P.MIXED))
+                    row[f"{src}_N{N}"] = dict(solves_per_s=round(N / dt, 1),
+                                              mean_iters=round(float(it.float().mean().item()), 2),
+                                              solver_algorithmic_GBs=round(alg / (ps["ms"] * 1e-3) / 1e9, 1),
+                                              converged=int((st == 0).sum().item()))
+            res[f"{pname}_h=1/{1 << lv}"] = dict(launch=list(c.get_launch(lv)), **row)
+            log(f"levels {pname} h=1/{1 << lv}: " + ", ".join(f"{k} {v['solves_per_s']}" for k, v in row.items()))
+        c.close()
+    print(json.dumps({
+        "metric": "forward solves/s per level", "value": res["fp64_h=1/64"]["prior_N1024"]["solves_per_s"],
+        "unit": "forward solves/s (h=1/64, N=1024, prior draws)", "n_gpus": 1, "higher_is_better": True,
+        "vs_baseline": None, "dtype": "f64 / mixed", "data": "synthetic",
+        "config": {"workload": "h=1/8..1/512, K=100, corr 0.3, Nobs=49, N in {1024, 8192}"}, **res}))
+
+
 def leg_batched(args):
     """32 instances, seeds 0..31, J ~ U{256..4096}, finest h in {1/64, 1/128,
     1/256}, K=100, 49 obs, sigma_n=0.002: fused rounds with HIP graphs"""
@@ -340,7 +437,8 @@ def main():
                     help="autotune even when the committed shapes match this device and solver")
     ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
-    ap.add_argument("--workload", default="cfg1", choices=["cfg1", "fast", "batched", "largest", "largest-run"],
+    ap.add_argument("--workload", default="cfg1",
+                    choices=["cfg1", "fast", "batched", "largest", "largest-run", "compare", "levels"],
                     help="cfg1: the default stage benchmark; others: the extra workloads")
     ap.add_argument("--seeds", type=int, default=1, help="fast: independent runs per form")
     ap.add_argument("--fp64-surrogate", action="store_true",
@@ -364,7 +462,7 @@ def main():
         return
     if args.workload != "cfg1":
         {"fast": leg_fast, "batched": leg_batched, "largest": leg_largest,
-         "largest-run": leg_largest_run}[args.workload](args)
+         "largest-run": leg_largest_run, "compare": leg_compare, "levels": leg_levels}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     W = WL
