@@ -69,10 +69,14 @@ __host__ __device__ inline int64_t hier_elems(int l, bool mixed)
     return o;
 }
 
+// 9 x 9 inverse of the h = 1/4 operator, the FP64 V-cycle's coarsest solve
+constexpr int64_t kCinvElems = 81;
+
 __host__ __device__ inline int64_t slot_elems_hd(int l, bool mixed)
 {
-    // float slot: + FP64 X64 (2 floats per node) after an even offset
-    return hier_elems(l, mixed) + (mixed ? 2 * pad_sz(l) + 2 : 0);
+    // float slot: + FP64 X64 (2 floats per node) after an even offset;
+    // double slot: + the coarse inverse, used when LDS has no room for it
+    return hier_elems(l, mixed) + (mixed ? 2 * pad_sz(l) + 2 : kCinvElems);
 }
 
 int64_t solver_slot_elems(int l, bool mixed) { return slot_elems_hd(l, mixed); }
@@ -119,6 +123,7 @@ struct Map {
     int l;
     int lds_top;
     int fine_n;
+    double* cinv;  // 9 x 9 inverse of the h = 1/4 operator (LDS or the slot), FP64 only
 };
 
 __host__ __device__ inline int64_t lds_coarse_elems(int top)
@@ -158,12 +163,13 @@ int64_t solver_lds_elems_used(int l, bool mixed, int64_t budget_elems)
 }
 
 template <typename T>
-__device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems)
+__device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems, double* cinv)
 {
     Map<T> M;
     M.slot = slot;
     M.lds = lds;
     M.l = l;
+    M.cinv = cinv;
     lds_policy(l, sizeof(T) == 8, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_n);
     return M;
 }
@@ -239,6 +245,20 @@ __device__ __forceinline__ T lnb(const Lv<T, W>& L, const T* __restrict__ x, int
         const int c = j * (L).s + i;                                                \
         __VA_ARGS__                                                                 \
     }
+
+// Synchronisation of the first wave alone: a wave's lanes see each other's
+// LDS stores once the wave's own memory operations have completed, which
+// the workgroup-scope fences wait for.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Working types whose V-cycle ends in an exact solve at h = 1/4
+template <typename T>
+constexpr bool kExactCoarse = sizeof(T) == 8;
 
 template <int BS, typename T>
 __device__ void zero_boundary(T* a, int n)
@@ -412,6 +432,64 @@ __device__ double up_step(const Lv<T, W>& L, const Lv<T>& C, const T* __restrict
     return dot;
 }
 
+// The V-cycle's coarsest level is h = 1/4 (nine unknowns), solved exactly
+// with the inverse of its operator, formed once per particle in FP64 by the
+// first wave: Gauss-Jordan sweeps in place over the 9 x 9 array (the
+// operator is a symmetric M-matrix, so no pivoting is needed).  Unknown
+// u = 3 (j - 1) + (i - 1).
+template <int BS, typename T, typename W>
+__device__ void build_coarse_inverse(const Lv<T, W>& L, double* cinv)
+{
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x, s = L.s;
+        for (int e = lane; e < 81; e += 64) {
+            const int u = e / 9, v = e % 9;
+            const int i = u % 3 + 1, j = u / 3 + 1, c = j * s + i;
+            double a = 0.0;
+            if (v == u) a = (double)ldiag(L, c);
+            else if (v == u - 1 && i > 1) a = -(double)L.wx[c - 1];
+            else if (v == u + 1 && i < 3) a = -(double)L.wx[c];
+            else if (v == u - 3) a = -(double)L.wy[c - s];
+            else if (v == u + 3) a = -(double)L.wy[c];
+            cinv[e] = a;
+        }
+        wave_sync();
+        // new value of entry e under the sweep on pivot p (r = 1 / pivot)
+        auto swept = [&](int e, int p, double r) {
+            const int u = e / 9, v = e % 9;
+            if (u == p && v == p) return r;
+            if (u == p) return cinv[9 * p + v] * r;
+            if (v == p) return -cinv[9 * u + p] * r;
+            return cinv[e] - cinv[9 * u + p] * cinv[9 * p + v] * r;
+        };
+        const int e1 = lane + 64;  // lanes 0..16 own a second entry
+        for (int p = 0; p < 9; ++p) {
+            const double r = 1.0 / cinv[9 * p + p];
+            const double n0 = swept(lane, p, r);
+            const double n1 = e1 < 81 ? swept(e1, p, r) : 0.0;
+            wave_sync();
+            cinv[lane] = n0;
+            if (e1 < 81) cinv[e1] = n1;
+            wave_sync();
+        }
+    }
+    __syncthreads();
+}
+
+// x = A^{-1} b on the h = 1/4 level L (nine threads)
+template <int BS, typename T, typename W>
+__device__ void coarse_exact(const Lv<T, W>& L, const T* __restrict__ b, T* __restrict__ x, const double* cinv)
+{
+    if (threadIdx.x < 9) {
+        const int s = L.s, u = threadIdx.x;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v += cinv[9 * u + q] * (double)b[(q / 3 + 1) * s + q % 3 + 1];
+        x[(u / 3 + 1) * s + u % 3 + 1] = T(v);
+    }
+    __syncthreads();
+}
+
 // One V-cycle z = V r on the hierarchy of M whose finest level is F (its
 // weights of type W).  See down_step and up_step for pre_red_done and
 // want_dot.
@@ -433,20 +511,36 @@ __device__ double vcycle(const Map<T>& M, const Lv<T, W>& F, const T* __restrict
         }
         return d;
     }
+    if (kExactCoarse<T> && l == 2) {  // the fine level is the coarsest: exact
+        coarse_exact<BS>(F, rhs, sol, M.cinv);
+        double d = 0.0;
+        if (want_dot) {
+            MLS_FOR_INTERIOR(F, { d += (double)rhs[c] * (double)sol[c]; })
+            d = block_sum<BS>(d, red);
+        }
+        return d;
+    }
+    // FP64 hierarchies stop at h = 1/4 and solve it exactly; FP32 ones go
+    // down to the single unknown of h = 1/2 (fewer registers in that kernel)
+    constexpr int Lc = kExactCoarse<T> ? 2 : 1;
     down_step<BS>(F, coarse_level(M, l - 1), rhs, sol, nu, pre_red_done);
-    for (int Lk = l - 1; Lk >= 2; --Lk) {
+    for (int Lk = l - 1; Lk > Lc; --Lk) {
         const Lv<T> L = coarse_level(M, Lk);
         down_step<BS>(L, coarse_level(M, Lk - 1), L.b, L.x, nu, false);
     }
-    {  // coarsest level, one unknown at (1,1)
-        const Lv<T> C = coarse_level(M, 1);
-        if (threadIdx.x == 0) {
-            const int c = C.s + 1;  // solved in FP64 for either working type
-            C.x[c] = T((double)C.b[c] / (double)diag_at(C.wx, C.wy, c, C.s));
+    {
+        const Lv<T> C = coarse_level(M, Lc);
+        if constexpr (kExactCoarse<T>) {
+            coarse_exact<BS>(C, C.b, C.x, M.cinv);
+        } else {  // one unknown at (1,1), solved in FP64
+            if (threadIdx.x == 0) {
+                const int c = C.s + 1;
+                C.x[c] = T((double)C.b[c] / (double)diag_at(C.wx, C.wy, c, C.s));
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
-    for (int Lk = 2; Lk <= l - 1; ++Lk) {
+    for (int Lk = Lc + 1; Lk <= l - 1; ++Lk) {
         const Lv<T> L = coarse_level(M, Lk);
         up_step<BS>(L, coarse_level(M, Lk - 1), L.b, L.x, nu, false, red);
     }
@@ -559,6 +653,8 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
     zero_boundary<BS>(Pb[0], F.n);
     zero_boundary<BS>(Pb[1], F.n);
     setup_hierarchy<BS>(M, F, kap, FV.wx, FV.wy);
+    if (l == 2) build_coarse_inverse<BS>(FV, M.cinv);
+    else if (l >= 3) build_coarse_inverse<BS>(coarse_level(M, 2), M.cinv);
     MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
     __syncthreads();
     vcycle<BS>(M, FV, R, Z, C.nu, false, false, red);
@@ -744,6 +840,7 @@ struct SolveParams {
     const int32_t* obs_idx;
     const double* obs_w;
     int64_t lds_elems;  // LDS budget in elements of the working type
+    int cinv_lds;       // FP64: the coarse inverse follows the budget in LDS (else in the slot)
     Common C;
 };
 
@@ -774,12 +871,14 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P
         J.phi = P.phi ? P.phi + q : nullptr;
         J.obs_idx = P.obs_idx;
         J.obs_w = P.obs_w;
-        if (MIXED)
+        if (MIXED) {
             solve_one_mixed<BS>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
-                                         P.lds_elems), J, P.C, red);
-        else
-            solve_one_f64<BS>(make_map((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (double*)mls_lds, l,
-                                       P.lds_elems), J, P.C, red);
+                                         P.lds_elems, nullptr), J, P.C, red);
+        } else {
+            double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
+            double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
+            solve_one_f64<BS>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+        }
     }
 }
 
@@ -797,6 +896,7 @@ struct ListParams {
     const int32_t* obs_idx[kMaxLevel + 1];
     const double* obs_w[kMaxLevel + 1];
     int64_t lds_elems;
+    int cinv_lds;
     Common C;
 };
 
@@ -825,12 +925,14 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListPara
         J.phi = it.phi ? it.phi + q : nullptr;
         J.obs_idx = P.obs_idx[l];
         J.obs_w = P.obs_w[l];
-        if (MIXED)
+        if (MIXED) {
             solve_one_mixed<BS>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
-                                         P.lds_elems), J, P.C, red);
-        else
-            solve_one_f64<BS>(make_map((double*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (double*)mls_lds, l,
-                                       P.lds_elems), J, P.C, red);
+                                         P.lds_elems, nullptr), J, P.C, red);
+        } else {
+            double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
+            double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
+            solve_one_f64<BS>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+        }
     }
 }
 
@@ -868,13 +970,20 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
 // *alloc_elems is what the launch allocates; kernels decide each particle's
 // residency with it as the budget, so no level uses more than is allocated
 // (the policy is monotone in the budget).
-static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* alloc_elems)
+// The FP64 kernels' coarse inverse goes after those elements when the
+// budget has room for it (or there is no residency), else in the slot: the
+// launch takes no more LDS than the budget (or than the inverse's 648 bytes
+// under a smaller one), so the workgroups per CU that a budget was chosen
+// for still fit.
+static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* alloc_elems, int* cinv_lds)
 {
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
     if (budget > ctx->max_lds) budget = ctx->max_lds;
     *alloc_elems = lds_elems_used(l, !mixed, (int64_t)(budget / esz));
-    return (size_t)*alloc_elems * esz;
+    const int64_t room = budget > kCinvElems * 8 ? budget : kCinvElems * 8;
+    *cinv_lds = !mixed && (*alloc_elems + kCinvElems) * 8 <= room;
+    return (size_t)(*alloc_elems + (*cinv_lds ? kCinvElems : 0)) * esz;
 }
 
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
@@ -899,7 +1008,7 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
     P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w;
     P.C = make_common(ctx, l);
-    const size_t lds = lds_bytes_for(ctx, l, mixed, &P.lds_elems);
+    const size_t lds = lds_bytes_for(ctx, l, mixed, &P.lds_elems, &P.cinv_lds);
     ProfRec rec;
     if (ctx->prof_on) {
         if (!P.iters) {  // the iteration totals need per-particle counts
@@ -944,7 +1053,7 @@ int launch_solve_list(mls2mc_ctx* ctx, const SolveItem* items_dev, int n_items, 
         P.obs_w[l] = ctx->obs[l].w;
     }
     P.C = make_common(ctx, lmax);
-    const size_t lds = lds_bytes_for(ctx, lmax, mixed, &P.lds_elems);
+    const size_t lds = lds_bytes_for(ctx, lmax, mixed, &P.lds_elems, &P.cinv_lds);
     dim3 g((unsigned)grid);
     if (mixed) { MLS_SWITCH_BS(bs, true, solve_list_kernel, g, lds, s, P) }
     else { MLS_SWITCH_BS(bs, false, solve_list_kernel, g, lds, s, P) }
