@@ -59,6 +59,24 @@ extern "C" {
                           stencil/smoothing/inner PCG, FP64 residual and
                           iterative refinement, FP64 coarsest solve       */
 
+/* ---- prior covariances (Sec. 5) ---- */
+#define MLS2MC_COV_SEPEXP 0   /* sigma2 exp(-|dx1|/c) exp(-|dx2|/c): KL modes in
+                                 closed form (roots of the 1-D eigen-equation) */
+#define MLS2MC_COV_MATERN32 1 /* Matern, smoothness 3/2, the prior of the
+                                 paper's elliptic examples (Sec. 5):
+                                 sigma2 (1 + sqrt(6) r/lam) exp(-sqrt(6) r/lam),
+                                 r = |x - x'|.  KL modes by the Nystrom method
+                                 on the kl_quad x kl_quad midpoint grid; the
+                                 eigenvectors are taken parity definite under
+                                 x1 -> 1-x1 and x2 -> 1-x2 (paired eigenvalues:
+                                 the one odd in x1 first), with the sign that
+                                 makes sum_q g_q v_q > 0 for
+                                 g_q = frac((q+1) 0.6180339887498949) - 1/2,
+                                 q = b m + a over the grid points
+                                 ((a+1/2)/m, (b+1/2)/m).  The basis at the
+                                 element centroids is the Nystrom extension
+                                 of each eigenvector.                         */
+
 /* ---- kinds of mls2mc_kl_field output ---- */
 #define MLS2MC_FIELD_LOG_F64 0   /* a = theta B (double)                   */
 #define MLS2MC_FIELD_KAPPA_F64 1 /* kappa = exp(a) (double)                */
@@ -70,8 +88,9 @@ typedef struct {
     int l_min, l_max;  /* levels used, 1 <= l_min <= l_max <= 10 (h = 2^-l)  */
     int K;             /* KL terms, 1 <= K <= 512                            */
     double sigma2;     /* prior field variance (> 0)                         */
-    double corr_len;   /* correlation length of the separable exponential
-                          covariance sigma2 exp(-|dx1|/c) exp(-|dx2|/c)      */
+    double corr_len;   /* correlation length: c of the separable exponential
+                          covariance sigma2 exp(-|dx1|/c) exp(-|dx2|/c), or
+                          lam of the Matern covariance (see cov)             */
     int m;             /* observation grid side, N_obs = m*m, 1 <= m <= 32   */
     double sigma_n;    /* noise standard deviation, Gamma = sigma_n^2 I (> 0)*/
     int precision;     /* MLS2MC_FP64 or MLS2MC_MIXED                        */
@@ -81,10 +100,16 @@ typedef struct {
                           (MIXED, measured on the FP64 residual of the
                           iterative refinement)                             */
     int max_iters;     /* PCG iteration cap; 0 selects 200                   */
+    int cov;           /* prior covariance: MLS2MC_COV_SEPEXP (0) or
+                          MLS2MC_COV_MATERN32                                */
+    int kl_quad;       /* MLS2MC_COV_MATERN32: side m of the Nystrom midpoint
+                          grid (even, 4..128, K <= m*m); 0 selects 64.  Must
+                          be 0 for MLS2MC_COV_SEPEXP                         */
 } mls2mc_problem;
 
 /* Create a context on the current HIP device: builds the KL modes (roots of
- * the 1-D eigen-equation, Sec. 5 truncated KL expansion), the basis tables
+ * the 1-D eigen-equation, or the Nystrom eigenpairs of the Matern operator;
+ * Sec. 5 truncated KL expansion), the basis tables
  * B_l[k, e] = sqrt(lambda_k) phi_k(centroid_e) for l_min..l_max on the GPU,
  * and the observation tables.  *out receives the context.  Synchronous.    */
 int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out);

@@ -11,6 +11,7 @@ FP64, MIXED = 0, 1
 FIELD_LOG_F64, FIELD_KAPPA_F64, FIELD_KAPPA_F32 = 0, 1, 2
 KERNEL_PCN, KERNEL_RWM = 0, 1
 SCHEME_MLS2MC, SCHEME_MLB = 0, 1
+COV_SEPEXP, COV_MATERN32 = 0, 1
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV", 5: "ESINGULAR"}
 
 
@@ -23,7 +24,8 @@ class Mls2mcError(RuntimeError):
 class Problem(C.Structure):
     _fields_ = [("l_min", C.c_int), ("l_max", C.c_int), ("K", C.c_int), ("sigma2", C.c_double),
                 ("corr_len", C.c_double), ("m", C.c_int), ("sigma_n", C.c_double),
-                ("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int)]
+                ("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int),
+                ("cov", C.c_int), ("kl_quad", C.c_int)]
 
 
 class Stage(C.Structure):
@@ -459,9 +461,9 @@ class Context:
     """Owns one library context; methods mirror the C entry points."""
 
     def __init__(self, l_min, l_max, K, sigma2=1.0, corr_len=0.3, m=3, sigma_n=0.01,
-                 precision=FP64, rtol=0.0, max_iters=0):
+                 precision=FP64, rtol=0.0, max_iters=0, cov=COV_SEPEXP, kl_quad=0):
         self.problem = Problem(l_min, l_max, K, sigma2, corr_len, m, sigma_n, precision, rtol,
-                               max_iters)
+                               max_iters, cov, kl_quad)
         self.K = K
         self.h = mls2mc_create(self.problem)
         self.nobs = mls2mc_n_obs(self.h)

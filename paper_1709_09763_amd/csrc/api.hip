@@ -233,6 +233,13 @@ int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out)
     MLS_REQUIRE(p->precision == MLS2MC_FP64 || p->precision == MLS2MC_MIXED,
                 "create: unknown precision");
     MLS_REQUIRE(p->rtol >= 0 && p->max_iters >= 0, "create: negative tolerance or cap");
+    MLS_REQUIRE(p->cov == MLS2MC_COV_SEPEXP || p->cov == MLS2MC_COV_MATERN32, "create: unknown covariance");
+    MLS_REQUIRE(p->cov == MLS2MC_COV_MATERN32 || p->kl_quad == 0,
+                "create: kl_quad applies to the Matern covariance only");
+    MLS_REQUIRE(p->kl_quad == 0 || (p->kl_quad >= 4 && p->kl_quad <= 128 && p->kl_quad % 2 == 0),
+                "create: kl_quad must be even, 4..128");
+    MLS_REQUIRE(p->cov != MLS2MC_COV_MATERN32 || p->K <= (p->kl_quad ? p->kl_quad * p->kl_quad : 4096),
+                "create: K exceeds the kl_quad^2 Nystrom eigenpairs");
     mls2mc_ctx* ctx = new (std::nothrow) mls2mc_ctx();
     if (!ctx) {
         set_error("create: host allocation failed");

@@ -136,6 +136,7 @@ namespace mls {
 
 // ------------------------------------------------------------ launchers --
 int build_kl_tables(mls2mc_ctx* ctx);
+int build_matern_tables(mls2mc_ctx* ctx);  // kl_matern.hip
 int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void* out, int kind,
                     hipStream_t s, const int64_t* N_dev = nullptr);
 int build_obs_tables(mls2mc_ctx* ctx);

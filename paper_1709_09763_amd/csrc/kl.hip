@@ -1,8 +1,9 @@
 // Truncated Karhunen-Loeve field of the prior (Sec. 5, truncated KL
-// expansion; Sec. 2.2, parameter discretisation) for the separable
-// exponential covariance sigma2 exp(-|dx1|/c) exp(-|dx2|/c), evaluated at the
-// element centroids as a GEMM  A[N x n_e] = Theta[N x K] B_l[K x n_e]  on the
-// CDNA4 matrix cores.
+// expansion; Sec. 2.2, parameter discretisation), evaluated at the element
+// centroids as a GEMM  A[N x n_e] = Theta[N x K] B_l[K x n_e]  on the CDNA4
+// matrix cores.  The modes of the separable exponential covariance
+// sigma2 exp(-|dx1|/c) exp(-|dx2|/c) are built here in closed form; those of
+// the Matern covariance in kl_matern.hip.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -112,6 +113,7 @@ __global__ void kl_basis_kernel(const double* __restrict__ modes, int K, int l, 
 int build_kl_tables(mls2mc_ctx* ctx)
 {
     const mls2mc_problem& p = ctx->prob;
+    if (p.cov == MLS2MC_COV_MATERN32) return build_matern_tables(ctx);
     const int K = p.K;
     const double c = 1.0 / p.corr_len;
     const int nm = K;  // 1-D modes needed at most
