@@ -412,6 +412,59 @@ def leg_largest(args):
         "config": {"workload": "h=1/512 K=200 corr=0.1 Nobs=100 J=8192 forward batch"}, **res}))
 
 
+def leg_matern(args):
+    """Matern (nu = 3/2) priors of the paper's elliptic examples (Sec. 5,
+    Examples 5.1 and 5.3; source f = 1 and the homogeneous Dirichlet problem
+    of the main path): KL build time (Nystrom eigenpairs and the basis at every
+    level), forward solves/s at the finest level, and one MLS^2MC run"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    cfgs = [("example_5_1", dict(lmin=3, lmax=7, K=10, lam=0.65, m=5, sn=0.07, J=1000)),
+            ("example_5_3", dict(lmin=4, lmax=8, K=320, lam=0.1, m=7, sn=0.045, J=1000))]
+    out = {}
+    for name, c in cfgs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = P.Context(c["lmin"], c["lmax"], c["K"], 1.0, c["lam"], c["m"], c["sn"], cov=P.COV_MATERN32)
+        torch.cuda.synchronize()
+        build = time.perf_counter() - t0
+        lam = ctx.kl_eigenvalues()
+        rng = np.random.default_rng(71)
+        l, K = c["lmax"], c["K"]
+        tune_levels(ctx, range(c["lmin"], l + 1), c["J"])
+        th = torch.tensor(rng.standard_normal((1024, K)), device=dev)
+        ctx.forward(l, th[:256].contiguous())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G, st, it = ctx.forward(l, th, with_stats=True)
+        torch.cuda.synchronize()
+        fwd = 1024 / (time.perf_counter() - t0)
+        th_true = rng.standard_normal(K)
+        y = ctx.forward(l, torch.tensor(th_true[None, :], device=dev))[0]
+        y = (y + c["sn"] * torch.tensor(rng.standard_normal(ctx.nobs), device=dev)).contiguous()
+        r = ctx.run(y, c["J"], seed=13)
+        mean = r["theta"].cpu().numpy().mean(0)
+        out[name] = dict(config=dict((k, v) for k, v in c.items()), kl_build_s=round(build, 3),
+                         variance_fraction=round(float(lam.sum()), 4),
+                         forward_solves_per_s=round(fwd, 1), mean_iters=float(it.float().mean().item()),
+                         converged=int((st == 0).sum().item()),
+                         run=dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
+                                  solves={str(i): v for i, v in enumerate(r["solves"]) if v},
+                                  rel_err_vs_truth=rel_err_paper(mean, th_true, lam), log_Z=r["log_Z"],
+                                  accept_rate=r["accepted"] / max(1, r["proposed"])))
+        log(f"matern {name} {out[name]}")
+        ctx.close()
+    print(json.dumps({
+        "metric": "Matern-prior KL build and forward solves/s", "value": out["example_5_3"]["forward_solves_per_s"],
+        "unit": "forward solves/s (h=1/256, K=320 Matern prior)", "n_gpus": 1, "higher_is_better": True,
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Matern 3/2 priors of Examples 5.1 (lam 0.65, K 10, h 1/8..1/128) and 5.3 "
+                               "(lam 0.1, K 320, h 1/16..1/256), Nystrom grid 64"}, **out}))
+
+
 def copy_calibration(gib=2.0):
     """plain device copy of known size, for scaling rocprofv3 byte counters"""
     import torch
@@ -438,7 +491,7 @@ def main():
     ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
     ap.add_argument("--workload", default="cfg1",
-                    choices=["cfg1", "fast", "batched", "largest", "largest-run", "compare", "levels"],
+                    choices=["cfg1", "fast", "batched", "largest", "largest-run", "compare", "levels", "matern"],
                     help="cfg1: the default stage benchmark; others: the extra workloads")
     ap.add_argument("--seeds", type=int, default=1, help="fast: independent runs per form")
     ap.add_argument("--fp64-surrogate", action="store_true",
@@ -462,7 +515,8 @@ def main():
         return
     if args.workload != "cfg1":
         {"fast": leg_fast, "batched": leg_batched, "largest": leg_largest,
-         "largest-run": leg_largest_run, "compare": leg_compare, "levels": leg_levels}[args.workload](args)
+         "largest-run": leg_largest_run, "compare": leg_compare, "levels": leg_levels,
+         "matern": leg_matern}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     W = WL
