@@ -77,6 +77,17 @@ extern "C" {
                                  element centroids is the Nystrom extension
                                  of each eigenvector.                         */
 
+/* ---- boundary-value problems (Sec. 5) ---- */
+#define MLS2MC_BC_DIRICHLET 0 /* -div(kappa grad p) = 1, p = 0 on the whole
+                                 boundary; unknowns (i, j), 1 <= i, j <= n-1  */
+#define MLS2MC_BC_FLOW_CELL 1 /* -div(kappa grad p) = 0, p = 0 at x1 = 0,
+                                 p = 1 at x1 = 1, no flow through x2 = 0 and
+                                 x2 = 1 (Example 5.3).  Unknowns (i, j),
+                                 1 <= i <= n-1, 0 <= j <= n, ordered
+                                 u = j (n-1) + (i-1).  kappa -> c kappa leaves
+                                 p unchanged, so a constant prior mean of
+                                 log kappa drops out                          */
+
 /* ---- kinds of mls2mc_kl_field output ---- */
 #define MLS2MC_FIELD_LOG_F64 0   /* a = theta B (double)                   */
 #define MLS2MC_FIELD_KAPPA_F64 1 /* kappa = exp(a) (double)                */
@@ -105,6 +116,9 @@ typedef struct {
     int kl_quad;       /* MLS2MC_COV_MATERN32: side m of the Nystrom midpoint
                           grid (even, 4..128, K <= m*m); 0 selects 64.  Must
                           be 0 for MLS2MC_COV_SEPEXP                         */
+    int bc;            /* boundary-value problem: MLS2MC_BC_DIRICHLET (0) or
+                          MLS2MC_BC_FLOW_CELL (FP64 only; not with the
+                          batched entry points)                              */
 } mls2mc_problem;
 
 /* Create a context on the current HIP device: builds the KL modes (roots of
@@ -127,6 +141,9 @@ int mls2mc_kl_eigenvalues(const mls2mc_ctx* ctx, double* lambda_out);
 int mls2mc_n_obs(const mls2mc_ctx* ctx);
 int64_t mls2mc_n_elem(int l);     /* 2 * 4^l                              */
 int64_t mls2mc_n_unknowns(int l); /* (2^l - 1)^2                          */
+/* unknowns of level l under the context's boundary-value problem:
+ * (2^l - 1)^2, or (2^l - 1)(2^l + 1) for the flow cell; -1 on bad input   */
+int64_t mls2mc_ctx_n_unknowns(const mls2mc_ctx* ctx, int l);
 
 /* KL field (Sec. 5, truncated KL expansion; Sec. 2.2 discretisation):
  * out[q, e] = sum_k theta[q, k] B_l[k, e] for q < N, e < n_e(l), evaluated
@@ -152,7 +169,8 @@ int mls2mc_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, doubl
 
 /* Forward response from a given coefficient batch (skips the KL field):
  * kappa: N x n_e(l) double, one positive value per element; G_out as above;
- * p_out (N x M(l) double, may be NULL) receives the nodal solution.        */
+ * p_out (N x M(l) double, may be NULL) receives the nodal solution at the
+ * unknowns, M(l) = mls2mc_ctx_n_unknowns(ctx, l).                          */
 int mls2mc_forward_field(mls2mc_ctx* ctx, int l, int64_t N, const double* kappa,
                          double* G_out, double* p_out, int8_t* status_out,
                          int32_t* iters_out, void* stream);

@@ -12,6 +12,7 @@ FIELD_LOG_F64, FIELD_KAPPA_F64, FIELD_KAPPA_F32 = 0, 1, 2
 KERNEL_PCN, KERNEL_RWM = 0, 1
 SCHEME_MLS2MC, SCHEME_MLB = 0, 1
 COV_SEPEXP, COV_MATERN32 = 0, 1
+BC_DIRICHLET, BC_FLOW_CELL = 0, 1
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV", 5: "ESINGULAR"}
 
 
@@ -25,7 +26,7 @@ class Problem(C.Structure):
     _fields_ = [("l_min", C.c_int), ("l_max", C.c_int), ("K", C.c_int), ("sigma2", C.c_double),
                 ("corr_len", C.c_double), ("m", C.c_int), ("sigma_n", C.c_double),
                 ("precision", C.c_int), ("rtol", C.c_double), ("max_iters", C.c_int),
-                ("cov", C.c_int), ("kl_quad", C.c_int)]
+                ("cov", C.c_int), ("kl_quad", C.c_int), ("bc", C.c_int)]
 
 
 class Stage(C.Structure):
@@ -93,6 +94,8 @@ def lib():
         L.mls2mc_n_elem.argtypes = [C.c_int]
         L.mls2mc_n_unknowns.restype = C.c_int64
         L.mls2mc_n_unknowns.argtypes = [C.c_int]
+        L.mls2mc_ctx_n_unknowns.restype = C.c_int64
+        L.mls2mc_ctx_n_unknowns.argtypes = [_vp, C.c_int]
         L.mls2mc_n_obs.argtypes = [_vp]
         L.mls2mc_create.argtypes = [C.POINTER(Problem), C.POINTER(_vp)]
         L.mls2mc_destroy.argtypes = [_vp]
@@ -149,6 +152,10 @@ def mls2mc_n_elem(l):
 
 def mls2mc_n_unknowns(l):
     return lib().mls2mc_n_unknowns(l)
+
+
+def mls2mc_ctx_n_unknowns(h, l):
+    return lib().mls2mc_ctx_n_unknowns(h, l)
 
 
 def _check(rc, where):
@@ -212,7 +219,7 @@ def mls2mc_forward_field(h, l, kappa, G_out, p_out=None, status_out=None, iters_
     _check(lib().mls2mc_forward_field(
         h, l, N, _ptr(kappa, torch.float64, (N, mls2mc_n_elem(l)), "kappa"),
         _ptr(G_out, torch.float64, (N, mls2mc_n_obs(h)), "G_out"),
-        _ptr(p_out, torch.float64, (N, mls2mc_n_unknowns(l)), "p_out", True),
+        _ptr(p_out, torch.float64, (N, mls2mc_ctx_n_unknowns(h, l)), "p_out", True),
         _ptr(status_out, torch.int8, (N,), "status_out", True),
         _ptr(iters_out, torch.int32, (N,), "iters_out", True), _stream()), "mls2mc_forward_field")
 
@@ -461,9 +468,9 @@ class Context:
     """Owns one library context; methods mirror the C entry points."""
 
     def __init__(self, l_min, l_max, K, sigma2=1.0, corr_len=0.3, m=3, sigma_n=0.01,
-                 precision=FP64, rtol=0.0, max_iters=0, cov=COV_SEPEXP, kl_quad=0):
+                 precision=FP64, rtol=0.0, max_iters=0, cov=COV_SEPEXP, kl_quad=0, bc=BC_DIRICHLET):
         self.problem = Problem(l_min, l_max, K, sigma2, corr_len, m, sigma_n, precision, rtol,
-                               max_iters, cov, kl_quad)
+                               max_iters, cov, kl_quad, bc)
         self.K = K
         self.h = mls2mc_create(self.problem)
         self.nobs = mls2mc_n_obs(self.h)
@@ -516,7 +523,7 @@ class Context:
         N = kappa.shape[0]
         dev = kappa.device
         G = torch.empty((N, self.nobs), dtype=torch.float64, device=dev)
-        p = torch.empty((N, mls2mc_n_unknowns(l)), dtype=torch.float64, device=dev) if want_p else None
+        p = torch.empty((N, mls2mc_ctx_n_unknowns(self.h, l)), dtype=torch.float64, device=dev) if want_p else None
         st = torch.empty(N, dtype=torch.int8, device=dev)
         it = torch.empty(N, dtype=torch.int32, device=dev)
         mls2mc_forward_field(self.h, l, kappa, G, p, st, it)

@@ -179,6 +179,11 @@ const char* mls2mc_version(void) { return "mls2mc 1.0 gfx950"; }
 int64_t mls2mc_n_elem(int l) { return (l >= 0 && l <= 15) ? n_elem(l) : -1; }
 int64_t mls2mc_n_unknowns(int l) { return (l >= 0 && l <= 15) ? n_unk(l) : -1; }
 int mls2mc_n_obs(const mls2mc_ctx* ctx) { return ctx ? ctx->nobs : -1; }
+int64_t mls2mc_ctx_n_unknowns(const mls2mc_ctx* ctx, int l)
+{
+    if (!ctx || l < 1 || l > kMaxLevel) return -1;
+    return ctx->prob.bc == MLS2MC_BC_FLOW_CELL ? flow_unknowns(l) : n_unk(l);
+}
 
 int mls2mc_kl_eigenvalues(const mls2mc_ctx* ctx, double* lambda_out)
 {
@@ -236,6 +241,9 @@ int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out)
     MLS_REQUIRE(p->cov == MLS2MC_COV_SEPEXP || p->cov == MLS2MC_COV_MATERN32, "create: unknown covariance");
     MLS_REQUIRE(p->cov == MLS2MC_COV_MATERN32 || p->kl_quad == 0,
                 "create: kl_quad applies to the Matern covariance only");
+    MLS_REQUIRE(p->bc == MLS2MC_BC_DIRICHLET || p->bc == MLS2MC_BC_FLOW_CELL, "create: unknown boundary-value problem");
+    MLS_REQUIRE(p->bc == MLS2MC_BC_DIRICHLET || p->precision == MLS2MC_FP64,
+                "create: the flow cell is solved in FP64 only (precision)");
     MLS_REQUIRE(p->kl_quad == 0 || (p->kl_quad >= 4 && p->kl_quad <= 128 && p->kl_quad % 2 == 0),
                 "create: kl_quad must be even, 4..128");
     MLS_REQUIRE(p->cov != MLS2MC_COV_MATERN32 || p->K <= (p->kl_quad ? p->kl_quad * p->kl_quad : 4096),

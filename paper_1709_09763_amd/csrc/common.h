@@ -155,6 +155,9 @@ struct SolveArgs {
     const int64_t* N_dev = nullptr;  // device-side count <= N (null: N)
 };
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s);
+// flow-cell problem (flowcell.hip): its solver and its unknowns per level
+int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s);
+int64_t flow_unknowns(int l);
 
 // one entry of a fused multi-instance / multi-level solver launch
 struct SolveItem {

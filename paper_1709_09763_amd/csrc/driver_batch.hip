@@ -110,6 +110,7 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
 {
     MLS_REQUIRE(ctx && cfg && inst && res, "run_batch: null argument");
     MLS_REQUIRE(n_inst >= 1 && n_inst <= 4096, "run_batch: need 1 <= n_inst <= 4096");
+    MLS_REQUIRE(ctx->prob.bc == MLS2MC_BC_DIRICHLET, "run_batch: Dirichlet problem only");
     MLS_REQUIRE(cfg->surrogate == 0 && cfg->s_adapt == 0 && cfg->scheme == MLS2MC_SCHEME_MLS2MC &&
                     cfg->tau_min == 0.0 && cfg->kernel == MLS2MC_KERNEL_PCN,
                 "run_batch: the surrogate form, pCN step adaptation, other schemes and kernels, and the "

@@ -1,0 +1,415 @@
+// Flow-cell forward problem (Sec. 5, Example 5.3): P1 finite elements for
+//   -div(kappa grad p) = 0 on (0,1)^2,  p = 0 on x1 = 0,  p = 1 on x1 = 1,
+//   no flow through x2 = 0 and x2 = 1,
+// solved by multigrid-preconditioned CG with one persistent workgroup per
+// particle, like the Dirichlet solver, on a layout of its own.
+//
+// Layout of level L (n = 2^L): nodes (i, j), 0 <= i <= n, with a ghost row
+// below j = 0 and above j = n; index c = (j + 1)(n + 1) + i, (n+1)(n+3)
+// entries.  Unknowns are 1 <= i <= n-1, 0 <= j <= n (the two no-flow rows
+// included), u = j (n-1) + (i-1).  The operator is the 5-point form of P1 on
+// the SW-NE mesh: the weight of an edge is half the sum of the coefficients
+// of the (one or two) triangles that have it as a leg, so the no-flow rows get
+// their natural one-sided weights and the edges to the ghost rows weigh 0.
+// The Dirichlet value 1 at i = n enters the right-hand side through the
+// weights of the edges (n-1, j)-(n, j); the iterates hold 0 on both
+// Dirichlet columns.
+//
+// V-cycle: red-black Gauss-Seidel (red first down, black first up, so the
+// cycle is symmetric), residual, restriction by the transpose of P1
+// interpolation, coarse coefficients averaged over the four children of
+// each coarse triangle (the Galerkin operator of the nested meshes), an exact
+// tridiagonal solve at h = 1/2 (three unknowns on the column i = 1).
+#include "common.h"
+
+namespace mls {
+
+namespace {
+
+__host__ __device__ inline int64_t fsz(int L)
+{
+    const int64_t n = int64_t(1) << L;
+    return (n + 1) * (n + 3);
+}
+
+// slot: fine arrays, then per coarse level l-1 .. 1 its arrays and coefficients
+enum { F_U = 0, F_R, F_Z, F_P, F_Q, F_WX, F_WY, F_COUNT };
+enum { C_X = 0, C_B, C_T, C_WX, C_WY, C_COUNT };
+
+__host__ __device__ inline int64_t coarse_base(int l, int L)
+{
+    int64_t o = F_COUNT * fsz(l);
+    for (int k = l - 1; k > L; --k) o += C_COUNT * fsz(k) + (int64_t(2) << (2 * k));
+    return o;
+}
+
+__host__ __device__ inline int64_t flow_slot(int l) { return coarse_base(l, 0); }
+
+struct FLv {
+    double *x, *b, *t, *wx, *wy, *kc;
+    int n, s;
+};
+
+// level L of the hierarchy of the slot (L = l: the fine level's V-cycle
+// arrays, x = Z, b = R, t = Q)
+__device__ inline FLv flevel(double* slot, int l, int L)
+{
+    FLv v;
+    v.n = 1 << L;
+    v.s = v.n + 1;
+    const int64_t f = fsz(L);
+    if (L == l) {
+        v.x = slot + F_Z * f;
+        v.b = slot + F_R * f;
+        v.t = slot + F_Q * f;
+        v.wx = slot + F_WX * f;
+        v.wy = slot + F_WY * f;
+        v.kc = nullptr;
+    } else {
+        double* base = slot + coarse_base(l, L);
+        v.x = base + C_X * f;
+        v.b = base + C_B * f;
+        v.t = base + C_T * f;
+        v.wx = base + C_WX * f;
+        v.wy = base + C_WY * f;
+        v.kc = base + C_COUNT * f;
+    }
+    return v;
+}
+
+#define FLOW_FOR_UNK(n_, ...)                                                  \
+    for (int t_ = threadIdx.x; t_ < ((n_) - 1) * ((n_) + 1); t_ += BS) {     \
+        const int i = 1 + t_ % ((n_) - 1), j = t_ / ((n_) - 1);              \
+        const int c = (j + 1) * ((n_) + 1) + i;                              \
+        __VA_ARGS__                                                          \
+    }
+
+__device__ __forceinline__ double fdiag(const FLv& L, int c)
+{
+    return L.wx[c - 1] + L.wx[c] + L.wy[c - L.s] + L.wy[c];
+}
+
+__device__ __forceinline__ double fnb(const FLv& L, const double* x, int c)
+{
+    return L.wx[c - 1] * x[c - 1] + L.wx[c] * x[c + 1] + L.wy[c - L.s] * x[c - L.s] + L.wy[c] * x[c + L.s];
+}
+
+template <int BS>
+__device__ void zero_all(double* a, int64_t n)
+{
+    for (int64_t t = threadIdx.x; t < n; t += BS) a[t] = 0.0;
+}
+
+// edge weights of a level from its element coefficients (kl: lower
+// triangles at 2(jn+i), upper at 2(jn+i)+1)
+template <int BS, typename KT>
+__device__ void flow_weights(const FLv& L, const KT* __restrict__ ke)
+{
+    const int n = L.n, s = L.s;
+    const int64_t tot = fsz(31 - __builtin_clz(n));
+    for (int64_t c = threadIdx.x; c < tot; c += BS) {
+        const int i = (int)(c % s), j = (int)(c / s) - 1;
+        double wxv = 0.0, wyv = 0.0;
+        if (i < n && j >= 0 && j <= n) {  // edge (i,j)-(i+1,j)
+            const double lo = j < n ? (double)ke[2 * (j * n + i)] : 0.0;
+            const double up = j > 0 ? (double)ke[2 * ((j - 1) * n + i) + 1] : 0.0;
+            wxv = 0.5 * (lo + up);
+        }
+        if (j >= 0 && j < n) {  // edge (i,j)-(i,j+1)
+            const double lo = i > 0 ? (double)ke[2 * (j * n + i - 1)] : 0.0;
+            const double up = i < n ? (double)ke[2 * (j * n + i) + 1] : 0.0;
+            wyv = 0.5 * (lo + up);
+        }
+        L.wx[c] = wxv;
+        L.wy[c] = wyv;
+    }
+}
+
+// coefficients of level Lc = Lf - 1: each coarse triangle averages its four children
+template <int BS, typename KT>
+__device__ void flow_coarsen(const KT* __restrict__ kf, double* __restrict__ kc, int nc)
+{
+    const int nf = 2 * nc;
+    for (int t = threadIdx.x; t < nc * nc; t += BS) {
+        const int I = t % nc, J = t / nc;
+        auto lo = [&](int i, int j) { return (double)kf[2 * (j * nf + i)]; };
+        auto up = [&](int i, int j) { return (double)kf[2 * (j * nf + i) + 1]; };
+        const int i0 = 2 * I, j0 = 2 * J;
+        kc[2 * t] = 0.25 * (lo(i0, j0) + lo(i0 + 1, j0) + lo(i0 + 1, j0 + 1) + up(i0 + 1, j0));
+        kc[2 * t + 1] = 0.25 * (up(i0, j0) + up(i0, j0 + 1) + up(i0 + 1, j0 + 1) + lo(i0, j0 + 1));
+    }
+}
+
+template <int BS>
+__device__ void smooth(const FLv& L, int col)
+{
+    FLOW_FOR_UNK(L.n, {
+        if (((i + j) & 1) != col) continue;
+        L.x[c] = (L.b[c] + fnb(L, L.x, c)) / fdiag(L, c);
+    })
+    __syncthreads();
+}
+
+// t = b - A x on the unknowns (t stays 0 elsewhere)
+template <int BS>
+__device__ void residual(const FLv& L)
+{
+    FLOW_FOR_UNK(L.n, { L.t[c] = L.b[c] - (fdiag(L, c) * L.x[c] - fnb(L, L.x, c)); })
+    __syncthreads();
+}
+
+// C.b = P^T F.t, C.x = 0
+template <int BS>
+__device__ void restrict_to(const FLv& F, const FLv& C)
+{
+    const int fs = F.s;
+    FLOW_FOR_UNK(C.n, {
+        const int f = (2 * j + 1) * fs + 2 * i;
+        const double* t = F.t;
+        C.b[c] = t[f] + 0.5 * (t[f - 1] + t[f + 1] + t[f - fs] + t[f + fs] + t[f + fs + 1] + t[f - fs - 1]);
+        C.x[c] = 0.0;
+    })
+    __syncthreads();
+}
+
+// F.x += P C.x
+template <int BS>
+__device__ void prolong_add(const FLv& C, const FLv& F)
+{
+    const int cs = C.s;
+    FLOW_FOR_UNK(F.n, {
+        const int I = i >> 1, Jc = j >> 1;
+        const int q = (Jc + 1) * cs + I;
+        double v;
+        if (!(i & 1) && !(j & 1)) v = C.x[q];
+        else if ((i & 1) && !(j & 1)) v = 0.5 * (C.x[q] + C.x[q + 1]);
+        else if (!(i & 1)) v = 0.5 * (C.x[q] + C.x[q + cs]);
+        else v = 0.5 * (C.x[q] + C.x[q + cs + 1]);
+        F.x[c] += v;
+    })
+    __syncthreads();
+}
+
+// exact solve at h = 1/2: unknowns (1,0), (1,1), (1,2), a tridiagonal system
+template <int BS>
+__device__ void coarsest(const FLv& L)
+{
+    if (threadIdx.x == 0) {
+        const int s = L.s, c0 = s + 1, c1 = 2 * s + 1, c2 = 3 * s + 1;
+        const double d0 = fdiag(L, c0), d1 = fdiag(L, c1), d2 = fdiag(L, c2);
+        const double e0 = L.wy[c0], e1 = L.wy[c1];
+        // forward elimination of -e x_{k-1} + d x_k - e' x_{k+1} = b_k
+        const double g0 = d0, y0 = L.b[c0];
+        const double g1 = d1 - e0 * e0 / g0, y1 = L.b[c1] + e0 * y0 / g0;
+        const double g2 = d2 - e1 * e1 / g1, y2 = L.b[c2] + e1 * y1 / g1;
+        const double x2 = y2 / g2;
+        const double x1 = (y1 + e1 * x2) / g1;
+        const double x0 = (y0 + e0 * x1) / g0;
+        L.x[c0] = x0;
+        L.x[c1] = x1;
+        L.x[c2] = x2;
+    }
+    __syncthreads();
+}
+
+// z = V r on the fine level l
+template <int BS>
+__device__ void flow_vcycle(double* slot, int l, int nu)
+{
+    const FLv F = flevel(slot, l, l);
+    FLOW_FOR_UNK(F.n, { F.x[c] = 0.0; })
+    __syncthreads();
+    if (l == 1) {
+        coarsest<BS>(F);
+        return;
+    }
+    for (int L = l; L >= 2; --L) {
+        const FLv V = flevel(slot, l, L);
+        for (int k = 0; k < nu; ++k) {
+            smooth<BS>(V, 0);
+            smooth<BS>(V, 1);
+        }
+        residual<BS>(V);
+        restrict_to<BS>(V, flevel(slot, l, L - 1));
+    }
+    coarsest<BS>(flevel(slot, l, 1));
+    for (int L = 2; L <= l; ++L) {
+        const FLv V = flevel(slot, l, L);
+        prolong_add<BS>(flevel(slot, l, L - 1), V);
+        for (int k = 0; k < nu; ++k) {
+            smooth<BS>(V, 1);
+            smooth<BS>(V, 0);
+        }
+    }
+}
+
+struct FlowParams {
+    int l;
+    int64_t N;
+    const int64_t* N_dev;
+    const double* kappa;  // N x n_e
+    double* ws;
+    int64_t slot_elems;
+    double* G;
+    double* p_out;
+    int8_t* status;
+    int32_t* iters;
+    const double* y;
+    double* phi;
+    const int32_t* obs_idx;
+    const double* obs_w;
+    int nobs;
+    double inv_sigma, tol2;
+    int max_iters, nu;
+};
+
+template <int BS>
+__global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
+{
+    __shared__ double red[BS / 64];
+    const int l = P.l, n = 1 << l, s = n + 1;
+    const int64_t ne = int64_t(2) << (2 * l), f = fsz(l);
+    const int64_t NN = P.N_dev ? min(P.N, *P.N_dev) : P.N;
+    double* slot = P.ws + (int64_t)blockIdx.x * P.slot_elems;
+    double* U = slot + F_U * f;
+    double* R = slot + F_R * f;
+    double* Z = slot + F_Z * f;
+    double* Pp = slot + F_P * f;
+    double* Q = slot + F_Q * f;
+    const FLv F = flevel(slot, l, l);
+    for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
+        const double* kap = P.kappa + q * ne;
+        // set-up: zero the arrays, weights of every level, the lifted right-hand side
+        zero_all<BS>(slot, F_COUNT * f);
+        for (int L = l - 1; L >= 1; --L) zero_all<BS>(slot + coarse_base(l, L), C_COUNT * fsz(L));
+        __syncthreads();
+        flow_weights<BS>(F, kap);
+        if (l >= 2) flow_coarsen<BS>(kap, flevel(slot, l, l - 1).kc, n / 2);
+        __syncthreads();
+        for (int L = l - 1; L >= 1; --L) {
+            const FLv C = flevel(slot, l, L);
+            flow_weights<BS>(C, C.kc);
+            if (L >= 2) flow_coarsen<BS>(C.kc, flevel(slot, l, L - 1).kc, C.n / 2);
+            __syncthreads();
+        }
+        FLOW_FOR_UNK(n, { R[c] = i == n - 1 ? F.wx[c] : 0.0; })
+        __syncthreads();
+        // PCG
+        flow_vcycle<BS>(slot, l, P.nu);
+        double rz = 0.0;
+        FLOW_FOR_UNK(n, {
+            rz += R[c] * Z[c];
+            Pp[c] = Z[c];
+        })
+        rz = block_sum<BS>(rz, red);
+        const double rz0 = rz;
+        int8_t st = 1;
+        int it = 0;
+        if (!(rz0 > 0.0)) st = isfinite(rz0) ? 0 : 2;
+        while (st == 1 && it < P.max_iters) {
+            ++it;
+            double pq = 0.0;
+            FLOW_FOR_UNK(n, {
+                const double v = fdiag(F, c) * Pp[c] - fnb(F, Pp, c);
+                Q[c] = v;
+                pq += Pp[c] * v;
+            })
+            pq = block_sum<BS>(pq, red);
+            const double alpha = rz / pq;
+            FLOW_FOR_UNK(n, {
+                U[c] += alpha * Pp[c];
+                R[c] -= alpha * Q[c];
+            })
+            __syncthreads();
+            flow_vcycle<BS>(slot, l, P.nu);
+            double rzn = 0.0;
+            FLOW_FOR_UNK(n, { rzn += R[c] * Z[c]; })
+            rzn = block_sum<BS>(rzn, red);
+            if (!isfinite(rzn) || !isfinite(alpha)) { st = 2; break; }
+            if (rzn <= P.tol2 * rz0) { st = 0; break; }
+            const double beta = rzn / rz;
+            rz = rzn;
+            FLOW_FOR_UNK(n, { Pp[c] = Z[c] + beta * Pp[c]; })
+            __syncthreads();
+        }
+        // the Dirichlet column i = n holds 1; observe and store
+        for (int j = threadIdx.x; j <= n; j += BS) U[(j + 1) * s + n] = 1.0;
+        __syncthreads();
+        double ph = 0.0;
+        for (int o = threadIdx.x; o < P.nobs; o += BS) {
+            double g = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) g += P.obs_w[3 * o + k] * U[P.obs_idx[3 * o + k]];
+            P.G[q * P.nobs + o] = g;
+            if (P.y) {
+                const double r = (P.y[o] - g) * P.inv_sigma;
+                ph += r * r;
+            }
+        }
+        if (P.p_out) {
+            double* po = P.p_out + q * (int64_t)(n - 1) * (n + 1);
+            FLOW_FOR_UNK(n, { po[t_] = U[c]; })
+        }
+        if (P.y) ph = block_sum<BS>(ph, red);
+        if (threadIdx.x == 0) {
+            if (P.status) P.status[q] = st;
+            if (P.iters) P.iters[q] = it;
+            if (P.phi) P.phi[q] = 0.5 * ph;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int64_t flow_unknowns(int l) { return ((int64_t(1) << l) - 1) * ((int64_t(1) << l) + 1); }
+
+int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
+{
+    if (a.N == 0) return MLS2MC_OK;
+    MLS_REQUIRE(!a.kappa_f32, "flow cell: FP64 coefficients only");
+    const int l = a.l;
+    int64_t slot = flow_slot(l);
+    slot = (slot + 31) & ~int64_t(31);
+    int bs = ctx->solver_block[l] ? ctx->solver_block[l] : (l <= 5 ? 256 : (l == 6 ? 512 : 1024));
+    int64_t grid = ctx->solver_grid[l] ? ctx->solver_grid[l] : (int64_t)ctx->n_cu * 4;
+    const int64_t cap = (int64_t)((16ull << 30) / (slot * sizeof(double)));
+    if (grid > cap) grid = cap;
+    if (grid > a.N) grid = a.N;
+    if (grid < 1) grid = 1;
+    MLS_TRY(ctx->ws_solver.ensure((size_t)grid * slot * sizeof(double)));
+    FlowParams P;
+    P.l = l; P.N = a.N; P.N_dev = a.N_dev; P.kappa = (const double*)a.kappa;
+    P.ws = ctx->ws_solver.as<double>(); P.slot_elems = slot;
+    P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
+    P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w; P.nobs = ctx->nobs;
+    P.inv_sigma = 1.0 / ctx->prob.sigma_n;
+    P.tol2 = ctx->rtol * ctx->rtol;
+    P.max_iters = ctx->max_iters;
+    P.nu = ctx->solver_nu[l] > 0 ? ctx->solver_nu[l] : 1;
+    ProfRec rec;
+    if (ctx->prof_on) {
+        if (!P.iters) {
+            MLS_TRY(ctx->ws_prof.ensure(sizeof(int32_t) * (size_t)a.N));
+            P.iters = ctx->ws_prof.as<int32_t>();
+        }
+        MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
+    }
+    dim3 g((unsigned)grid);
+    switch (bs) {
+        case 64: flow_solve_kernel<64><<<g, 64, 0, s>>>(P); break;
+        case 128: flow_solve_kernel<128><<<g, 128, 0, s>>>(P); break;
+        case 256: flow_solve_kernel<256><<<g, 256, 0, s>>>(P); break;
+        case 512: flow_solve_kernel<512><<<g, 512, 0, s>>>(P); break;
+        case 1024: flow_solve_kernel<1024><<<g, 1024, 0, s>>>(P); break;
+        default: MLS_REQUIRE(false, "flow cell: unsupported block size");
+    }
+    MLS_CHECK_HIP(hipGetLastError());
+    if (ctx->prof_on) {
+        MLS_TRY(prof_end(ctx, MLS2MC_PROF_SOLVE, l, rec, s));
+        MLS_TRY(launch_reduce_i32(a.N, P.iters, nullptr, ctx->d_prof_iters + 2 * l, s));
+    }
+    return MLS2MC_OK;
+}
+
+}  // namespace mls

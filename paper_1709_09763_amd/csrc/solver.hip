@@ -989,6 +989,7 @@ static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* a
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
 {
     if (a.N == 0) return MLS2MC_OK;
+    if (ctx->prob.bc == MLS2MC_BC_FLOW_CELL) return launch_flow_solve(ctx, a, s);
     const int l = a.l;
     const bool mixed = a.kappa_f32;
     const int dev_cus = ctx->n_cu;
@@ -1071,6 +1072,8 @@ int build_obs_tables(mls2mc_ctx* ctx)
     ctx->nobs = nobs;
     for (int l = ctx->prob.l_min; l <= ctx->prob.l_max; ++l) {
         const int n = 1 << l, s = n + 1;
+        // the flow-cell layout has a ghost row below j = 0
+        const int row0 = ctx->prob.bc == MLS2MC_BC_FLOW_CELL ? s : 0;
         std::vector<int32_t> idx(3 * nobs);
         std::vector<double> w(3 * nobs);
         for (int bb = 1; bb <= m; ++bb)
@@ -1091,7 +1094,7 @@ int build_obs_tables(mls2mc_ctx* ctx)
                     nodes[1] = (j + 1) * s + i + 1; nodes[2] = (j + 1) * s + i;
                     wt[0] = 1.0 - eta; wt[1] = xi; wt[2] = eta - xi;
                 }
-                for (int k = 0; k < 3; ++k) { idx[3 * o + k] = nodes[k]; w[3 * o + k] = wt[k]; }
+                for (int k = 0; k < 3; ++k) { idx[3 * o + k] = row0 + nodes[k]; w[3 * o + k] = wt[k]; }
             }
         MLS_CHECK_HIP(hipMalloc(&ctx->obs[l].idx, sizeof(int32_t) * idx.size()));
         MLS_CHECK_HIP(hipMalloc(&ctx->obs[l].w, sizeof(double) * w.size()));
@@ -1252,6 +1255,7 @@ int enqueue_list(mls2mc_ctx* ctx, const std::vector<ListChunk>& chunks, hipStrea
 
 int forward_list(mls2mc_ctx* ctx, const std::vector<FwdItem>& items, hipStream_t s)
 {
+    MLS_REQUIRE(ctx->prob.bc == MLS2MC_BC_DIRICHLET, "batched forwards: Dirichlet problem only");
     std::vector<ListChunk> chunks;
     MLS_TRY(prepare_list(ctx, items, chunks, s));
     return enqueue_list(ctx, chunks, s);

@@ -47,6 +47,7 @@ def test_size_queries(L):
     ("l_min", 0, "l_min"), ("l_max", 11, "l_max"), ("K", 0, "K"), ("sigma2", -1.0, "sigma2"),
     ("corr_len", 0.0, "corr_len"), ("m", 0, "m"), ("sigma_n", 0.0, "sigma_n"),
     ("precision", 7, "precision"), ("cov", 5, "covariance"), ("kl_quad", 16, "kl_quad"),
+    ("bc", 3, "boundary-value"),
 ])
 def test_create_rejects_bad_problems(L, field, val, msg):
     import paper_1709_09763_amd as P
@@ -57,6 +58,14 @@ def test_create_rejects_bad_problems(L, field, val, msg):
     assert rc == 1
     assert h.value is None
     assert msg in P.mls2mc_last_error()
+
+
+def test_flow_cell_is_fp64_only(L):
+    import paper_1709_09763_amd as P
+    pr = P.Problem(3, 6, 10, 1.0, 0.3, 3, 0.01, P.MIXED, 0.0, 0, 0, 0, P.BC_FLOW_CELL)
+    h = C.c_void_p()
+    assert L.mls2mc_create(C.byref(pr), C.byref(h)) == 1
+    assert "FP64 only" in P.mls2mc_last_error()
 
 
 @pytest.mark.parametrize("quad,K,msg", [(15, 10, "kl_quad"), (2, 1, "kl_quad"), (130, 10, "kl_quad"),

@@ -1,0 +1,134 @@
+"""GPU parity of the flow-cell forward problem (Sec. 5, Example 5.3: p = 0 at
+x1 = 0, p = 1 at x1 = 1, no flow through x2 = 0 and x2 = 1, no source)
+against the oracle's P1 assembly and sparse direct solve.
+
+Bars (the solver stops at a preconditioned residual of 1e-11 relative): G
+and the nodal pressure rel 1e-10 for moderate coefficients, 1e-9 for
+strong contrast; exact cases (p = x1) to 1e-10."""
+import numpy as np
+import pytest
+import torch
+
+import oracle  # noqa: F401  (builds the C oracle for the shared helpers)
+from oracle import flowcell as fc
+from oracle import matern
+import paper_1709_09763_amd as P
+from tests import inputs
+from tests.gpu_util import case, device, host, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(l_min, l_max, K=4, m=5, corr=0.3, **kw):
+    return P.Context(l_min, l_max, K, 1.0, corr, m, 0.01, bc=P.BC_FLOW_CELL, **kw)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 6])
+def test_flowcell_forward_field_parity(l):
+    device()
+    N, m = 13, 5
+    case(f"flowcell forward_field l={l} N={N}")
+    ctx = _ctx(l, l, m=m)
+    kap = inputs.kappa_batch(300 + l, N, 2 * 4 ** l, spread=1.0)
+    G, p, st, it = ctx.forward_field(l, to_dev(kap), want_p=True)
+    Gr, pr = fc.forward_kappa(l, m, kap, want_p=True)
+    assert (host(st) == 0).all()
+    assert p.shape == (N, fc.n_unknowns(l))
+    assert rel_err(host(G), Gr) < 1e-10
+    assert rel_err(host(p), pr) < 1e-10
+    print(f"  iters {host(it).tolist()}")
+
+
+def test_flowcell_exact_linear_pressure():
+    """coefficients constant per row of cells: the pressure is x1 exactly"""
+    device()
+    l, m = 5, 7
+    n = 1 << l
+    case("flowcell layered coefficients")
+    ctx = _ctx(l, l, m=m)
+    rows = np.exp(np.random.default_rng(3).normal(size=n))
+    kap = rows[(np.arange(2 * n * n) // 2) // n][None, :]
+    G, p, st, it = ctx.forward_field(l, to_dev(kap), want_p=True)
+    x1 = np.tile(np.arange(1, n) / n, n + 1)
+    assert np.abs(host(p)[0] - x1).max() < 1e-10
+    a = np.tile(np.arange(1, m + 1), m) / (m + 1)
+    assert np.abs(host(G)[0] - a).max() < 1e-10
+
+
+def test_flowcell_strong_contrast():
+    device()
+    l, N, m = 6, 6, 7
+    case(f"flowcell contrast l={l}")
+    ctx = _ctx(l, l, m=m)
+    kap = inputs.kappa_batch(9, N, 2 * 4 ** l, spread=2.0)
+    G, p, st, it = ctx.forward_field(l, to_dev(kap), want_p=True)
+    Gr, pr = fc.forward_kappa(l, m, kap, want_p=True)
+    assert (host(st) == 0).all()
+    assert rel_err(host(p), pr) < 1e-9
+
+
+def test_flowcell_example_5_3_matern_forward():
+    """Example 5.3's setting: Matern prior (lam = 0.1, nu = 3/2), 49
+    observations; theta -> G through the GPU's KL GEMM and flow-cell solver
+    against the oracle's basis and solve."""
+    device()
+    K, quad, m = 60, 32, 7
+    case("flowcell example 5.3 matern forward")
+    ctx = P.Context(4, 6, K, 1.0, 0.1, m, 0.045, cov=P.COV_MATERN32, kl_quad=quad, bc=P.BC_FLOW_CELL)
+    lam_o, V, _ = matern.modes(K, quad, 0.1)
+    th = inputs.theta_batch(21, 9, K)
+    for l in (4, 6):
+        G, st, it = ctx.forward(l, to_dev(th), with_stats=True)
+        B = matern.extend(matern.centroids(l), lam_o, V, quad, 0.1)
+        Gr = fc.forward_kappa(l, m, np.exp(th @ B))
+        assert (host(st) == 0).all()
+        assert rel_err(host(G), Gr) < 1e-9
+
+
+def test_flowcell_full_size_sampled():
+    """h = 1/256 (Example 5.3's finest level): sampled particles one by one"""
+    device()
+    l, N, m = 8, 96, 7
+    case(f"flowcell full-size l={l} N={N}")
+    ctx = _ctx(l, l, m=m)
+    kap = inputs.kappa_batch(77, N, 2 * 4 ** l, spread=1.0)
+    G, p, st, it = ctx.forward_field(l, to_dev(kap), want_p=False)
+    assert (host(st) == 0).all()
+    idx = [0, N // 2, N - 1]
+    Gr = fc.forward_kappa(l, m, kap[idx])
+    assert rel_err(host(G)[idx], Gr) < 1e-10
+    print(f"  iters mean {host(it).mean():.1f}")
+
+
+def test_flowcell_edge_cases():
+    device()
+    case("flowcell max_iters=1 -> status 1")
+    ctx = _ctx(5, 5, max_iters=1)
+    kap = inputs.kappa_batch(4, 3, 2 * 4 ** 5, spread=1.0)
+    G, p, st, it = ctx.forward_field(5, to_dev(kap))
+    assert (host(st) == 1).all() and (host(it) == 1).all()
+    case("flowcell non-finite coefficient -> status 2")
+    ctx2 = _ctx(4, 4)
+    kap = inputs.kappa_batch(5, 3, 2 * 4 ** 4)
+    kap[2, 11] = np.nan
+    G, p, st, it = ctx2.forward_field(4, to_dev(kap))
+    assert host(st).tolist() == [0, 0, 2]
+    case("flowcell N=0")
+    G, p, st, it = ctx2.forward_field(4, torch.zeros((0, 2 * 4 ** 4), dtype=torch.float64, device="cuda:0"))
+    assert G.shape == (0, 25)
+    case("flowcell batched entry points refuse")
+    th = to_dev(inputs.theta_batch(1, 4, 4))
+    Gb = torch.empty((4, 25), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(P.Mls2mcError):
+        P.mls2mc_forward_batch(ctx2.h, [dict(l=4, theta=th, G_out=Gb)])
+
+
+def test_flowcell_run_completes():
+    device()
+    case("flowcell run")
+    ctx = _ctx(3, 5, K=10, m=5, corr=0.3)
+    th_true = inputs.theta_batch(8, 1, 10)
+    y = host(ctx.forward(5, to_dev(th_true)))[0] + 0.01 * np.random.default_rng(2).standard_normal(25)
+    res = ctx.run(to_dev(y), J=256, J_tilde=64, seed=5)
+    assert res["final_level"] == 5 and res["final_beta"] == 1.0 and res["not_converged"] == 0
+    assert np.isfinite(res["log_Z"])
