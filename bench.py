@@ -81,17 +81,17 @@ def solve_bytes(l, nobs, particles, iters, b_iter):
 
 
 def flow_solve_bytes(l, nobs, particles, iters, nu):
-    """streaming model of the flow-cell solver (separate passes, each array
-    read or written once per pass), per fine unknown and PCG iteration: the
-    operator apply 32 B, the x/r update 48 B, <r,z> and the p update 40 B,
-    and a V-cycle of 78 + 160 nu B on the fine level plus a third of that on
-    the coarse ones; per solve also the coefficients, the zeroed slot and the
+    """streaming model of the flow-cell solver's fused passes, per fine
+    unknown and PCG iteration: p = z + beta p_old with q = A p 48 B, the x/r
+    update with the first red sweep 72 B, and per level a V-cycle of
+    170 + 160 (nu - 1) B (black sweep 40, restriction of the red residuals 32,
+    prolongation 18, black and red sweeps 80), a third more for the coarse
+    levels; per solve also the coefficients, the zeroed slot and the
     observations"""
     n = 1 << l
     M = (n - 1) * (n + 1)
-    vc = 78 + 160 * nu
-    b_iter = 32 + 48 + 40 + vc * 4.0 / 3.0
-    slot = (7 * (n + 1) * (n + 3)) * 4.0 / 3.0 + 2 * n * n * 2.0 / 3.0
+    b_iter = 48 + 72 + (170 + 160 * (nu - 1)) * 4.0 / 3.0
+    slot = (8 * (n + 1) * (n + 3)) * 4.0 / 3.0 + 2 * n * n * 2.0 / 3.0
     return particles * (8 * 2 * n * n + 8 * slot + 32 * nobs) + iters * b_iter * M
 
 

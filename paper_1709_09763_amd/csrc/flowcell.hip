@@ -16,10 +16,16 @@
 // Dirichlet columns.
 //
 // V-cycle: red-black Gauss-Seidel (red first down, black first up, so the
-// cycle is symmetric), residual, restriction by the transpose of P1
-// interpolation, coarse coefficients averaged over the four children of
-// each coarse triangle (the Galerkin operator of the nested meshes), an exact
+// cycle is symmetric), restriction by the transpose of P1 interpolation,
+// coarse coefficients averaged over the four children of each coarse
+// triangle (the Galerkin operator of the nested meshes), an exact
 // tridiagonal solve at h = 1/2 (three unknowns on the column i = 1).
+//
+// Fused passes: p = z + beta p_old is formed inside the operator apply
+// (double-buffered p); the x/r update also does the V-cycle's first red
+// sweep from z = 0; the residual, which after a black sweep lives on the red
+// nodes only, is formed inside the restriction, which also does the coarse
+// level's first red sweep; <r, z> is summed in the last red sweep.
 #include "common.h"
 
 namespace mls {
@@ -33,8 +39,8 @@ __host__ __device__ inline int64_t fsz(int L)
 }
 
 // slot: fine arrays, then per coarse level l-1 .. 1 its arrays and coefficients
-enum { F_U = 0, F_R, F_Z, F_P, F_Q, F_WX, F_WY, F_COUNT };
-enum { C_X = 0, C_B, C_T, C_WX, C_WY, C_COUNT };
+enum { F_U = 0, F_R, F_Z, F_P, F_P2, F_Q, F_WX, F_WY, F_COUNT };
+enum { C_X = 0, C_B, C_WX, C_WY, C_COUNT };
 
 __host__ __device__ inline int64_t coarse_base(int l, int L)
 {
@@ -46,12 +52,12 @@ __host__ __device__ inline int64_t coarse_base(int l, int L)
 __host__ __device__ inline int64_t flow_slot(int l) { return coarse_base(l, 0); }
 
 struct FLv {
-    double *x, *b, *t, *wx, *wy, *kc;
+    double *x, *b, *wx, *wy, *kc;
     int n, s;
 };
 
 // level L of the hierarchy of the slot (L = l: the fine level's V-cycle
-// arrays, x = Z, b = R, t = Q)
+// arrays, x = Z, b = R)
 __device__ inline FLv flevel(double* slot, int l, int L)
 {
     FLv v;
@@ -61,7 +67,6 @@ __device__ inline FLv flevel(double* slot, int l, int L)
     if (L == l) {
         v.x = slot + F_Z * f;
         v.b = slot + F_R * f;
-        v.t = slot + F_Q * f;
         v.wx = slot + F_WX * f;
         v.wy = slot + F_WY * f;
         v.kc = nullptr;
@@ -69,7 +74,6 @@ __device__ inline FLv flevel(double* slot, int l, int L)
         double* base = slot + coarse_base(l, L);
         v.x = base + C_X * f;
         v.b = base + C_B * f;
-        v.t = base + C_T * f;
         v.wx = base + C_WX * f;
         v.wy = base + C_WY * f;
         v.kc = base + C_COUNT * f;
@@ -150,24 +154,42 @@ __device__ void smooth(const FLv& L, int col)
     __syncthreads();
 }
 
-// t = b - A x on the unknowns (t stays 0 elsewhere)
-template <int BS>
-__device__ void residual(const FLv& L)
+// residual b - A x at an unknown node f
+__device__ __forceinline__ double fres(const FLv& F, int f)
 {
-    FLOW_FOR_UNK(L.n, { L.t[c] = L.b[c] - (fdiag(L, c) * L.x[c] - fnb(L, L.x, c)); })
-    __syncthreads();
+    return F.b[f] - (fdiag(F, f) * F.x[f] - fnb(F, F.x, f));
 }
 
-// C.b = P^T F.t, C.x = 0
+// ends a red sweep with sum_c b_c x_c over the unknowns (x final everywhere)
 template <int BS>
-__device__ void restrict_to(const FLv& F, const FLv& C)
+__device__ double smooth_red_dot(const FLv& L, double* red)
 {
-    const int fs = F.s;
+    double d = 0.0;
+    FLOW_FOR_UNK(L.n, {
+        double x = L.x[c];
+        if (!((i + j) & 1)) {
+            x = (L.b[c] + fnb(L, L.x, c)) / fdiag(L, c);
+            L.x[c] = x;
+        }
+        d += L.b[c] * x;
+    })
+    return block_sum<BS>(d, red);
+}
+
+// C.b = P^T (F.b - A F.x) right after a black sweep: the black residuals
+// vanish, so the coarse node (I, J) gathers the red residuals at (2I, 2J),
+// (2I+1, 2J+1) and (2I-1, 2J-1).  C.x gets the coarse first red sweep from 0.
+template <int BS>
+__device__ void restrict_red(const FLv& F, const FLv& C)
+{
+    const int fs = F.s, nf = F.n;
     FLOW_FOR_UNK(C.n, {
         const int f = (2 * j + 1) * fs + 2 * i;
-        const double* t = F.t;
-        C.b[c] = t[f] + 0.5 * (t[f - 1] + t[f + 1] + t[f - fs] + t[f + fs] + t[f + fs + 1] + t[f - fs - 1]);
-        C.x[c] = 0.0;
+        double v = fres(F, f);
+        if (2 * j + 1 <= nf) v += 0.5 * fres(F, f + fs + 1);
+        if (j >= 1) v += 0.5 * fres(F, f - fs - 1);
+        C.b[c] = v;
+        C.x[c] = ((i + j) & 1) ? 0.0 : v / fdiag(C, c);
     })
     __syncthreads();
 }
@@ -212,35 +234,39 @@ __device__ void coarsest(const FLv& L)
     __syncthreads();
 }
 
-// z = V r on the fine level l
+// z = V r on the fine level l whose first red sweep (from z = 0) is done;
+// returns <r, z>
 template <int BS>
-__device__ void flow_vcycle(double* slot, int l, int nu)
+__device__ double flow_vcycle(double* slot, int l, int nu, double* red)
 {
     const FLv F = flevel(slot, l, l);
-    FLOW_FOR_UNK(F.n, { F.x[c] = 0.0; })
-    __syncthreads();
     if (l == 1) {
         coarsest<BS>(F);
-        return;
+        double d = 0.0;
+        FLOW_FOR_UNK(F.n, { d += F.b[c] * F.x[c]; })
+        return block_sum<BS>(d, red);
     }
     for (int L = l; L >= 2; --L) {
         const FLv V = flevel(slot, l, L);
-        for (int k = 0; k < nu; ++k) {
+        smooth<BS>(V, 1);
+        for (int k = 1; k < nu; ++k) {
             smooth<BS>(V, 0);
             smooth<BS>(V, 1);
         }
-        residual<BS>(V);
-        restrict_to<BS>(V, flevel(slot, l, L - 1));
+        restrict_red<BS>(V, flevel(slot, l, L - 1));
     }
     coarsest<BS>(flevel(slot, l, 1));
+    double dot = 0.0;
     for (int L = 2; L <= l; ++L) {
         const FLv V = flevel(slot, l, L);
         prolong_add<BS>(flevel(slot, l, L - 1), V);
         for (int k = 0; k < nu; ++k) {
             smooth<BS>(V, 1);
-            smooth<BS>(V, 0);
+            if (L == l && k == nu - 1) dot = smooth_red_dot<BS>(V, red);
+            else smooth<BS>(V, 0);
         }
     }
+    return dot;
 }
 
 struct FlowParams {
@@ -274,7 +300,6 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
     double* U = slot + F_U * f;
     double* R = slot + F_R * f;
     double* Z = slot + F_Z * f;
-    double* Pp = slot + F_P * f;
     double* Q = slot + F_Q * f;
     const FLv F = flevel(slot, l, l);
     for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
@@ -292,45 +317,54 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
             if (L >= 2) flow_coarsen<BS>(C.kc, flevel(slot, l, L - 1).kc, C.n / 2);
             __syncthreads();
         }
-        FLOW_FOR_UNK(n, { R[c] = i == n - 1 ? F.wx[c] : 0.0; })
+        // lifted right-hand side; z starts with the V-cycle's first red sweep
+        FLOW_FOR_UNK(n, {
+            const double r = i == n - 1 ? F.wx[c] : 0.0;
+            R[c] = r;
+            Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F, c);
+        })
         __syncthreads();
         // PCG
-        flow_vcycle<BS>(slot, l, P.nu);
-        double rz = 0.0;
-        FLOW_FOR_UNK(n, {
-            rz += R[c] * Z[c];
-            Pp[c] = Z[c];
-        })
-        rz = block_sum<BS>(rz, red);
+        double rz = flow_vcycle<BS>(slot, l, P.nu, red);
         const double rz0 = rz;
+        double beta = 0.0;
+        double* Po = slot + F_P * f;
+        double* Pn = slot + F_P2 * f;
         int8_t st = 1;
         int it = 0;
         if (!(rz0 > 0.0)) st = isfinite(rz0) ? 0 : 2;
         while (st == 1 && it < P.max_iters) {
             ++it;
+            // p = z + beta p_old and q = A p in one pass
             double pq = 0.0;
             FLOW_FOR_UNK(n, {
-                const double v = fdiag(F, c) * Pp[c] - fnb(F, Pp, c);
-                Q[c] = v;
-                pq += Pp[c] * v;
+                const double pc = Z[c] + beta * Po[c];
+                const double nb = F.wx[c - 1] * (Z[c - 1] + beta * Po[c - 1]) +
+                                  F.wx[c] * (Z[c + 1] + beta * Po[c + 1]) +
+                                  F.wy[c - s] * (Z[c - s] + beta * Po[c - s]) +
+                                  F.wy[c] * (Z[c + s] + beta * Po[c + s]);
+                const double qv = fdiag(F, c) * pc - nb;
+                Pn[c] = pc;
+                Q[c] = qv;
+                pq += pc * qv;
             })
             pq = block_sum<BS>(pq, red);
             const double alpha = rz / pq;
             FLOW_FOR_UNK(n, {
-                U[c] += alpha * Pp[c];
-                R[c] -= alpha * Q[c];
+                U[c] += alpha * Pn[c];
+                const double r = R[c] - alpha * Q[c];
+                R[c] = r;
+                Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F, c);
             })
             __syncthreads();
-            flow_vcycle<BS>(slot, l, P.nu);
-            double rzn = 0.0;
-            FLOW_FOR_UNK(n, { rzn += R[c] * Z[c]; })
-            rzn = block_sum<BS>(rzn, red);
+            const double rzn = flow_vcycle<BS>(slot, l, P.nu, red);
             if (!isfinite(rzn) || !isfinite(alpha)) { st = 2; break; }
             if (rzn <= P.tol2 * rz0) { st = 0; break; }
-            const double beta = rzn / rz;
+            beta = rzn / rz;
             rz = rzn;
-            FLOW_FOR_UNK(n, { Pp[c] = Z[c] + beta * Pp[c]; })
-            __syncthreads();
+            double* t = Po;
+            Po = Pn;
+            Pn = t;
         }
         // the Dirichlet column i = n holds 1; observe and store
         for (int j = threadIdx.x; j <= n; j += BS) U[(j + 1) * s + n] = 1.0;
