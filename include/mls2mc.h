@@ -216,6 +216,32 @@ int mls2mc_next_step(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, 
                      double tau_ess, double eps, double* out3, double* logw_out,
                      double* w_out, void* stream);
 
+/* ---- update-scheme decision (host function, no device work) ---- */
+#define MLS2MC_DECIDE_ITU 0     /* tempering update                        */
+#define MLS2MC_DECIDE_LU 1      /* level update                            */
+#define MLS2MC_DECIDE_DONE 2    /* finished: stop                          */
+#define MLS2MC_DECIDE_NEED_CV 3 /* cv_lu is needed: compute it, call again */
+
+/* The next update of the final update scheme (Sec. 4.4) and of the scheme
+ * with an adaptive maximum level (Sec. 4.5), as mls2mc_run takes it.
+ * beta: current inverse temperature; l, l_max: current and finest level;
+ * prev_lu: 1 if the previous update was a level update or there was none
+ * yet (the first update is a tempering update), else 0; scheme:
+ * MLS2MC_SCHEME_MLS2MC or MLS2MC_SCHEME_MLB (multilevel bridging: tempering
+ * up to beta = 1, then only level updates); cv_lu: coefficient of variation
+ * of the level-update weights exp(-beta (Phi_{l+1} - Phi_l)) on the
+ * look-ahead particles (mls2mc_next_step with mode CV_LU gives cv^2), or a
+ * negative value when not computed; tau_lu: level-update threshold; tau_min:
+ * the adaptive maximum level's threshold (0: off).
+ * Rules: at beta = 1 and l = l_max: DONE.  At beta = 1: with tau_min > 0,
+ * DONE when cv_lu < tau_min; otherwise LU.  Below beta = 1: ITU for
+ * multilevel bridging, at l = l_max, or after a level update; otherwise LU
+ * when cv_lu >= tau_lu, else ITU.  Returns NEED_CV when a rule needs cv_lu
+ * and it is negative; -1 on bad arguments (l > l_max, beta outside [0, 1],
+ * unknown scheme).                                                        */
+int mls2mc_decide(double beta, int l, int l_max, int prev_lu, int scheme, double cv_lu, double tau_lu,
+                  double tau_min);
+
 /* Multinomial resampling (Sec. 2.4) with an exact integer CDF: weights are
  * scaled by the power of two that brings max w into [1/2,1), quantised to
  * q_j = floor(w_j 2^(62 - ceil(log2 N))), prefix-summed in uint64; for each

@@ -13,6 +13,7 @@ KERNEL_PCN, KERNEL_RWM = 0, 1
 SCHEME_MLS2MC, SCHEME_MLB = 0, 1
 COV_SEPEXP, COV_MATERN32 = 0, 1
 BC_DIRICHLET, BC_FLOW_CELL = 0, 1
+DECIDE_ITU, DECIDE_LU, DECIDE_DONE, DECIDE_NEED_CV = 0, 1, 2, 3
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV", 5: "ESINGULAR"}
 
 
@@ -96,6 +97,8 @@ def lib():
         L.mls2mc_n_unknowns.argtypes = [C.c_int]
         L.mls2mc_ctx_n_unknowns.restype = C.c_int64
         L.mls2mc_ctx_n_unknowns.argtypes = [_vp, C.c_int]
+        L.mls2mc_decide.argtypes = [C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                    C.c_double]
         L.mls2mc_n_obs.argtypes = [_vp]
         L.mls2mc_create.argtypes = [C.POINTER(Problem), C.POINTER(_vp)]
         L.mls2mc_destroy.argtypes = [_vp]
@@ -156,6 +159,12 @@ def mls2mc_n_unknowns(l):
 
 def mls2mc_ctx_n_unknowns(h, l):
     return lib().mls2mc_ctx_n_unknowns(h, l)
+
+
+def mls2mc_decide(beta, l, l_max, prev_lu, scheme, cv_lu=-1.0, tau_lu=1.0, tau_min=0.0):
+    """next update of the update scheme: DECIDE_ITU, DECIDE_LU, DECIDE_DONE or DECIDE_NEED_CV"""
+    return lib().mls2mc_decide(float(beta), int(l), int(l_max), int(prev_lu), int(scheme), float(cv_lu),
+                               float(tau_lu), float(tau_min))
 
 
 def _check(rc, where):

@@ -13,6 +13,25 @@
 
 #include "common.h"
 
+extern "C" int mls2mc_decide(double beta, int l, int l_max, int prev_lu, int scheme, double cv_lu,
+                             double tau_lu, double tau_min)
+{
+    if (l > l_max || !(beta >= 0.0 && beta <= 1.0) ||
+        (scheme != MLS2MC_SCHEME_MLS2MC && scheme != MLS2MC_SCHEME_MLB))
+        return -1;
+    if (beta == 1.0) {
+        if (l == l_max) return MLS2MC_DECIDE_DONE;
+        if (tau_min > 0.0) {
+            if (cv_lu < 0.0) return MLS2MC_DECIDE_NEED_CV;
+            if (cv_lu < tau_min) return MLS2MC_DECIDE_DONE;
+        }
+        return MLS2MC_DECIDE_LU;
+    }
+    if (scheme == MLS2MC_SCHEME_MLB || l == l_max || prev_lu) return MLS2MC_DECIDE_ITU;
+    if (cv_lu < 0.0) return MLS2MC_DECIDE_NEED_CV;
+    return cv_lu < tau_lu ? MLS2MC_DECIDE_ITU : MLS2MC_DECIDE_LU;
+}
+
 namespace mls {
 
 enum { ST_PRIOR = 0, ST_RESAMPLE = 3, ST_PCN_XI = 4, ST_PCN_U = 5, ST_PCN_U2 = 6 };
@@ -253,22 +272,18 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
             *cv = std::sqrt(c2 > 0 ? c2 : 0.0);
             return MLS2MC_OK;
         };
-        if (beta == 1.0) {
-            if (cfg->tau_min > 0.0) {  // scheme u': stop when the level update would gain too little
-                double cv;
-                MLS_TRY(look_ahead(&cv));
-                checked = true;
-                if (cv < cfg->tau_min) break;
-            }
-            do_lu = true;
-        } else if (cfg->scheme == MLS2MC_SCHEME_MLB || l == ctx->prob.l_max || prev_lu) {
-            do_lu = false;
-        } else {
+        int dec = mls2mc_decide(beta, l, ctx->prob.l_max, prev_lu ? 1 : 0, cfg->scheme, -1.0, tau_lu,
+                                cfg->tau_min);
+        if (dec == MLS2MC_DECIDE_NEED_CV) {
             double cv;
             MLS_TRY(look_ahead(&cv));
             checked = true;
-            do_lu = !(cv < tau_lu);
+            dec = mls2mc_decide(beta, l, ctx->prob.l_max, prev_lu ? 1 : 0, cfg->scheme, cv, tau_lu,
+                                cfg->tau_min);
         }
+        MLS_REQUIRE(dec >= 0 && dec != MLS2MC_DECIDE_NEED_CV, "run: update-scheme decision failed");
+        if (dec == MLS2MC_DECIDE_DONE) break;
+        do_lu = dec == MLS2MC_DECIDE_LU;
         if (!do_lu) {
             MLS_TRY(launch_next_step(ctx, J, R.plo, 1.0, beta, tau_ess, eps, R.out3, nullptr, R.w, s));
             double h[3];
