@@ -12,9 +12,9 @@
 // A commutes with the reflections x1 -> 1 - x1 and x2 -> 1 - x2, so it splits
 // into four parity classes (+,+), (-,+), (+,-), (-,-) of (m/2)^2 unknowns each;
 // (+,-) is (-,+) with the coordinates swapped.  The three distinct classes are
-// solved separately by subspace iteration with Rayleigh-Ritz: the block
-// products A V run on the GPU, the orthonormalisation and the small dense
-// eigenproblems on the host.  The eigenvectors are then canonical: parity
+// solved separately, one host thread each, by subspace iteration with
+// Rayleigh-Ritz: the block products A V run on the GPU, the
+// orthonormalisation and the small dense eigenproblems on the host.  The eigenvectors are then canonical: parity
 // definite, swapped pairs with identical eigenvalues in class order, sign
 // fixed by a fixed generic vector.  The basis at the element centroids is the
 // Nystrom extension
@@ -23,6 +23,8 @@
 // on the FP64 matrix cores.
 #include <algorithm>
 #include <cmath>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -371,12 +373,31 @@ int build_matern_tables(mls2mc_ctx* ctx)
     struct Cand { double lam; int cls, j; };
     std::vector<Cand> cand;
     for (int round = 0; round < 16; ++round) {
+        // the classes are independent: one host thread each (the current
+        // device and the error message are per thread)
+        int rcs[4] = {MLS2MC_OK, MLS2MC_OK, MLS2MC_OK, MLS2MC_OK};
+        std::string errs[4];
+        std::vector<std::thread> workers;
         for (int c : {0, 1, 3})
-            if (todo[c]) {
-                MLS_TRY(solve_class(m, sc, p.sigma2 * w, cls_sx[c], cls_sy[c], need[c],
-                                    0x6d61746572ull + 977u * (unsigned)c + 131u * (unsigned)need[c], sol[c]));
-                todo[c] = false;
+            if (todo[c])
+                workers.emplace_back([&, c]() {
+                    if (hipSetDevice(ctx->device) != hipSuccess) {
+                        rcs[c] = MLS2MC_EDEVICE;
+                        errs[c] = "create: hipSetDevice failed in a Matern KL worker";
+                        return;
+                    }
+                    rcs[c] = solve_class(m, sc, p.sigma2 * w, cls_sx[c], cls_sy[c], need[c],
+                                         0x6d61746572ull + 977u * (unsigned)c + 131u * (unsigned)need[c], sol[c]);
+                    if (rcs[c] != MLS2MC_OK) errs[c] = mls2mc_last_error();
+                });
+        for (auto& t : workers) t.join();
+        for (int c : {0, 1, 3}) {
+            if (rcs[c] != MLS2MC_OK) {
+                set_error(errs[c]);
+                return rcs[c];
             }
+            todo[c] = false;
+        }
         cand.clear();
         for (int c : {0, 1, 3})
             for (int j = 0; j < sol[c].n; ++j) {
