@@ -177,27 +177,61 @@ int build_kl_tables(mls2mc_ctx* ctx)
 // 16w..16w+15 and four 16x16 accumulators.  Operand lanes: A[i][k] with
 // i = lane%16, k = lane/16; B[k][j] with j = lane%16, k = lane/16.  Result:
 // lane holds D[lane/16 + 4v][lane%16], v = 0..3 (FP64 accumulator layout).
+// The workgroup stages 16-deep k-chunks of its 64 theta rows and 64 basis
+// columns through LDS (coalesced loads, the next chunk prefetched into
+// registers while the current one feeds the MFMAs), so a global round trip
+// is paid once per 16 k instead of once per MFMA step.
+constexpr int kGemmKC = 16;
+struct GemmF64Smem {
+    double a[64][kGemmKC + 1];  // theta rows x k (padded against bank conflicts)
+    double b[kGemmKC][64 + 1];  // k x basis columns
+};
+
 template <bool EXP>
 __device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ theta, const double* __restrict__ B,
                                               double* __restrict__ out, int64_t N, int K, int64_t ne,
-                                              int64_t bx, int64_t by)
+                                              int64_t bx, int64_t by, GemmF64Smem& sm)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int64_t e0 = bx * 64;
-    const int64_t p0 = by * 64 + wv * 16;
-    const int64_t prow = p0 + r;
+    const int64_t pb = by * 64;
+    const int64_t p0 = pb + wv * 16;
     dbl4 acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + kq;
-        const double a = (prow < N && k < K) ? theta[prow * K + k] : 0.0;
+    // each thread moves 4 theta and 4 basis values per chunk
+    double ra[4], rb[4];
+    auto fetch = [&](int kc) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t e = e0 + c * 16 + r;
-            const double b = (k < K && e < ne) ? B[(int64_t)k * ne + e] : 0.0;
-            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) {
+            const int idx = tid + 256 * t;
+            const int row = idx >> 4, kk = idx & 15;          // theta: 64 rows x 16 k
+            const int k = kc + kk;
+            ra[t] = (pb + row < N && k < K) ? theta[(pb + row) * K + k] : 0.0;
+            const int kb = idx >> 6, col = idx & 63;         // basis: 16 k x 64 columns
+            const int k2 = kc + kb;
+            rb[t] = (k2 < K && e0 + col < ne) ? B[(int64_t)k2 * ne + e0 + col] : 0.0;
+        }
+    };
+    fetch(0);
+    for (int kc = 0; kc < K; kc += kGemmKC) {
+        __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int idx = tid + 256 * t;
+            sm.a[idx >> 4][idx & 15] = ra[t];
+            sm.b[idx >> 6][idx & 63] = rb[t];
+        }
+        __syncthreads();
+        if (kc + kGemmKC < K) fetch(kc + kGemmKC);
+#pragma unroll
+        for (int ks = 0; ks < kGemmKC; ks += 4) {
+            const double a = sm.a[wv * 16 + r][ks + kq];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.b[ks + kq][c * 16 + r], acc[c], 0, 0, 0);
         }
     }
 #pragma unroll
@@ -215,9 +249,10 @@ __global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ th
                                                    double* __restrict__ out, int64_t N, int K,
                                                    int64_t ne, const int64_t* __restrict__ N_dev)
 {
+    __shared__ GemmF64Smem sm;
     if (N_dev) N = min(N, *N_dev);
     if ((int64_t)blockIdx.y * 64 >= N) return;
-    gemm_f64_tile<EXP>(theta, B, out, N, K, ne, blockIdx.x, blockIdx.y);
+    gemm_f64_tile<EXP>(theta, B, out, N, K, ne, blockIdx.x, blockIdx.y, sm);
 }
 
 // BF16 on the matrix cores with FP32 accumulation: v_mfma_f32_16x16x32_bf16.
@@ -282,6 +317,7 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ t
 __global__ __launch_bounds__(256) void kl_gemm_list(const GemmItem* __restrict__ items, int n_items, int K,
                                                     int Kp, int bf16)
 {
+    __shared__ GemmF64Smem sm;
     const int64_t t = blockIdx.x;
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
@@ -292,7 +328,7 @@ __global__ __launch_bounds__(256) void kl_gemm_list(const GemmItem* __restrict__
     const int64_t lt = t - it.tile_base;
     const int64_t bx = lt % it.tiles_x, by = lt / it.tiles_x;
     if (bf16) gemm_bf16_tile(it.theta, it.B16, (float*)it.out, it.N, K, Kp, it.ne, bx, by);
-    else gemm_f64_tile<true>(it.theta, it.B, (double*)it.out, it.N, K, it.ne, bx, by);
+    else gemm_f64_tile<true>(it.theta, it.B, (double*)it.out, it.N, K, it.ne, bx, by, sm);
 }
 
 int launch_kl_list(mls2mc_ctx* ctx, const GemmItem* items_dev, int n_items, int64_t total_tiles, hipStream_t s)
