@@ -257,40 +257,66 @@ __global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ th
 
 // BF16 on the matrix cores with FP32 accumulation: v_mfma_f32_16x16x32_bf16.
 // Operand lanes: A[i][8*(lane/16) + 0..7] with i = lane%16 (theta rows,
-// rounded to BF16 here); B^T[j][8*(lane/16) + 0..7] with j = lane%16 (the
-// basis is stored transposed, n_e x Kp, K padded to 32 with zeros).
-// Output kappa = expf(a) in FP32.  Tile 64 x 64 as above.
+// rounded to BF16); B^T[j][8*(lane/16) + 0..7] with j = lane%16 (the basis is
+// stored transposed, n_e x Kp, K padded to 32 with zeros).  Output
+// kappa = expf(a) in FP32.  Tile 64 x 64 as above.  The workgroup stages
+// 128-deep k-chunks of its theta rows (rounded once) and basis columns in
+// LDS, so K <= 128 takes a single global round trip.
+constexpr int kBfKC = 128;
+struct GemmBf16Smem {
+    __bf16 a[64][kBfKC + 8];  // theta rows x k (row padding against bank conflicts)
+    __bf16 b[64][kBfKC + 8];  // basis columns x k
+};
+
 __device__ __forceinline__ void gemm_bf16_tile(const double* __restrict__ theta,
                                                const __hip_bfloat16* __restrict__ Bt, float* __restrict__ out,
-                                               int64_t N, int K, int Kp, int64_t ne, int64_t bx, int64_t by)
+                                               int64_t N, int K, int Kp, int64_t ne, int64_t bx, int64_t by,
+                                               GemmBf16Smem& sm)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int64_t e0 = bx * 64;
-    const int64_t p0 = by * 64 + wv * 16;
-    const int64_t prow = p0 + r;
+    const int64_t pb = by * 64;
+    const int64_t p0 = pb + wv * 16;
     flt4 acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = flt4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Kp; k0 += 32) {
-        bf16x8 a;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const int k = k0 + 8 * kq + t;
-            const float v = (prow < N && k < K) ? (float)theta[prow * K + k] : 0.f;
-            a[t] = (__bf16)v;
+    for (int kc = 0; kc < Kp; kc += kBfKC) {
+        __syncthreads();  // the previous chunk's reads are done
+        // theta chunk: 64 rows x 128 k, 32 values per thread (a row is 128 threads)
+#pragma unroll 8
+        for (int t = 0; t < 32; ++t) {
+            const int idx = tid + 256 * t;
+            const int row = idx >> 7, kk = idx & 127;
+            const int k = kc + kk;
+            const float v = (pb + row < N && k < K) ? (float)theta[(pb + row) * K + k] : 0.f;
+            sm.a[row][kk] = (__bf16)v;
         }
+        // basis chunk: 64 columns x 128 k in 16-byte vectors, 4 per thread
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int64_t e = e0 + c * 16 + r;
-            bf16x8 b;
-            if (e < ne) {
-                b = *reinterpret_cast<const bf16x8*>(Bt + e * Kp + k0 + 8 * kq);
+        for (int t = 0; t < 4; ++t) {
+            const int idx = tid + 256 * t;
+            const int col = idx >> 4, part = idx & 15;
+            const int k = kc + 8 * part;
+            bf16x8 v;
+            if (e0 + col < ne && k < Kp) {
+                v = *reinterpret_cast<const bf16x8*>(Bt + (e0 + col) * Kp + k);
             } else {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) b[t] = (__bf16)0.f;
+                for (int u = 0; u < 8; ++u) v[u] = (__bf16)0.f;
             }
-            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+            *reinterpret_cast<bf16x8*>(&sm.b[col][8 * part]) = v;
+        }
+        __syncthreads();
+        const int kend = Kp - kc < kBfKC ? Kp - kc : kBfKC;  // a multiple of 32
+        for (int ks = 0; ks < kend; ks += 32) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sm.a[wv * 16 + r][ks + 8 * kq]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sm.b[c * 16 + r][ks + 8 * kq]);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
@@ -307,9 +333,10 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ t
                                                     float* __restrict__ out, int64_t N, int K,
                                                     int Kp, int64_t ne, const int64_t* __restrict__ N_dev)
 {
+    __shared__ __align__(16) GemmBf16Smem sm;
     if (N_dev) N = min(N, *N_dev);
     if ((int64_t)blockIdx.y * 64 >= N) return;
-    gemm_bf16_tile(theta, Bt, out, N, K, Kp, ne, blockIdx.x, blockIdx.y);
+    gemm_bf16_tile(theta, Bt, out, N, K, Kp, ne, blockIdx.x, blockIdx.y, sm);
 }
 
 // Grouped launch: one 1-D grid over the 64x64 tiles of several items (each
@@ -317,7 +344,10 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ t
 __global__ __launch_bounds__(256) void kl_gemm_list(const GemmItem* __restrict__ items, int n_items, int K,
                                                     int Kp, int bf16)
 {
-    __shared__ GemmF64Smem sm;
+    __shared__ __align__(16) union {
+        GemmF64Smem f;
+        GemmBf16Smem b;
+    } sm;
     const int64_t t = blockIdx.x;
     int lo = 0, hi = n_items - 1;
     while (lo < hi) {
@@ -327,8 +357,8 @@ __global__ __launch_bounds__(256) void kl_gemm_list(const GemmItem* __restrict__
     const GemmItem& it = items[lo];
     const int64_t lt = t - it.tile_base;
     const int64_t bx = lt % it.tiles_x, by = lt / it.tiles_x;
-    if (bf16) gemm_bf16_tile(it.theta, it.B16, (float*)it.out, it.N, K, Kp, it.ne, bx, by);
-    else gemm_f64_tile<true>(it.theta, it.B, (double*)it.out, it.N, K, it.ne, bx, by, sm);
+    if (bf16) gemm_bf16_tile(it.theta, it.B16, (float*)it.out, it.N, K, Kp, it.ne, bx, by, sm.b);
+    else gemm_f64_tile<true>(it.theta, it.B, (double*)it.out, it.N, K, it.ne, bx, by, sm.f);
 }
 
 int launch_kl_list(mls2mc_ctx* ctx, const GemmItem* items_dev, int n_items, int64_t total_tiles, hipStream_t s)
