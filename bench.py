@@ -406,6 +406,7 @@ def leg_largest(args):
     res = {}
     for name, prec in (("fp64", P.FP64), ("mixed", P.MIXED)):
         ctx = P.Context(l, l, K, 1.0, 0.1, m, sn, precision=prec)
+        tuned = tune_levels(ctx, [l], 512)
         ctx.forward(l, th[:1024].contiguous())
         torch.cuda.synchronize()
         ctx.profile(True)
@@ -416,7 +417,7 @@ def leg_largest(args):
         ctx.profile(False)
         ps = ctx.profile_read(P.PROF_SOLVE, l)
         alg = solve_bytes(l, 100, ps["items"], ps["iters"], b_iter(ctx.get_launch(l)[2], prec == P.MIXED))
-        res[name] = dict(solves_per_s=round(J / dt, 1), seconds=round(dt, 3),
+        res[name] = dict(launch=tuned[f"h=1/{1 << l}"], solves_per_s=round(J / dt, 1), seconds=round(dt, 3),
                          mean_iters=float(it.float().mean().item()), converged=int((st == 0).sum().item()),
                          solver_algorithmic_GBs=round(alg / (ps["ms"] * 1e-3) / 1e9, 1))
         log(f"largest {name} {res[name]}")
