@@ -1,0 +1,47 @@
+"""The benchmark's command-line contract: one GPU only, and one JSON line
+with the metric, the roofline of the dominant kernel and the CPU baseline."""
+import json
+import sys
+
+import pytest
+
+import bench
+
+
+def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--gpus", "2"])
+    with pytest.raises(SystemExit) as e:
+        bench.main()
+    assert e.value.code == 2
+    assert "one GPU" in capsys.readouterr().err
+
+
+def test_flow_solver_byte_model_counts_the_fused_passes():
+    # V(1,1): 48 + 72 + (4/3) 170 B per unknown and iteration, nothing else
+    # when the per-solve terms are left out (particles = 0)
+    l, iters = 6, 10
+    M = (2 ** l - 1) * (2 ** l + 1)
+    assert bench.flow_solve_bytes(l, 25, 0, iters, 1) == pytest.approx(iters * M * (120 + 170 * 4 / 3))
+    assert bench.flow_solve_bytes(l, 25, 0, iters, 2) - bench.flow_solve_bytes(l, 25, 0, iters, 1) == \
+        pytest.approx(iters * M * 160 * 4 / 3)
+
+
+@pytest.mark.gpu
+def test_default_line_keeps_the_contract(monkeypatch, capsys):
+    from tests.gpu_util import case, device
+    device()
+    case("bench default line, 2 steps")
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "2", "--warmup", "1", "--no-extras"])
+    bench.main()
+    line = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")][-1]
+    d = json.loads(line)
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+              "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    assert d["n_gpus"] == 1 and d["steps"] == 2 and d["warmup"] == 1 and d["value"] > 0
+    assert d["config"]["workload"] and d["data"] == "synthetic" and d["vs_baseline"] is None
+    rf = d["roofline"]
+    assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3 and 0 < rf["frac"] < 1.2
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
