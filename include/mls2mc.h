@@ -157,7 +157,10 @@ int mls2mc_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void
 
 /* Forward response G_l(theta) = O(p) (Sec. 2.1 forward response operator;
  * Sec. 5 model): KL field, kappa = exp(a), solve A_l(kappa) p = b with
- * multigrid-preconditioned CG, observe p at the N_obs points.
+ * multigrid-preconditioned CG, observe p at the N_obs points.  The
+ * boundary-value problem is the context's (bc): the Dirichlet problem with
+ * f = 1, or the flow cell (Example 5.3), whose observations see p = 0 and
+ * p = 1 on its Dirichlet edges.
  * theta: N x K double; G_out: N x N_obs double.
  * status_out (N int8, may be NULL): 0 converged, 1 not converged within
  * max_iters, 2 non-finite.  iters_out (N int32, may be NULL): PCG
