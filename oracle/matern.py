@@ -25,7 +25,10 @@ a discretisation; these are the readings taken):
   paired eigenvalues exactly equal.  Within a class the eigenvalues are
   simple for the kernels and grids used here.
 * Order: lambda descending; exactly equal lambdas by class order.
-* Sign: sum_q g_q v_q > 0 with g_q = frac((q + 1) * 0.6180339887498949) - 1/2.
+* Sign: sum_q g_q v_q > 0 with g_q = frac((q + 1)^2 * 0.6180339887498949) - 1/2.
+  The quadratic Weyl sequence has no relation under the square's
+  reflections (the linear one makes g nearly constant over every reflection
+  orbit, so g.v vanishes for modes odd under the diagonal swap).
 * Basis: B[k, e] = sqrt(lambda_k) phi_k(c_e), phi_k the Nystrom extension
   phi_k(x) = (1/lambda_k) sum_q w C(|x - P_q|) phi_k(P_q), phi_k(P_q) = v_k[q]/sqrt(w),
   c_e the centroid of element e.
@@ -115,7 +118,8 @@ def modes(K, m, lam, sigma2=1.0):
             if c == 1:  # the swapped class (+,-): same eigenvalue
                 cand.append((lam_c[j], 2, expand(m, _swap(m, vec_c[:, j]), 1, -1)))
     cand.sort(key=lambda t: (-t[0], t[1]))
-    g = np.modf((np.arange(M) + 1.0) * GOLDEN_FRAC)[0] - 0.5
+    q1 = np.arange(M) + 1.0
+    g = np.modf(q1 * q1 * GOLDEN_FRAC)[0] - 0.5
     lam_out = np.array([t[0] for t in cand[:K]])
     V = np.zeros((M, K))
     for k, t in enumerate(cand[:K]):

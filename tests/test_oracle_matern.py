@@ -55,7 +55,8 @@ def test_parity_classes_reproduce_the_full_spectrum(m, lam):
 def test_canonical_basis_rules():
     m, lam = 16, 0.3
     lam_k, V, cls = matern.modes(40, m, lam)
-    g = np.modf((np.arange(m * m) + 1.0) * matern.GOLDEN_FRAC)[0] - 0.5
+    q1 = np.arange(m * m) + 1.0
+    g = np.modf(q1 * q1 * matern.GOLDEN_FRAC)[0] - 0.5
     assert np.all(g @ V > 0)
     grid = V.reshape(m, m, -1)  # [b, a, k]
     for k in range(40):
@@ -68,6 +69,21 @@ def test_canonical_basis_rules():
         j = np.nonzero((cls == 2) & (lam_k == lam_k[k]))[0]
         if k + 1 < 40:
             assert j.size == 1 and j[0] == k + 1
+
+
+@pytest.mark.parametrize("m", [4, 6, 8, 12, 16, 24, 32])
+def test_sign_rule_is_well_conditioned(m):
+    """|g.v| must stay far above rounding for every mode, or the sign (and
+    so the basis) would depend on the order of floating-point operations.
+    The quadratic sequence keeps it above 2e-4 here; a linear one vanishes
+    for the modes odd under the diagonal swap on small grids."""
+    _, V, _ = matern.modes(min(m * m, 200), m, 0.3)
+    q1 = np.arange(m * m) + 1.0
+    g = np.modf(q1 * q1 * matern.GOLDEN_FRAC)[0] - 0.5
+    assert np.abs(g @ V).min() > 1e-4
+    g_lin = np.modf(q1 * matern.GOLDEN_FRAC)[0] - 0.5
+    if m in (4, 6):
+        assert np.abs(g_lin @ V).min() < 1e-12
 
 
 def test_trace_is_the_variance():
