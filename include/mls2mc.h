@@ -71,7 +71,7 @@ extern "C" {
                                  x1 -> 1-x1 and x2 -> 1-x2 (paired eigenvalues:
                                  the one odd in x1 first), with the sign that
                                  makes sum_q g_q v_q > 0 for
-                                 g_q = frac((q+1) 0.6180339887498949) - 1/2,
+                                 g_q = frac((q+1)^2 0.6180339887498949) - 1/2,
                                  q = b m + a over the grid points
                                  ((a+1/2)/m, (b+1/2)/m).  The basis at the
                                  element centroids is the Nystrom extension

@@ -16,7 +16,8 @@
 // Rayleigh-Ritz: the block products A V run on the GPU, the
 // orthonormalisation and the small dense eigenproblems on the host.  The eigenvectors are then canonical: parity
 // definite, swapped pairs with identical eigenvalues in class order, sign
-// fixed by a fixed generic vector.  The basis at the element centroids is the
+// fixed by a quadratic Weyl sequence (a linear one is nearly constant over
+// the square's reflection orbits and cannot fix the sign of every mode).  The basis at the element centroids is the
 // Nystrom extension
 //   B_l[k, e] = sqrt(lambda_k) phi_k(c_e) = sqrt(w / lambda_k) sum_q C(|c_e - P_q|) v_k[q],
 // a K x M by M x n_e contraction with the kernel matrix generated on the fly,
@@ -35,7 +36,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr double kGoldenFrac = 0.6180339887498949;  // sign rule weights g_q = frac((q+1) * this) - 1/2
+constexpr double kGoldenFrac = 0.6180339887498949;  // sign rule weights g_q = frac((q+1)^2 * this) - 1/2
 constexpr double kResTol = 1e-13;                  // Ritz residual / largest eigenvalue at convergence
 constexpr double kResAccept = 1e-11;               // accepted when the residual no longer falls
 constexpr int kPowerSteps = 6;                     // subspace steps between Rayleigh-Ritz steps
@@ -440,7 +441,7 @@ int build_matern_tables(mls2mc_ctx* ctx)
             }
         double gsum = 0.0;
         for (int q = 0; q < M; ++q) {
-            const double g = std::fmod((q + 1.0) * kGoldenFrac, 1.0) - 0.5;
+            const double g = std::fmod((q + 1.0) * (q + 1.0) * kGoldenFrac, 1.0) - 0.5;
             gsum += g * out[q];
         }
         MLS_REQUIRE(cd.lam > 0, "create: Matern KL eigenvalue not positive (raise kl_quad or lower K)");

@@ -132,3 +132,16 @@ def test_flowcell_run_completes():
     res = ctx.run(to_dev(y), J=256, J_tilde=64, seed=5)
     assert res["final_level"] == 5 and res["final_beta"] == 1.0 and res["not_converged"] == 0
     assert np.isfinite(res["log_Z"])
+
+
+def test_flowcell_h512_sampled():
+    """h = 1/512, the largest level of the configurations: one sampled particle"""
+    device()
+    l, N, m = 9, 8, 10
+    case(f"flowcell l={l} N={N}")
+    ctx = _ctx(l, l, m=m)
+    kap = inputs.kappa_batch(91, N, 2 * 4 ** l, spread=0.7)
+    G, p, st, it = ctx.forward_field(l, to_dev(kap))
+    assert (host(st) == 0).all()
+    Gr = fc.forward_kappa(l, m, kap[[5]])
+    assert rel_err(host(G)[[5]], Gr) < 1e-10

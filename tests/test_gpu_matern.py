@@ -118,3 +118,21 @@ def test_matern_run_completes():
     res = ctx2.run(to_dev(y), J=256, J_tilde=64, seed=9)
     assert res["final_level"] == 5 and res["final_beta"] == 1.0 and res["not_converged"] == 0
     assert np.isfinite(res["log_Z"])
+
+
+@pytest.mark.parametrize("quad,K", [(4, 16), (6, 36), (8, 40)])
+def test_matern_all_or_most_eigenpairs(quad, K):
+    """K up to the whole Nystrom spectrum: the class solves take the whole
+    space (Rayleigh-Ritz is then exact) and the class bookkeeping must still
+    find every leading eigenpair; with K = m^2 the eigenvalues sum to sigma2."""
+    device()
+    case(f"matern quad={quad} K={K}")
+    ctx = _ctx(2, 3, K, 0.3, quad, sigma2=1.3)
+    lam_o, V, _ = matern.modes(K, quad, 0.3, 1.3)
+    ev = ctx.kl_eigenvalues()
+    assert rel_err(ev, lam_o) < 1e-11
+    if K == quad * quad:
+        assert abs(ev.sum() - 1.3) < 1e-12
+    Bg = host(ctx.kl_field(3, to_dev(np.eye(K)), P.FIELD_LOG_F64))
+    Bo = matern.extend(matern.centroids(3), lam_o, V, quad, 0.3, 1.3)
+    assert np.abs(Bg - Bo).max() <= 1e-10 * np.abs(Bo).max()
