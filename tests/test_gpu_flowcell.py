@@ -145,3 +145,33 @@ def test_flowcell_h512_sampled():
     assert (host(st) == 0).all()
     Gr = fc.forward_kappa(l, m, kap[[5]])
     assert rel_err(host(G)[[5]], Gr) < 1e-10
+
+
+def test_flowcell_schedules_and_autotune():
+    """The persistent grid and the (ignored) LDS budget change which
+    workgroup solves which particle, not the arithmetic: bitwise equal results
+    for a fixed block size and V-cycle.  The autotuner picks a shape on a
+    flow-cell context, and that shape still solves to the oracle's answer."""
+    device()
+    l, N, m = 5, 21, 5
+    case(f"flowcell schedules l={l}")
+    ctx = _ctx(l, l, m=m)
+    kap = inputs.kappa_batch(55, N, 2 * 4 ** l, spread=1.0)
+    Gr = fc.forward_kappa(l, m, kap)
+    for nu in (1, 2):
+        for block in (128, 512):
+            outs = []
+            for grid, lds in [(1, 0), (7, -1), (N, 81920)]:
+                ctx.set_launch(l, grid, block, nu, lds)
+                G, p, st, it = ctx.forward_field(l, to_dev(kap))
+                assert host(st).max() == 0
+                outs.append((host(G), host(it)))
+            for G, it in outs[1:]:
+                np.testing.assert_array_equal(G, outs[0][0])
+                np.testing.assert_array_equal(it, outs[0][1])
+            assert rel_err(outs[0][0], Gr) < 1e-10
+    case("flowcell autotune")
+    ms, shape = ctx.autotune(l, N)
+    assert ms > 0 and shape[1] in (64, 128, 256, 512, 1024)
+    G, p, st, it = ctx.forward_field(l, to_dev(kap))
+    assert host(st).max() == 0 and rel_err(host(G), Gr) < 1e-10
