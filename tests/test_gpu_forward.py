@@ -197,3 +197,25 @@ def test_solver_schedules_give_identical_results(l, prec):
         if block == 256:
             G256 = outs[0][0]
     assert rel_err(outs[0][0], G256) < (1e-12 if prec == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("form", ["fp64", "mixed", "flow"])
+def test_forward_chunks_are_seamless(form):
+    """At h = 1/512 a forward splits its batch into 2 GiB coefficient chunks
+    (512 particles in FP64, 1024 in FP32).  A particle's result does not
+    depend on the batch it is solved in, so a batch of 520 (FP64) or 1030
+    (FP32) must equal, bit for bit, a separate batch of its last particles,
+    across the chunk boundary."""
+    device()
+    l, K, m = 9, 20, 5
+    N = 1030 if form == "mixed" else 520
+    case(f"forward chunks l={l} {form} N={N}")
+    kw = dict(precision=P.MIXED) if form == "mixed" else dict(bc=P.BC_FLOW_CELL) if form == "flow" else {}
+    ctx = P.Context(l, l, K, 1.0, 0.3, m, 0.01, **kw)
+    th = to_dev(inputs.theta_batch(13, N, K))
+    G, st, it = ctx.forward(l, th, with_stats=True)
+    assert host(st).max() == 0
+    tail = N - 15
+    G2, st2, it2 = ctx.forward(l, th[tail:].contiguous(), with_stats=True)
+    np.testing.assert_array_equal(host(G)[tail:], host(G2))
+    np.testing.assert_array_equal(host(it)[tail:], host(it2))

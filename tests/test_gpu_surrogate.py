@@ -180,3 +180,55 @@ def test_surrogate_gain_in_the_sampler():
     sd = np.sqrt(0.5 * (a.var(0) + b.var(0)))
     # pCN particles are correlated: allow an effective sample size of J/10
     assert np.all(np.abs(a.mean(0) - b.mean(0)) < 5 * sd * np.sqrt(2 / (J / 10)))
+
+
+def test_delayed_acceptance_across_forward_chunks():
+    """At h = 1/512 the second-stage solves of the screened proposals run in
+    2 GiB chunks of 512 with a device-side count.  With about 650 of 700
+    proposals passing the first stage, the count crosses a chunk boundary;
+    every decision must still follow the two-stage rule applied to the plain
+    forward map's potentials, and the accepted particles must carry the plain
+    forward map's observations."""
+    device()
+    K, m, sn, N, l, beta = 12, 3, 0.1, 700, 9, 0.3
+    case(f"pcn_step_da chunks l={l} N={N}")
+    c = P.Context(l, l, K, 1.0, 0.3, m, sn)
+    P.mls2mc_surrogate_init(c.h, 64, 4096, 3)
+    th = inputs.theta_batch(31, N, K)
+    xi = inputs.theta_batch(32, N, K)
+    thp = oracle.pcn_propose(th, xi, 0.5)
+    y = host(c.forward(l, to_dev(inputs.theta_batch(33, 1, K))))[0] + sn * inputs.rng(3).standard_normal(9)
+    Glo, Glp = host(c.forward(l, to_dev(th))), host(c.forward(l, to_dev(thp)))
+    plo = np.array([oracle.potential(g, y, sn) for g in Glo])
+    plp = np.array([oracle.potential(g, y, sn) for g in Glp])
+    u1 = 1.0 - inputs.uniforms53(34, N)
+    u1[:650] = 1e-300  # the first stage passes these unless the surrogate's
+    # potential rises by more than 690 (sigma = 0.1 keeps it well below that)
+    u2 = 1.0 - inputs.uniforms53(35, N)
+    Gs = torch.empty((N, 9), dtype=torch.float64, device="cuda:0")
+    P.mls2mc_surrogate_predict(c.h, to_dev(th), Gs)
+    Gs_old = host(Gs).copy()
+    P.mls2mc_surrogate_predict(c.h, to_dev(thp), Gs)
+    Gs_new = host(Gs).copy()
+    ref = [oracle.da_accept(beta * plo[j], beta * plp[j], beta * oracle.potential(Gs_old[j], y, sn),
+                            beta * oracle.potential(Gs_new[j], y, sn), u1[j], u2[j]) for j in range(N)]
+    acc_ref = np.array([a for a, _ in ref])
+    s1_ref = np.array([s for _, s in ref])
+    print(f"  stage 1 passed {s1_ref.sum()}, accepted {acc_ref.sum()} of {N}")
+    assert s1_ref.sum() > 512 and 0 < acc_ref.sum() < N
+    T, GL, PL = to_dev(th), to_dev(Glo), to_dev(plo)
+    acc = torch.empty(N, dtype=torch.uint8, device="cuda:0")
+    s1 = torch.empty(N, dtype=torch.uint8, device="cuda:0")
+    nlo = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    P.mls2mc_pcn_step_da(c.h, l, l, beta, 1.0, 0.5, T, GL, None, PL, None, to_dev(y), to_dev(xi),
+                         to_dev(u1), to_dev(u2), acc, s1, nlo, None)
+    np.testing.assert_array_equal(host(s1).astype(bool), s1_ref)
+    np.testing.assert_array_equal(host(acc).astype(bool), acc_ref)
+    assert host(nlo)[0] == s1_ref.sum()
+    # proposals are formed on the device, so the solved inputs may differ from
+    # the host's in the last bit: the kept observations are the plain forward
+    # map's to the solver's tolerance, the rejected ones untouched
+    GLh = host(GL)
+    np.testing.assert_array_equal(GLh[~acc_ref], Glo[~acc_ref])
+    assert rel_err(GLh[acc_ref], Glp[acc_ref]) < 1e-10
+    assert rel_err(host(T), np.where(acc_ref[:, None], thp, th)) < 1e-15
