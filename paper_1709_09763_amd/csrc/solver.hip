@@ -318,6 +318,56 @@ __device__ void coarsen_kappa(const KT* __restrict__ kf, T* __restrict__ kc, int
     }
 }
 
+// ------------------------------------------------------- column walk --
+// On a level whose rows are exactly one workgroup wide (n == BS) the CG
+// stencil pass goes by columns: thread i owns column i and walks the rows
+// upward, keeping p and WY of the row below and at hand in registers, so
+// each row of Z, P_old and WY is read from memory once rather than three
+// times.  With many particles in flight the rows above and below have left
+// the L2 before that reuse.  The row loop gives thread i the same column in
+// the same row order when n == BS, and the walk evaluates the same
+// expressions, so only where the operands come from changes.  Lane 0 owns
+// the boundary column and idles.  (The Gauss-Seidel sweeps stay row loops:
+// a column holds one node of a colour per two rows, so a walking sweep runs
+// its division with half the lanes masked, which measured slower.)
+
+// The walk indexes every array with one 32-bit offset, as the row loops do;
+// left visible, the serial row index lets the compiler turn each access
+// into a 64-bit pointer of its own, which costs registers the solver has
+// not got.
+__device__ __forceinline__ int opaque(int c)
+{
+    asm("" : "+v"(c));
+    return c;
+}
+
+// p = z + beta p_old formed on the fly at the node and its neighbours,
+// stored to Pn with q = A p; returns this thread's share of (p, q)
+template <typename T>
+__device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* __restrict__ Po, T beta,
+                             T* __restrict__ Pn, T* __restrict__ Q)
+{
+    const int i = threadIdx.x, s = F.s;
+    double pq = 0.0;
+    if (i == 0) return pq;
+    auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
+    T pm = pn(i), p0 = pn(s + i), wym = F.wy[i];
+#pragma unroll 1
+    for (int j = 1; j < F.n; ++j) {
+        const int c = opaque(j * s + i);
+        const T pp = pn(c + s), wyc = F.wy[c];
+        const T v = (F.wx[c - 1] + F.wx[c] + wym + wyc) * p0
+                  - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + wym * pm + wyc * pp);
+        Pn[c] = p0;
+        Q[c] = v;
+        pq += (double)p0 * (double)v;
+        pm = p0;
+        p0 = pp;
+        wym = wyc;
+    }
+    return pq;
+}
+
 // ------------------------------------------------------------ V-cycle --
 template <int BS, typename T, typename W>
 __device__ void smooth_colour(const Lv<T, W>& L, const T* __restrict__ b, T* __restrict__ x, int col,
@@ -632,7 +682,7 @@ __device__ inline Lv<T> fine_level(const Map<T>& M)
 }
 
 // ---------------------------------------------------------- FP64 solve --
-template <int BS>
+template <int BS, bool WK>
 __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
@@ -675,15 +725,19 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         // stored at those nodes), so the pass needs no barrier in between
         double pq = 0.0;
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
-        MLS_FOR_INTERIOR(F, {
-            const double pc = pn(c);
-            const double v = diag_at(F.wx, F.wy, c, s) * pc
-                           - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
-                              + F.wy[c] * pn(c + s));
-            Pn[c] = pc;
-            Q[c] = v;
-            pq += pc * v;
-        })
+        if (WK && F.n == BS) {
+            pq = walk_apply(F, Z, Po, beta, Pn, Q);
+        } else {
+            MLS_FOR_INTERIOR(F, {
+                const double pc = pn(c);
+                const double v = diag_at(F.wx, F.wy, c, s) * pc
+                               - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
+                                  + F.wy[c] * pn(c + s));
+                Pn[c] = pc;
+                Q[c] = v;
+                pq += pc * v;
+            })
+        }
         pq = block_sum<BS>(pq, red);
         const double alpha = rz / pq;
         // x and r updates fused with the first red sweep of the V-cycle
@@ -720,7 +774,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
 // done in FP64.
 constexpr double kDrift2 = 1e-6;  // replace r after (r, z) fell by this factor (1e-3 in norm)
 
-template <int BS>
+template <int BS, bool WK>
 __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
@@ -775,15 +829,19 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         float* Pn = Pb[it & 1];
         double pq = 0.0;
         auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
-        MLS_FOR_INTERIOR(F, {
-            const float pc = pn(c);
-            const float v = diag_at(F.wx, F.wy, c, s) * pc
-                          - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
-                             + F.wy[c] * pn(c + s));
-            Pn[c] = pc;
-            Q[c] = v;
-            pq += (double)pc * (double)v;
-        })
+        if (WK && F.n == BS) {
+            pq = walk_apply(F, Z, Po, beta, Pn, Q);
+        } else {
+            MLS_FOR_INTERIOR(F, {
+                const float pc = pn(c);
+                const float v = diag_at(F.wx, F.wy, c, s) * pc
+                              - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
+                                 + F.wy[c] * pn(c + s));
+                Pn[c] = pc;
+                Q[c] = v;
+                pq += (double)pc * (double)v;
+            })
+        }
         pq = block_sum<BS>(pq, red);
         const float alpha = (float)(rz / pq);
         MLS_FOR_INTERIOR(F, {
@@ -848,10 +906,12 @@ extern __shared__ __align__(16) char mls_lds[];
 
 // FP64 solver kernels: ask for registers that leave room for six waves per
 // SIMD (measured faster at h = 1/512 than the compiler's own choice, equal
-// at h = 1/64); the FP32 kernels measured best unconstrained
-#define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(MIXED ? 1 : 6)))
+// at h = 1/64); the FP32 kernels measured best unconstrained.  The
+// column-walk instances run two 512-wide workgroups per CU at h = 1/512,
+// which four waves per SIMD hold without spilling.
+#define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(MIXED ? 1 : (WK ? 4 : 6))))
 
-template <int BS, bool MIXED>
+template <int BS, bool MIXED, bool WK>
 __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P)
 {
     __shared__ double red[BS / 64];
@@ -872,12 +932,12 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P
         J.obs_idx = P.obs_idx;
         J.obs_w = P.obs_w;
         if (MIXED) {
-            solve_one_mixed<BS>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
+            solve_one_mixed<BS, WK>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
                                          P.lds_elems, nullptr), J, P.C, red);
         } else {
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
-            solve_one_f64<BS>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
         }
     }
 }
@@ -900,7 +960,7 @@ struct ListParams {
     Common C;
 };
 
-template <int BS, bool MIXED>
+template <int BS, bool MIXED, bool WK = false>
 __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListParams P)
 {
     __shared__ double red[BS / 64];
@@ -926,12 +986,12 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListPara
         J.obs_idx = P.obs_idx[l];
         J.obs_w = P.obs_w[l];
         if (MIXED) {
-            solve_one_mixed<BS>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
+            solve_one_mixed<BS, false>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
                                          P.lds_elems, nullptr), J, P.C, red);
         } else {
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
-            solve_one_f64<BS>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+            solve_one_f64<BS, false>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
         }
     }
 }
@@ -963,6 +1023,19 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
         case 256: KERNEL<256, MIXED><<<grid, 256, lds, stream>>>(params); break;                  \
         case 512: KERNEL<512, MIXED><<<grid, 512, lds, stream>>>(params); break;                  \
         case 1024: KERNEL<1024, MIXED><<<grid, 1024, lds, stream>>>(params); break;               \
+        default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
+    }
+
+// solve_kernel instances: WK selects the column walk of the CG stencil
+// pass, built for the block sizes that equal a row width of h = 1/256 and
+// finer
+#define MLS_SWITCH_SOLVE(bs, MIXED, WK, grid, lds, stream, params)                               \
+    switch (bs) {                                                                                \
+        case 64: solve_kernel<64, MIXED, false><<<grid, 64, lds, stream>>>(params); break;        \
+        case 128: solve_kernel<128, MIXED, false><<<grid, 128, lds, stream>>>(params); break;     \
+        case 256: solve_kernel<256, MIXED, WK><<<grid, 256, lds, stream>>>(params); break;        \
+        case 512: solve_kernel<512, MIXED, WK><<<grid, 512, lds, stream>>>(params); break;        \
+        case 1024: solve_kernel<1024, MIXED, WK><<<grid, 1024, lds, stream>>>(params); break;     \
         default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
     }
 
@@ -1019,8 +1092,16 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
         MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
     }
     dim3 g((unsigned)grid);
-    if (mixed) { MLS_SWITCH_BS(bs, true, solve_kernel, g, lds, s, P) }
-    else { MLS_SWITCH_BS(bs, false, solve_kernel, g, lds, s, P) }
+    // Rows of h <= 1/256 stream from HBM with many particles in flight; when
+    // a row is one workgroup wide the CG stencil pass walks columns
+    const bool walk = l >= 8 && bs == (1 << l);
+    if (walk) {
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, true, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, true, g, lds, s, P) }
+    } else {
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, false, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, false, g, lds, s, P) }
+    }
     MLS_CHECK_HIP(hipGetLastError());
     if (ctx->prof_on) {
         MLS_TRY(prof_end(ctx, MLS2MC_PROF_SOLVE, l, rec, s));
