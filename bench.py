@@ -529,7 +529,7 @@ def main():
                     help="batched workload: also time the instances one after another")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the particle axis would shard across GPUs)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
