@@ -219,3 +219,31 @@ def test_forward_chunks_are_seamless(form):
     G2, st2, it2 = ctx.forward(l, th[tail:].contiguous(), with_stats=True)
     np.testing.assert_array_equal(host(G)[tail:], host(G2))
     np.testing.assert_array_equal(host(it)[tail:], host(it2))
+
+
+@pytest.mark.parametrize("l,N", [(8, 40), (9, 12)])
+def test_column_walk_instances_parity(l, N):
+    """Blocks as wide as a row (256 threads at h = 1/256, 512 at h = 1/512)
+    run the solver instances whose CG stencil pass walks columns.  FP64 and
+    mixed, on the same FP32-representable coefficients: sampled particles
+    against the oracle (rel 1e-10 and 1e-6), and all particles against a
+    row-loop launch of twice the width (rel 1e-9: only the summation order of
+    the inner products differs)."""
+    device()
+    n = 1 << l
+    kap = inputs.kappa_batch(60 + l, N, oracle.n_elem(l), spread=1.0)
+    kap32 = kap.astype(np.float32).astype(np.float64)
+    idx = [N - 1] if l == 9 else [0, N - 1]
+    Gr = oracle.forward_kappa(l, 7, kap32[idx])
+    for prec, tol in ((P.FP64, 1e-10), (P.MIXED, 1e-6)):
+        case(f"column walk l={l} block={n} precision={prec}")
+        ctx = P.Context(l, l, 4, 1.0, 0.3, 7, 0.01, precision=prec)
+        ctx.set_launch(l, N, n, 1, -1)
+        G, p, st, it = ctx.forward_field(l, to_dev(kap32))
+        assert host(st).max() == 0
+        assert rel_err(host(G)[idx], Gr) < tol
+        if l == 8:
+            ctx.set_launch(l, N, 2 * n, 1, -1)
+            G2, p2, st2, it2 = ctx.forward_field(l, to_dev(kap32))
+            assert rel_err(host(G), host(G2)) < (1e-9 if prec == P.FP64 else 1e-5)
+        ctx.close()
