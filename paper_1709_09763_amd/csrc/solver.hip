@@ -319,17 +319,19 @@ __device__ void coarsen_kappa(const KT* __restrict__ kf, T* __restrict__ kc, int
 }
 
 // ------------------------------------------------------- column walk --
-// On a level whose rows are exactly one workgroup wide (n == BS) the CG
-// stencil pass goes by columns: thread i owns column i and walks the rows
-// upward, keeping p and WY of the row below and at hand in registers, so
-// each row of Z, P_old and WY is read from memory once rather than three
-// times.  With many particles in flight the rows above and below have left
-// the L2 before that reuse.  The row loop gives thread i the same column in
-// the same row order when n == BS, and the walk evaluates the same
-// expressions, so only where the operands come from changes.  Lane 0 owns
-// the boundary column and idles.  (The Gauss-Seidel sweeps stay row loops:
-// a column holds one node of a colour per two rows, so a walking sweep runs
-// its division with half the lanes masked, which measured slower.)
+// On a level whose row width n divides the workgroup (BS = m n) the CG
+// stencil pass goes by columns: the m groups of n threads take m bands of
+// rows, and thread i of a group owns column i of its band and walks it
+// upward, keeping p and WY of the row below and of its own row in
+// registers.  Each row of Z, P_old and WY is then loaded once per pass
+// rather than three times (plus one row at each band's start).  Lane 0 of a
+// group owns the boundary column and idles.  With m = 1 the row loop gives
+// thread i the same nodes in the same order, and the walk evaluates the
+// same expressions, so the results are bitwise the row loop's; with m > 1
+// only the order of the inner product's terms differs.  (The Gauss-Seidel
+// sweeps stay row loops: a column holds one node of a colour per two rows,
+// so a walking sweep runs its division with half the lanes masked, which
+// measured slower.)
 
 // The walk indexes every array with one 32-bit offset, as the row loops do;
 // left visible, the serial row index lets the compiler turn each access
@@ -343,17 +345,21 @@ __device__ __forceinline__ int opaque(int c)
 
 // p = z + beta p_old formed on the fly at the node and its neighbours,
 // stored to Pn with q = A p; returns this thread's share of (p, q)
-template <typename T>
+template <int BS, typename T>
 __device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* __restrict__ Po, T beta,
                              T* __restrict__ Pn, T* __restrict__ Q)
 {
-    const int i = threadIdx.x, s = F.s;
+    const int n = F.n, s = F.s, m = BS / n;
+    const int i = threadIdx.x & (n - 1), band = threadIdx.x / n;
+    const int rows = (n - 2 + m) / m;  // ceil((n - 1) / m)
+    const int j0 = 1 + band * rows, j1 = min(n, j0 + rows);
     double pq = 0.0;
-    if (i == 0) return pq;
+    if (i == 0 || j0 >= j1) return pq;
     auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
-    T pm = pn(i), p0 = pn(s + i), wym = F.wy[i];
+    const int c0 = (j0 - 1) * s + i;
+    T pm = pn(c0), p0 = pn(c0 + s), wym = F.wy[c0];
 #pragma unroll 1
-    for (int j = 1; j < F.n; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const int c = opaque(j * s + i);
         const T pp = pn(c + s), wyc = F.wy[c];
         const T v = (F.wx[c - 1] + F.wx[c] + wym + wyc) * p0
@@ -725,8 +731,8 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         // stored at those nodes), so the pass needs no barrier in between
         double pq = 0.0;
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
-        if (WK && F.n == BS) {
-            pq = walk_apply(F, Z, Po, beta, Pn, Q);
+        if (WK && BS % F.n == 0) {
+            pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
         } else {
             MLS_FOR_INTERIOR(F, {
                 const double pc = pn(c);
@@ -829,8 +835,8 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         float* Pn = Pb[it & 1];
         double pq = 0.0;
         auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
-        if (WK && F.n == BS) {
-            pq = walk_apply(F, Z, Po, beta, Pn, Q);
+        if (WK && BS % F.n == 0) {
+            pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
         } else {
             MLS_FOR_INTERIOR(F, {
                 const float pc = pn(c);
@@ -1027,8 +1033,8 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
     }
 
 // solve_kernel instances: WK selects the column walk of the CG stencil
-// pass, built for the block sizes that equal a row width of h = 1/256 and
-// finer
+// pass, built for the block sizes that a row width of h = 1/256 or finer
+// divides
 #define MLS_SWITCH_SOLVE(bs, MIXED, WK, grid, lds, stream, params)                               \
     switch (bs) {                                                                                \
         case 64: solve_kernel<64, MIXED, false><<<grid, 64, lds, stream>>>(params); break;        \
@@ -1093,8 +1099,8 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     }
     dim3 g((unsigned)grid);
     // Rows of h <= 1/256 stream from HBM with many particles in flight; when
-    // a row is one workgroup wide the CG stencil pass walks columns
-    const bool walk = l >= 8 && bs == (1 << l);
+    // the row width divides the workgroup the CG stencil pass walks columns
+    const bool walk = l >= 8 && bs % (1 << l) == 0;
     if (walk) {
         if (mixed) { MLS_SWITCH_SOLVE(bs, true, true, g, lds, s, P) }
         else { MLS_SWITCH_SOLVE(bs, false, true, g, lds, s, P) }

@@ -223,27 +223,32 @@ def test_forward_chunks_are_seamless(form):
 
 @pytest.mark.parametrize("l,N", [(8, 40), (9, 12)])
 def test_column_walk_instances_parity(l, N):
-    """Blocks as wide as a row (256 threads at h = 1/256, 512 at h = 1/512)
-    run the solver instances whose CG stencil pass walks columns.  FP64 and
+    """Blocks that the row width divides (256, 512 and 1024 threads at
+    h = 1/256; 512 and 1024 at h = 1/512) run the solver instances whose CG
+    stencil pass walks columns, in one, two or four bands of rows.  FP64 and
     mixed, on the same FP32-representable coefficients: sampled particles
     against the oracle (rel 1e-10 and 1e-6), and all particles against a
-    row-loop launch of twice the width (rel 1e-9: only the summation order of
-    the inner products differs)."""
+    row-loop launch with half the row width (rel 1e-9 and 1e-5: only the
+    summation order of the inner products differs)."""
     device()
     n = 1 << l
     kap = inputs.kappa_batch(60 + l, N, oracle.n_elem(l), spread=1.0)
     kap32 = kap.astype(np.float32).astype(np.float64)
     idx = [N - 1] if l == 9 else [0, N - 1]
     Gr = oracle.forward_kappa(l, 7, kap32[idx])
-    for prec, tol in ((P.FP64, 1e-10), (P.MIXED, 1e-6)):
-        case(f"column walk l={l} block={n} precision={prec}")
+    for prec, tol, tol_rl in ((P.FP64, 1e-10, 1e-9), (P.MIXED, 1e-6, 1e-5)):
         ctx = P.Context(l, l, 4, 1.0, 0.3, 7, 0.01, precision=prec)
-        ctx.set_launch(l, N, n, 1, -1)
-        G, p, st, it = ctx.forward_field(l, to_dev(kap32))
+        case(f"column walk l={l} row loop block={n // 2} precision={prec}")
+        ctx.set_launch(l, N, n // 2, 1, -1)
+        G_rl, p, st, it = ctx.forward_field(l, to_dev(kap32))
         assert host(st).max() == 0
-        assert rel_err(host(G)[idx], Gr) < tol
-        if l == 8:
-            ctx.set_launch(l, N, 2 * n, 1, -1)
-            G2, p2, st2, it2 = ctx.forward_field(l, to_dev(kap32))
-            assert rel_err(host(G), host(G2)) < (1e-9 if prec == P.FP64 else 1e-5)
+        for block in (n, 2 * n, 4 * n):
+            if block > 1024:
+                continue
+            case(f"column walk l={l} block={block} precision={prec}")
+            ctx.set_launch(l, N, block, 1, -1)
+            G, p, st, it = ctx.forward_field(l, to_dev(kap32))
+            assert host(st).max() == 0
+            assert rel_err(host(G)[idx], Gr) < tol
+            assert rel_err(host(G), host(G_rl)) < tol_rl
         ctx.close()
