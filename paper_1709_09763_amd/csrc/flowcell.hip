@@ -237,7 +237,7 @@ __device__ void coarsest(const FLv& L)
 // z = V r on the fine level l whose first red sweep (from z = 0) is done;
 // returns <r, z>
 template <int BS>
-__device__ double flow_vcycle(double* slot, int l, int nu, double* red)
+__device__ __forceinline__ double flow_vcycle(double* slot, int l, int nu, double* red)
 {
     const FLv F = flevel(slot, l, l);
     if (l == 1) {
@@ -289,7 +289,49 @@ struct FlowParams {
     int max_iters, nu;
 };
 
+// The CG stencil pass by columns, for blocks that the row width n divides
+// (BS = m n, h <= 1/256): the m groups of n threads take m bands of the
+// n + 1 unknown rows, and thread i of a group owns column i of its band,
+// keeping p and WY of the row below and of its own row in registers, so
+// each row of Z, P_old and WY is loaded once per pass rather than three
+// times.  Lane 0 of a group owns the Dirichlet column x1 = 0 and idles; the
+// ghost rows below and above carry zero weights, as in the row loop.
+__device__ __forceinline__ int flow_opaque(int c)  // keeps one 32-bit offset for all arrays
+{
+    asm("" : "+v"(c));
+    return c;
+}
+
 template <int BS>
+__device__ double flow_walk_apply(const FLv& F, const double* __restrict__ Z, const double* __restrict__ Po,
+                                  double beta, double* __restrict__ Pn, double* __restrict__ Q)
+{
+    const int n = F.n, s = F.s, m = BS / n;
+    const int i = threadIdx.x & (n - 1), band = threadIdx.x / n;
+    const int rows = (n + m) / m;  // ceil((n + 1) / m)
+    const int j0 = band * rows, j1 = min(n + 1, j0 + rows);
+    double pq = 0.0;
+    if (i == 0 || j0 >= j1) return pq;
+    auto pn = [&](int q) { return Z[q] + beta * Po[q]; };
+    const int c0 = j0 * s + i;  // the row below unknown row j0
+    double pm = pn(c0), p0 = pn(c0 + s), wym = F.wy[c0];
+#pragma unroll 1
+    for (int j = j0; j < j1; ++j) {
+        const int c = flow_opaque((j + 1) * s + i);
+        const double pp = pn(c + s), wyc = F.wy[c];
+        const double nb = F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + wym * pm + wyc * pp;
+        const double qv = (F.wx[c - 1] + F.wx[c] + wym + wyc) * p0 - nb;
+        Pn[c] = p0;
+        Q[c] = qv;
+        pq += p0 * qv;
+        pm = p0;
+        p0 = pp;
+        wym = wyc;
+    }
+    return pq;
+}
+
+template <int BS, bool WK>
 __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
 {
     __shared__ double red[BS / 64];
@@ -337,17 +379,21 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
             ++it;
             // p = z + beta p_old and q = A p in one pass
             double pq = 0.0;
-            FLOW_FOR_UNK(n, {
-                const double pc = Z[c] + beta * Po[c];
-                const double nb = F.wx[c - 1] * (Z[c - 1] + beta * Po[c - 1]) +
-                                  F.wx[c] * (Z[c + 1] + beta * Po[c + 1]) +
-                                  F.wy[c - s] * (Z[c - s] + beta * Po[c - s]) +
-                                  F.wy[c] * (Z[c + s] + beta * Po[c + s]);
-                const double qv = fdiag(F, c) * pc - nb;
-                Pn[c] = pc;
-                Q[c] = qv;
-                pq += pc * qv;
-            })
+            if (WK && BS % n == 0) {
+                pq = flow_walk_apply<BS>(F, Z, Po, beta, Pn, Q);
+            } else {
+                FLOW_FOR_UNK(n, {
+                    const double pc = Z[c] + beta * Po[c];
+                    const double nb = F.wx[c - 1] * (Z[c - 1] + beta * Po[c - 1]) +
+                                      F.wx[c] * (Z[c + 1] + beta * Po[c + 1]) +
+                                      F.wy[c - s] * (Z[c - s] + beta * Po[c - s]) +
+                                      F.wy[c] * (Z[c + s] + beta * Po[c + s]);
+                    const double qv = fdiag(F, c) * pc - nb;
+                    Pn[c] = pc;
+                    Q[c] = qv;
+                    pq += pc * qv;
+                })
+            }
             pq = block_sum<BS>(pq, red);
             const double alpha = rz / pq;
             FLOW_FOR_UNK(n, {
@@ -430,12 +476,25 @@ int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
         MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
     }
     dim3 g((unsigned)grid);
+    // the column walk of the stencil pass where the row width divides the
+    // block on the levels that stream from HBM (separate instances, so the
+    // others keep their registers)
+    const bool walk = l >= 8 && bs % (1 << l) == 0;
     switch (bs) {
-        case 64: flow_solve_kernel<64><<<g, 64, 0, s>>>(P); break;
-        case 128: flow_solve_kernel<128><<<g, 128, 0, s>>>(P); break;
-        case 256: flow_solve_kernel<256><<<g, 256, 0, s>>>(P); break;
-        case 512: flow_solve_kernel<512><<<g, 512, 0, s>>>(P); break;
-        case 1024: flow_solve_kernel<1024><<<g, 1024, 0, s>>>(P); break;
+        case 64: flow_solve_kernel<64, false><<<g, 64, 0, s>>>(P); break;
+        case 128: flow_solve_kernel<128, false><<<g, 128, 0, s>>>(P); break;
+        case 256:
+            if (walk) flow_solve_kernel<256, true><<<g, 256, 0, s>>>(P);
+            else flow_solve_kernel<256, false><<<g, 256, 0, s>>>(P);
+            break;
+        case 512:
+            if (walk) flow_solve_kernel<512, true><<<g, 512, 0, s>>>(P);
+            else flow_solve_kernel<512, false><<<g, 512, 0, s>>>(P);
+            break;
+        case 1024:
+            if (walk) flow_solve_kernel<1024, true><<<g, 1024, 0, s>>>(P);
+            else flow_solve_kernel<1024, false><<<g, 1024, 0, s>>>(P);
+            break;
         default: MLS_REQUIRE(false, "flow cell: unsupported block size");
     }
     MLS_CHECK_HIP(hipGetLastError());

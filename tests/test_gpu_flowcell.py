@@ -175,3 +175,26 @@ def test_flowcell_schedules_and_autotune():
     assert ms > 0 and shape[1] in (64, 128, 256, 512, 1024)
     G, p, st, it = ctx.forward_field(l, to_dev(kap))
     assert host(st).max() == 0 and rel_err(host(G), Gr) < 1e-10
+
+
+def test_flowcell_column_walk_blocks():
+    """h = 1/256 with 256, 512 and 1024 threads runs the flow solver's column
+    walk in one, two and four bands of rows; 128 threads run the row loop.
+    All agree to rel 1e-9 (only the inner products' summation order
+    differs), and sampled particles match the oracle to rel 1e-10."""
+    device()
+    l, N, m = 8, 24, 7
+    kap = inputs.kappa_batch(88, N, 2 * 4 ** l, spread=1.0)
+    idx = [0, N - 1]
+    Gr = fc.forward_kappa(l, m, kap[idx])
+    ctx = _ctx(l, l, m=m)
+    outs = {}
+    for block in (128, 256, 512, 1024):
+        case(f"flowcell l={l} block={block}")
+        ctx.set_launch(l, N, block, 1, 0)
+        G, p, st, it = ctx.forward_field(l, to_dev(kap))
+        assert host(st).max() == 0
+        outs[block] = host(G)
+        assert rel_err(outs[block][idx], Gr) < 1e-10
+    for block in (256, 512, 1024):
+        assert rel_err(outs[block], outs[128]) < 1e-9
