@@ -319,7 +319,8 @@ __device__ void coarsen_kappa(const KT* __restrict__ kf, T* __restrict__ kc, int
 }
 
 // ------------------------------------------------------- column walk --
-// On a level whose row width n divides the workgroup (BS = m n) the CG
+// On a level whose row width n divides the workgroup (BS = m n; used from
+// h = 1/64 on) the CG
 // stencil pass goes by columns: the m groups of n threads take m bands of
 // rows, and thread i of a group owns column i of its band and walks it
 // upward, keeping p and WY of the row below and of its own row in
@@ -913,8 +914,9 @@ extern __shared__ __align__(16) char mls_lds[];
 // FP64 solver kernels: ask for registers that leave room for six waves per
 // SIMD (measured faster at h = 1/512 than the compiler's own choice, equal
 // at h = 1/64); the FP32 kernels measured best unconstrained.  The
-// column-walk instances run two 512-wide workgroups per CU at h = 1/512,
-// which four waves per SIMD hold without spilling.
+// column-walk instances run two 512-wide workgroups per CU at h = 1/512 and
+// at the tuned h = 1/64 shape, which four waves per SIMD hold without
+// spilling.
 #define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(MIXED ? 1 : (WK ? 4 : 6))))
 
 template <int BS, bool MIXED, bool WK>
@@ -1032,13 +1034,11 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
         default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
     }
 
-// solve_kernel instances: WK selects the column walk of the CG stencil
-// pass, built for the block sizes that a row width of h = 1/256 or finer
-// divides
+// solve_kernel instances: WK selects the column walk of the CG stencil pass
 #define MLS_SWITCH_SOLVE(bs, MIXED, WK, grid, lds, stream, params)                               \
     switch (bs) {                                                                                \
-        case 64: solve_kernel<64, MIXED, false><<<grid, 64, lds, stream>>>(params); break;        \
-        case 128: solve_kernel<128, MIXED, false><<<grid, 128, lds, stream>>>(params); break;     \
+        case 64: solve_kernel<64, MIXED, WK><<<grid, 64, lds, stream>>>(params); break;           \
+        case 128: solve_kernel<128, MIXED, WK><<<grid, 128, lds, stream>>>(params); break;        \
         case 256: solve_kernel<256, MIXED, WK><<<grid, 256, lds, stream>>>(params); break;        \
         case 512: solve_kernel<512, MIXED, WK><<<grid, 512, lds, stream>>>(params); break;        \
         case 1024: solve_kernel<1024, MIXED, WK><<<grid, 1024, lds, stream>>>(params); break;     \
@@ -1098,9 +1098,10 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
         MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
     }
     dim3 g((unsigned)grid);
-    // Rows of h <= 1/256 stream from HBM with many particles in flight; when
-    // the row width divides the workgroup the CG stencil pass walks columns
-    const bool walk = l >= 8 && bs % (1 << l) == 0;
+    // from h = 1/64 on, when the row width divides the workgroup, the CG
+    // stencil pass walks columns (measured faster from there; the smaller
+    // levels are latency bound)
+    const bool walk = l >= 6 && bs % (1 << l) == 0;
     if (walk) {
         if (mixed) { MLS_SWITCH_SOLVE(bs, true, true, g, lds, s, P) }
         else { MLS_SWITCH_SOLVE(bs, false, true, g, lds, s, P) }
