@@ -290,7 +290,7 @@ struct FlowParams {
 };
 
 // The CG stencil pass by columns, for blocks that the row width n divides
-// (BS = m n, h <= 1/256): the m groups of n threads take m bands of the
+// (BS = m n, from h = 1/64 on): the m groups of n threads take m bands of the
 // n + 1 unknown rows, and thread i of a group owns column i of its band,
 // keeping p and WY of the row below and of its own row in registers, so
 // each row of Z, P_old and WY is loaded once per pass rather than three
@@ -476,10 +476,10 @@ int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
         MLS_TRY(prof_begin(ctx, MLS2MC_PROF_SOLVE, l, a.N, s, &rec));
     }
     dim3 g((unsigned)grid);
-    // the column walk of the stencil pass where the row width divides the
-    // block on the levels that stream from HBM (separate instances, so the
-    // others keep their registers)
-    const bool walk = l >= 8 && bs % (1 << l) == 0;
+    // the column walk of the stencil pass from h = 1/64 on, where the row
+    // width divides the block (separate instances, so the others keep their
+    // registers)
+    const bool walk = l >= 6 && bs % (1 << l) == 0;
     switch (bs) {
         case 64: flow_solve_kernel<64, false><<<g, 64, 0, s>>>(P); break;
         case 128: flow_solve_kernel<128, false><<<g, 128, 0, s>>>(P); break;
