@@ -732,7 +732,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         // stored at those nodes), so the pass needs no barrier in between
         double pq = 0.0;
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
-        if (WK && BS % F.n == 0) {
+        if (WK && F.n >= 64 && BS % F.n == 0) {
             pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
         } else {
             MLS_FOR_INTERIOR(F, {
@@ -836,7 +836,7 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         float* Pn = Pb[it & 1];
         double pq = 0.0;
         auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
-        if (WK && BS % F.n == 0) {
+        if (WK && F.n >= 64 && BS % F.n == 0) {
             pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
         } else {
             MLS_FOR_INTERIOR(F, {
@@ -968,7 +968,7 @@ struct ListParams {
     Common C;
 };
 
-template <int BS, bool MIXED, bool WK = false>
+template <int BS, bool MIXED, bool WK>
 __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListParams P)
 {
     __shared__ double red[BS / 64];
@@ -994,12 +994,12 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListPara
         J.obs_idx = P.obs_idx[l];
         J.obs_w = P.obs_w[l];
         if (MIXED) {
-            solve_one_mixed<BS, false>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
+            solve_one_mixed<BS, WK>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
                                          P.lds_elems, nullptr), J, P.C, red);
         } else {
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
-            solve_one_f64<BS, false>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
         }
     }
 }
@@ -1024,16 +1024,6 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
     return C;
 }
 
-#define MLS_SWITCH_BS(bs, MIXED, KERNEL, grid, lds, stream, params)                              \
-    switch (bs) {                                                                                \
-        case 64: KERNEL<64, MIXED><<<grid, 64, lds, stream>>>(params); break;                     \
-        case 128: KERNEL<128, MIXED><<<grid, 128, lds, stream>>>(params); break;                  \
-        case 256: KERNEL<256, MIXED><<<grid, 256, lds, stream>>>(params); break;                  \
-        case 512: KERNEL<512, MIXED><<<grid, 512, lds, stream>>>(params); break;                  \
-        case 1024: KERNEL<1024, MIXED><<<grid, 1024, lds, stream>>>(params); break;               \
-        default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
-    }
-
 // solve_kernel instances: WK selects the column walk of the CG stencil pass
 #define MLS_SWITCH_SOLVE(bs, MIXED, WK, grid, lds, stream, params)                               \
     switch (bs) {                                                                                \
@@ -1042,6 +1032,17 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
         case 256: solve_kernel<256, MIXED, WK><<<grid, 256, lds, stream>>>(params); break;        \
         case 512: solve_kernel<512, MIXED, WK><<<grid, 512, lds, stream>>>(params); break;        \
         case 1024: solve_kernel<1024, MIXED, WK><<<grid, 1024, lds, stream>>>(params); break;     \
+        default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
+    }
+
+// solve_list_kernel instances, WK as for solve_kernel (each item decides)
+#define MLS_SWITCH_LIST(bs, MIXED, WK, grid, lds, stream, params)                                \
+    switch (bs) {                                                                                \
+        case 64: solve_list_kernel<64, MIXED, WK><<<grid, 64, lds, stream>>>(params); break;      \
+        case 128: solve_list_kernel<128, MIXED, WK><<<grid, 128, lds, stream>>>(params); break;   \
+        case 256: solve_list_kernel<256, MIXED, WK><<<grid, 256, lds, stream>>>(params); break;   \
+        case 512: solve_list_kernel<512, MIXED, WK><<<grid, 512, lds, stream>>>(params); break;   \
+        case 1024: solve_list_kernel<1024, MIXED, WK><<<grid, 1024, lds, stream>>>(params); break;\
         default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
     }
 
@@ -1144,8 +1145,15 @@ int launch_solve_list(mls2mc_ctx* ctx, const SolveItem* items_dev, int n_items, 
     P.C = make_common(ctx, lmax);
     const size_t lds = lds_bytes_for(ctx, lmax, mixed, &P.lds_elems, &P.cinv_lds);
     dim3 g((unsigned)grid);
-    if (mixed) { MLS_SWITCH_BS(bs, true, solve_list_kernel, g, lds, s, P) }
-    else { MLS_SWITCH_BS(bs, false, solve_list_kernel, g, lds, s, P) }
+    // items of h = 1/64 and finer walk columns in the CG stencil pass (the
+    // instance decides per item)
+    if (lmax >= 6) {
+        if (mixed) { MLS_SWITCH_LIST(bs, true, true, g, lds, s, P) }
+        else { MLS_SWITCH_LIST(bs, false, true, g, lds, s, P) }
+    } else {
+        if (mixed) { MLS_SWITCH_LIST(bs, true, false, g, lds, s, P) }
+        else { MLS_SWITCH_LIST(bs, false, false, g, lds, s, P) }
+    }
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
 }
