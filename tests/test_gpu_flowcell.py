@@ -23,7 +23,7 @@ def _ctx(l_min, l_max, K=4, m=5, corr=0.3, **kw):
     return P.Context(l_min, l_max, K, 1.0, corr, m, 0.01, bc=P.BC_FLOW_CELL, **kw)
 
 
-@pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("l", [1, 2, 3, 4, 5, 6, 7])
 def test_flowcell_forward_field_parity(l):
     device()
     N, m = 13, 5
