@@ -38,8 +38,12 @@ __host__ __device__ inline int64_t fsz(int L)
     return (n + 1) * (n + 3);
 }
 
-// slot: fine arrays, then per coarse level l-1 .. 1 its arrays and coefficients
-enum { F_U = 0, F_R, F_Z, F_P, F_P2, F_Q, F_WX, F_WY, F_COUNT };
+// slot: fine arrays, then per coarse level l-1 .. 1 its arrays and coefficients.
+// F_W32 holds the FP32-rounded fine weights WX then WY (2 fsz floats): the
+// V-cycle's fine level reads those, while the CG operator keeps the FP64
+// ones, so the preconditioner is a fixed SPD operator close to A that reads
+// half the weight bytes.
+enum { F_U = 0, F_R, F_Z, F_P, F_P2, F_Q, F_WX, F_WY, F_W32, F_COUNT };
 enum { C_X = 0, C_B, C_WX, C_WY, C_COUNT };
 
 __host__ __device__ inline int64_t coarse_base(int l, int L)
@@ -51,10 +55,14 @@ __host__ __device__ inline int64_t coarse_base(int l, int L)
 
 __host__ __device__ inline int64_t flow_slot(int l) { return coarse_base(l, 0); }
 
-struct FLv {
-    double *x, *b, *wx, *wy, *kc;
+template <typename W>
+struct FLvT {
+    double *x, *b;
+    W *wx, *wy;  // edge weights, promoted exactly to FP64 where used
+    double* kc;
     int n, s;
 };
+using FLv = FLvT<double>;
 
 // level L of the hierarchy of the slot (L = l: the fine level's V-cycle
 // arrays, x = Z, b = R)
@@ -81,6 +89,21 @@ __device__ inline FLv flevel(double* slot, int l, int L)
     return v;
 }
 
+// the fine level as the V-cycle sees it: x = Z, b = R, FP32 weights
+__device__ inline FLvT<float> flevel32(double* slot, int l)
+{
+    FLvT<float> v;
+    v.n = 1 << l;
+    v.s = v.n + 1;
+    const int64_t f = fsz(l);
+    v.x = slot + F_Z * f;
+    v.b = slot + F_R * f;
+    v.wx = reinterpret_cast<float*>(slot + F_W32 * f);
+    v.wy = v.wx + f;
+    v.kc = nullptr;
+    return v;
+}
+
 #define FLOW_FOR_UNK(n_, ...)                                                  \
     for (int t_ = threadIdx.x; t_ < ((n_) - 1) * ((n_) + 1); t_ += BS) {     \
         const int i = 1 + t_ % ((n_) - 1), j = t_ / ((n_) - 1);              \
@@ -88,14 +111,17 @@ __device__ inline FLv flevel(double* slot, int l, int L)
         __VA_ARGS__                                                          \
     }
 
-__device__ __forceinline__ double fdiag(const FLv& L, int c)
+template <typename W>
+__device__ __forceinline__ double fdiag(const FLvT<W>& L, int c)
 {
-    return L.wx[c - 1] + L.wx[c] + L.wy[c - L.s] + L.wy[c];
+    return (double)L.wx[c - 1] + (double)L.wx[c] + (double)L.wy[c - L.s] + (double)L.wy[c];
 }
 
-__device__ __forceinline__ double fnb(const FLv& L, const double* x, int c)
+template <typename W>
+__device__ __forceinline__ double fnb(const FLvT<W>& L, const double* x, int c)
 {
-    return L.wx[c - 1] * x[c - 1] + L.wx[c] * x[c + 1] + L.wy[c - L.s] * x[c - L.s] + L.wy[c] * x[c + L.s];
+    return (double)L.wx[c - 1] * x[c - 1] + (double)L.wx[c] * x[c + 1] + (double)L.wy[c - L.s] * x[c - L.s]
+         + (double)L.wy[c] * x[c + L.s];
 }
 
 template <int BS>
@@ -107,7 +133,8 @@ __device__ void zero_all(double* a, int64_t n)
 // edge weights of a level from its element coefficients (kl: lower
 // triangles at 2(jn+i), upper at 2(jn+i)+1)
 template <int BS, typename KT>
-__device__ void flow_weights(const FLv& L, const KT* __restrict__ ke)
+__device__ void flow_weights(const FLv& L, const KT* __restrict__ ke, float* __restrict__ wx32 = nullptr,
+                             float* __restrict__ wy32 = nullptr)
 {
     const int n = L.n, s = L.s;
     const int64_t tot = fsz(31 - __builtin_clz(n));
@@ -126,6 +153,10 @@ __device__ void flow_weights(const FLv& L, const KT* __restrict__ ke)
         }
         L.wx[c] = wxv;
         L.wy[c] = wyv;
+        if (wx32) {  // FP32-rounded copies for the V-cycle
+            wx32[c] = (float)wxv;
+            wy32[c] = (float)wyv;
+        }
     }
 }
 
@@ -144,8 +175,8 @@ __device__ void flow_coarsen(const KT* __restrict__ kf, double* __restrict__ kc,
     }
 }
 
-template <int BS>
-__device__ void smooth(const FLv& L, int col)
+template <int BS, typename W>
+__device__ void smooth(const FLvT<W>& L, int col)
 {
     FLOW_FOR_UNK(L.n, {
         if (((i + j) & 1) != col) continue;
@@ -155,14 +186,15 @@ __device__ void smooth(const FLv& L, int col)
 }
 
 // residual b - A x at an unknown node f
-__device__ __forceinline__ double fres(const FLv& F, int f)
+template <typename W>
+__device__ __forceinline__ double fres(const FLvT<W>& F, int f)
 {
     return F.b[f] - (fdiag(F, f) * F.x[f] - fnb(F, F.x, f));
 }
 
 // ends a red sweep with sum_c b_c x_c over the unknowns (x final everywhere)
-template <int BS>
-__device__ double smooth_red_dot(const FLv& L, double* red)
+template <int BS, typename W>
+__device__ double smooth_red_dot(const FLvT<W>& L, double* red)
 {
     double d = 0.0;
     FLOW_FOR_UNK(L.n, {
@@ -179,8 +211,8 @@ __device__ double smooth_red_dot(const FLv& L, double* red)
 // C.b = P^T (F.b - A F.x) right after a black sweep: the black residuals
 // vanish, so the coarse node (I, J) gathers the red residuals at (2I, 2J),
 // (2I+1, 2J+1) and (2I-1, 2J-1).  C.x gets the coarse first red sweep from 0.
-template <int BS>
-__device__ void restrict_red(const FLv& F, const FLv& C)
+template <int BS, typename W>
+__device__ void restrict_red(const FLvT<W>& F, const FLv& C)
 {
     const int fs = F.s, nf = F.n;
     FLOW_FOR_UNK(C.n, {
@@ -195,8 +227,8 @@ __device__ void restrict_red(const FLv& F, const FLv& C)
 }
 
 // F.x += P C.x
-template <int BS>
-__device__ void prolong_add(const FLv& C, const FLv& F)
+template <int BS, typename W>
+__device__ void prolong_add(const FLv& C, const FLvT<W>& F)
 {
     const int cs = C.s;
     FLOW_FOR_UNK(F.n, {
@@ -239,14 +271,21 @@ __device__ void coarsest(const FLv& L)
 template <int BS>
 __device__ __forceinline__ double flow_vcycle(double* slot, int l, int nu, double* red)
 {
-    const FLv F = flevel(slot, l, l);
-    if (l == 1) {
+    if (l == 1) {  // the fine level is the coarsest: exact, FP64 weights
+        const FLv F = flevel(slot, l, l);
         coarsest<BS>(F);
         double d = 0.0;
         FLOW_FOR_UNK(F.n, { d += F.b[c] * F.x[c]; })
         return block_sum<BS>(d, red);
     }
-    for (int L = l; L >= 2; --L) {
+    const FLvT<float> F32 = flevel32(slot, l);
+    smooth<BS>(F32, 1);
+    for (int k = 1; k < nu; ++k) {
+        smooth<BS>(F32, 0);
+        smooth<BS>(F32, 1);
+    }
+    restrict_red<BS>(F32, flevel(slot, l, l - 1));
+    for (int L = l - 1; L >= 2; --L) {
         const FLv V = flevel(slot, l, L);
         smooth<BS>(V, 1);
         for (int k = 1; k < nu; ++k) {
@@ -256,15 +295,20 @@ __device__ __forceinline__ double flow_vcycle(double* slot, int l, int nu, doubl
         restrict_red<BS>(V, flevel(slot, l, L - 1));
     }
     coarsest<BS>(flevel(slot, l, 1));
-    double dot = 0.0;
-    for (int L = 2; L <= l; ++L) {
+    for (int L = 2; L <= l - 1; ++L) {
         const FLv V = flevel(slot, l, L);
         prolong_add<BS>(flevel(slot, l, L - 1), V);
         for (int k = 0; k < nu; ++k) {
             smooth<BS>(V, 1);
-            if (L == l && k == nu - 1) dot = smooth_red_dot<BS>(V, red);
-            else smooth<BS>(V, 0);
+            smooth<BS>(V, 0);
         }
+    }
+    prolong_add<BS>(flevel(slot, l, l - 1), F32);
+    double dot = 0.0;
+    for (int k = 0; k < nu; ++k) {
+        smooth<BS>(F32, 1);
+        if (k == nu - 1) dot = smooth_red_dot<BS>(F32, red);
+        else smooth<BS>(F32, 0);
     }
     return dot;
 }
@@ -344,13 +388,14 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
     double* Z = slot + F_Z * f;
     double* Q = slot + F_Q * f;
     const FLv F = flevel(slot, l, l);
+    const FLvT<float> F32 = flevel32(slot, l);  // the V-cycle's view of the fine level
     for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
         const double* kap = P.kappa + q * ne;
         // set-up: zero the arrays, weights of every level, the lifted right-hand side
         zero_all<BS>(slot, F_COUNT * f);
         for (int L = l - 1; L >= 1; --L) zero_all<BS>(slot + coarse_base(l, L), C_COUNT * fsz(L));
         __syncthreads();
-        flow_weights<BS>(F, kap);
+        flow_weights<BS>(F, kap, F32.wx, F32.wy);
         if (l >= 2) flow_coarsen<BS>(kap, flevel(slot, l, l - 1).kc, n / 2);
         __syncthreads();
         for (int L = l - 1; L >= 1; --L) {
@@ -363,7 +408,7 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
         FLOW_FOR_UNK(n, {
             const double r = i == n - 1 ? F.wx[c] : 0.0;
             R[c] = r;
-            Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F, c);
+            Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F32, c);
         })
         __syncthreads();
         // PCG
@@ -400,7 +445,7 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
                 U[c] += alpha * Pn[c];
                 const double r = R[c] - alpha * Q[c];
                 R[c] = r;
-                Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F, c);
+                Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F32, c);
             })
             __syncthreads();
             const double rzn = flow_vcycle<BS>(slot, l, P.nu, red);

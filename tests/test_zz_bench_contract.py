@@ -17,13 +17,14 @@ def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
 
 
 def test_flow_solver_byte_model_counts_the_fused_passes():
-    # V(1,1): 48 + 72 + (4/3) 170 B per unknown and iteration, nothing else
-    # when the per-solve terms are left out (particles = 0)
+    # V(1,1): 48 + 64 + 138 (fine level, FP32 V-cycle weights) + 170 / 3
+    # (coarse levels, FP64) B per unknown and iteration, nothing else when
+    # the per-solve terms are left out (particles = 0)
     l, iters = 6, 10
     M = (2 ** l - 1) * (2 ** l + 1)
-    assert bench.flow_solve_bytes(l, 25, 0, iters, 1) == pytest.approx(iters * M * (120 + 170 * 4 / 3))
+    assert bench.flow_solve_bytes(l, 25, 0, iters, 1) == pytest.approx(iters * M * (112 + 138 + 170 / 3))
     assert bench.flow_solve_bytes(l, 25, 0, iters, 2) - bench.flow_solve_bytes(l, 25, 0, iters, 1) == \
-        pytest.approx(iters * M * 160 * 4 / 3)
+        pytest.approx(iters * M * (128 + 160 / 3))
 
 
 @pytest.mark.gpu
