@@ -244,6 +244,34 @@ __device__ void prolong_add(const FLv& C, const FLvT<W>& F)
     __syncthreads();
 }
 
+// The first black sweep of the up-leg with the coarse correction x += P e
+// folded in.  A black node's four neighbours are red, and their corrected
+// values are read only by this sweep (the red sweep after it recomputes
+// them), so the correction is interpolated at the neighbours on the fly and
+// never stored; the black nodes' own corrections would be overwritten.  As
+// in prolong_add, only unknown nodes take a correction; a red unknown has
+// both indices even (a coarse node) or both odd (the middle of a coarse
+// diagonal edge).
+template <int BS, typename W>
+__device__ void smooth_black_corrected(const FLvT<W>& L, const FLv& C)
+{
+    const int n = L.n, s = L.s, cs = C.s;
+    auto pe = [&](int i, int j) -> double {
+        if (i < 1 || i > n - 1 || j < 0 || j > n) return 0.0;
+        const int q = ((j >> 1) + 1) * cs + (i >> 1);
+        return (i & 1) ? 0.5 * (C.x[q] + C.x[q + cs + 1]) : C.x[q];
+    };
+    FLOW_FOR_UNK(n, {
+        if (!((i + j) & 1)) continue;
+        const double nb = (double)L.wx[c - 1] * (L.x[c - 1] + pe(i - 1, j))
+                        + (double)L.wx[c] * (L.x[c + 1] + pe(i + 1, j))
+                        + (double)L.wy[c - s] * (L.x[c - s] + pe(i, j - 1))
+                        + (double)L.wy[c] * (L.x[c + s] + pe(i, j + 1));
+        L.x[c] = (L.b[c] + nb) / fdiag(L, c);
+    })
+    __syncthreads();
+}
+
 // exact solve at h = 1/2: unknowns (1,0), (1,1), (1,2), a tridiagonal system
 template <int BS>
 __device__ void coarsest(const FLv& L)
@@ -265,6 +293,8 @@ __device__ void coarsest(const FLv& L)
     }
     __syncthreads();
 }
+
+constexpr int kFoldFrom = 7;  // levels that fold the coarse correction into the black sweep
 
 // z = V r on the fine level l whose first red sweep (from z = 0) is done;
 // returns <r, z>
@@ -295,18 +325,23 @@ __device__ __forceinline__ double flow_vcycle(double* slot, int l, int nu, doubl
         restrict_red<BS>(V, flevel(slot, l, L - 1));
     }
     coarsest<BS>(flevel(slot, l, 1));
+    // the coarse correction: folded into the first black sweep from h = 1/128
+    // on (bitwise the same values); on the smaller levels the separate pass
+    // measured faster than the on-the-fly interpolation
     for (int L = 2; L <= l - 1; ++L) {
         const FLv V = flevel(slot, l, L);
-        prolong_add<BS>(flevel(slot, l, L - 1), V);
+        if (L < kFoldFrom) prolong_add<BS>(flevel(slot, l, L - 1), V);
         for (int k = 0; k < nu; ++k) {
-            smooth<BS>(V, 1);
+            if (k == 0 && L >= kFoldFrom) smooth_black_corrected<BS>(V, flevel(slot, l, L - 1));
+            else smooth<BS>(V, 1);
             smooth<BS>(V, 0);
         }
     }
-    prolong_add<BS>(flevel(slot, l, l - 1), F32);
+    if (l < kFoldFrom) prolong_add<BS>(flevel(slot, l, l - 1), F32);
     double dot = 0.0;
     for (int k = 0; k < nu; ++k) {
-        smooth<BS>(F32, 1);
+        if (k == 0 && l >= kFoldFrom) smooth_black_corrected<BS>(F32, flevel(slot, l, l - 1));
+        else smooth<BS>(F32, 1);
         if (k == nu - 1) dot = smooth_red_dot<BS>(F32, red);
         else smooth<BS>(F32, 0);
     }

@@ -25,6 +25,11 @@ def test_flow_solver_byte_model_counts_the_fused_passes():
     assert bench.flow_solve_bytes(l, 25, 0, iters, 1) == pytest.approx(iters * M * (112 + 138 + 170 / 3))
     assert bench.flow_solve_bytes(l, 25, 0, iters, 2) - bench.flow_solve_bytes(l, 25, 0, iters, 1) == \
         pytest.approx(iters * M * (128 + 160 / 3))
+    # from h = 1/128 on the prolongation pass (18 B) becomes 2 B of coarse
+    # values read inside the first black sweep
+    l = 8
+    M = (2 ** l - 1) * (2 ** l + 1)
+    assert bench.flow_solve_bytes(l, 49, 0, iters, 1) == pytest.approx(iters * M * (112 + 122 + 170 / 3))
 
 
 @pytest.mark.gpu
