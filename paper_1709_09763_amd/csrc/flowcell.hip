@@ -55,6 +55,31 @@ __host__ __device__ inline int64_t coarse_base(int l, int L)
 
 __host__ __device__ inline int64_t flow_slot(int l) { return coarse_base(l, 0); }
 
+// Coarse levels 1 .. ltop keep X, B, WX and WY in LDS (level 1 first, in
+// elements of double); their coefficients stay in the slot.
+__host__ __device__ inline int64_t flow_lds_off(int L)
+{
+    int64_t o = 0;
+    for (int k = 1; k < L; ++k) o += C_COUNT * fsz(k);
+    return o;
+}
+
+// the finest coarse level whose hierarchy fits the budget (0: none)
+inline int flow_lds_top(int l, int64_t budget_bytes)
+{
+    int top = 0;
+    for (int L = 1; L < l; ++L)
+        if (flow_lds_off(L + 1) * (int64_t)sizeof(double) <= budget_bytes) top = L;
+    return top;
+}
+
+// where a particle's arrays live: its slot, and the LDS levels
+struct FSlot {
+    double* slot;
+    double* lds;
+    int ltop;
+};
+
 template <typename W>
 struct FLvT {
     double *x, *b;
@@ -66,8 +91,9 @@ using FLv = FLvT<double>;
 
 // level L of the hierarchy of the slot (L = l: the fine level's V-cycle
 // arrays, x = Z, b = R)
-__device__ inline FLv flevel(double* slot, int l, int L)
+__device__ inline FLv flevel(const FSlot& S, int l, int L)
 {
+    double* slot = S.slot;
     FLv v;
     v.n = 1 << L;
     v.s = v.n + 1;
@@ -79,12 +105,13 @@ __device__ inline FLv flevel(double* slot, int l, int L)
         v.wy = slot + F_WY * f;
         v.kc = nullptr;
     } else {
-        double* base = slot + coarse_base(l, L);
+        double* g = slot + coarse_base(l, L);
+        double* base = L <= S.ltop ? S.lds + flow_lds_off(L) : g;
         v.x = base + C_X * f;
         v.b = base + C_B * f;
         v.wx = base + C_WX * f;
         v.wy = base + C_WY * f;
-        v.kc = base + C_COUNT * f;
+        v.kc = g + C_COUNT * f;
     }
     return v;
 }
@@ -299,48 +326,48 @@ constexpr int kFoldFrom = 7;  // levels that fold the coarse correction into the
 // z = V r on the fine level l whose first red sweep (from z = 0) is done;
 // returns <r, z>
 template <int BS>
-__device__ __forceinline__ double flow_vcycle(double* slot, int l, int nu, double* red)
+__device__ __forceinline__ double flow_vcycle(const FSlot& S, int l, int nu, double* red)
 {
     if (l == 1) {  // the fine level is the coarsest: exact, FP64 weights
-        const FLv F = flevel(slot, l, l);
+        const FLv F = flevel(S, l, l);
         coarsest<BS>(F);
         double d = 0.0;
         FLOW_FOR_UNK(F.n, { d += F.b[c] * F.x[c]; })
         return block_sum<BS>(d, red);
     }
-    const FLvT<float> F32 = flevel32(slot, l);
+    const FLvT<float> F32 = flevel32(S.slot, l);
     smooth<BS>(F32, 1);
     for (int k = 1; k < nu; ++k) {
         smooth<BS>(F32, 0);
         smooth<BS>(F32, 1);
     }
-    restrict_red<BS>(F32, flevel(slot, l, l - 1));
+    restrict_red<BS>(F32, flevel(S, l, l - 1));
     for (int L = l - 1; L >= 2; --L) {
-        const FLv V = flevel(slot, l, L);
+        const FLv V = flevel(S, l, L);
         smooth<BS>(V, 1);
         for (int k = 1; k < nu; ++k) {
             smooth<BS>(V, 0);
             smooth<BS>(V, 1);
         }
-        restrict_red<BS>(V, flevel(slot, l, L - 1));
+        restrict_red<BS>(V, flevel(S, l, L - 1));
     }
-    coarsest<BS>(flevel(slot, l, 1));
+    coarsest<BS>(flevel(S, l, 1));
     // the coarse correction: folded into the first black sweep from h = 1/128
     // on (bitwise the same values); on the smaller levels the separate pass
     // measured faster than the on-the-fly interpolation
     for (int L = 2; L <= l - 1; ++L) {
-        const FLv V = flevel(slot, l, L);
-        if (L < kFoldFrom) prolong_add<BS>(flevel(slot, l, L - 1), V);
+        const FLv V = flevel(S, l, L);
+        if (L < kFoldFrom) prolong_add<BS>(flevel(S, l, L - 1), V);
         for (int k = 0; k < nu; ++k) {
-            if (k == 0 && L >= kFoldFrom) smooth_black_corrected<BS>(V, flevel(slot, l, L - 1));
+            if (k == 0 && L >= kFoldFrom) smooth_black_corrected<BS>(V, flevel(S, l, L - 1));
             else smooth<BS>(V, 1);
             smooth<BS>(V, 0);
         }
     }
-    if (l < kFoldFrom) prolong_add<BS>(flevel(slot, l, l - 1), F32);
+    if (l < kFoldFrom) prolong_add<BS>(flevel(S, l, l - 1), F32);
     double dot = 0.0;
     for (int k = 0; k < nu; ++k) {
-        if (k == 0 && l >= kFoldFrom) smooth_black_corrected<BS>(F32, flevel(slot, l, l - 1));
+        if (k == 0 && l >= kFoldFrom) smooth_black_corrected<BS>(F32, flevel(S, l, l - 1));
         else smooth<BS>(F32, 1);
         if (k == nu - 1) dot = smooth_red_dot<BS>(F32, red);
         else smooth<BS>(F32, 0);
@@ -366,7 +393,10 @@ struct FlowParams {
     int nobs;
     double inv_sigma, tol2;
     int max_iters, nu;
+    int ltop;  // coarse levels 1 .. ltop in LDS
 };
+
+extern __shared__ __align__(16) double flow_lds[];
 
 // The CG stencil pass by columns, for blocks that the row width n divides
 // (BS = m n, from h = 1/64 on): the m groups of n threads take m bands of the
@@ -422,21 +452,22 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
     double* R = slot + F_R * f;
     double* Z = slot + F_Z * f;
     double* Q = slot + F_Q * f;
-    const FLv F = flevel(slot, l, l);
+    const FSlot S{slot, flow_lds, P.ltop};
+    const FLv F = flevel(S, l, l);
     const FLvT<float> F32 = flevel32(slot, l);  // the V-cycle's view of the fine level
     for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
         const double* kap = P.kappa + q * ne;
         // set-up: zero the arrays, weights of every level, the lifted right-hand side
         zero_all<BS>(slot, F_COUNT * f);
-        for (int L = l - 1; L >= 1; --L) zero_all<BS>(slot + coarse_base(l, L), C_COUNT * fsz(L));
+        for (int L = l - 1; L >= 1; --L) zero_all<BS>(flevel(S, l, L).x, C_COUNT * fsz(L));
         __syncthreads();
         flow_weights<BS>(F, kap, F32.wx, F32.wy);
-        if (l >= 2) flow_coarsen<BS>(kap, flevel(slot, l, l - 1).kc, n / 2);
+        if (l >= 2) flow_coarsen<BS>(kap, flevel(S, l, l - 1).kc, n / 2);
         __syncthreads();
         for (int L = l - 1; L >= 1; --L) {
-            const FLv C = flevel(slot, l, L);
+            const FLv C = flevel(S, l, L);
             flow_weights<BS>(C, C.kc);
-            if (L >= 2) flow_coarsen<BS>(C.kc, flevel(slot, l, L - 1).kc, C.n / 2);
+            if (L >= 2) flow_coarsen<BS>(C.kc, flevel(S, l, L - 1).kc, C.n / 2);
             __syncthreads();
         }
         // lifted right-hand side; z starts with the V-cycle's first red sweep
@@ -447,7 +478,7 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
         })
         __syncthreads();
         // PCG
-        double rz = flow_vcycle<BS>(slot, l, P.nu, red);
+        double rz = flow_vcycle<BS>(S, l, P.nu, red);
         const double rz0 = rz;
         double beta = 0.0;
         double* Po = slot + F_P * f;
@@ -483,7 +514,7 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
                 Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F32, c);
             })
             __syncthreads();
-            const double rzn = flow_vcycle<BS>(slot, l, P.nu, red);
+            const double rzn = flow_vcycle<BS>(S, l, P.nu, red);
             if (!isfinite(rzn) || !isfinite(alpha)) { st = 2; break; }
             if (rzn <= P.tol2 * rz0) { st = 0; break; }
             beta = rzn / rz;
@@ -547,6 +578,11 @@ int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     P.tol2 = ctx->rtol * ctx->rtol;
     P.max_iters = ctx->max_iters;
     P.nu = ctx->solver_nu[l] > 0 ? ctx->solver_nu[l] : 1;
+    // the level's LDS budget, as for the Dirichlet solver (0 = 64 KiB, -1 = none)
+    int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
+    if (budget > ctx->max_lds) budget = ctx->max_lds;
+    P.ltop = flow_lds_top(l, budget);
+    const size_t lds = (size_t)flow_lds_off(P.ltop + 1) * sizeof(double);
     ProfRec rec;
     if (ctx->prof_on) {
         if (!P.iters) {
@@ -561,19 +597,19 @@ int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     // registers)
     const bool walk = l >= 6 && bs % (1 << l) == 0;
     switch (bs) {
-        case 64: flow_solve_kernel<64, false><<<g, 64, 0, s>>>(P); break;
-        case 128: flow_solve_kernel<128, false><<<g, 128, 0, s>>>(P); break;
+        case 64: flow_solve_kernel<64, false><<<g, 64, lds, s>>>(P); break;
+        case 128: flow_solve_kernel<128, false><<<g, 128, lds, s>>>(P); break;
         case 256:
-            if (walk) flow_solve_kernel<256, true><<<g, 256, 0, s>>>(P);
-            else flow_solve_kernel<256, false><<<g, 256, 0, s>>>(P);
+            if (walk) flow_solve_kernel<256, true><<<g, 256, lds, s>>>(P);
+            else flow_solve_kernel<256, false><<<g, 256, lds, s>>>(P);
             break;
         case 512:
-            if (walk) flow_solve_kernel<512, true><<<g, 512, 0, s>>>(P);
-            else flow_solve_kernel<512, false><<<g, 512, 0, s>>>(P);
+            if (walk) flow_solve_kernel<512, true><<<g, 512, lds, s>>>(P);
+            else flow_solve_kernel<512, false><<<g, 512, lds, s>>>(P);
             break;
         case 1024:
-            if (walk) flow_solve_kernel<1024, true><<<g, 1024, 0, s>>>(P);
-            else flow_solve_kernel<1024, false><<<g, 1024, 0, s>>>(P);
+            if (walk) flow_solve_kernel<1024, true><<<g, 1024, lds, s>>>(P);
+            else flow_solve_kernel<1024, false><<<g, 1024, lds, s>>>(P);
             break;
         default: MLS_REQUIRE(false, "flow cell: unsupported block size");
     }

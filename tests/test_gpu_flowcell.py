@@ -148,8 +148,9 @@ def test_flowcell_h512_sampled():
 
 
 def test_flowcell_schedules_and_autotune():
-    """The persistent grid and the (ignored) LDS budget change which
-    workgroup solves which particle, not the arithmetic: bitwise equal results
+    """The persistent grid and the LDS budget (which coarse levels live in
+    LDS: none, up to h = 1/16 by default and with 80 KiB) change where the
+    work runs and the data sit, not the arithmetic: bitwise equal results
     for a fixed block size and V-cycle.  The autotuner picks a shape on a
     flow-cell context, and that shape still solves to the oracle's answer."""
     device()
