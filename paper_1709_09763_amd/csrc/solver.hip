@@ -345,10 +345,11 @@ __device__ __forceinline__ int opaque(int c)
 }
 
 // p = z + beta p_old formed on the fly at the node and its neighbours,
-// stored to Pn with q = A p; returns this thread's share of (p, q)
+// stored to Pn with q = A p; returns this thread's share of (p, q).  With X
+// the pass also applies the pending x += xa p_old at its nodes.
 template <int BS, typename T>
 __device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* __restrict__ Po, T beta,
-                             T* __restrict__ Pn, T* __restrict__ Q)
+                             T* __restrict__ Pn, T* __restrict__ Q, T* __restrict__ X = nullptr, T xa = T(0))
 {
     const int n = F.n, s = F.s, m = BS / n;
     const int i = threadIdx.x & (n - 1), band = threadIdx.x / n;
@@ -367,6 +368,7 @@ __device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* _
                   - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + wym * pm + wyc * pp);
         Pn[c] = p0;
         Q[c] = v;
+        if (X) X[c] += xa * Po[c];
         pq += (double)p0 * (double)v;
         pm = p0;
         p0 = pp;
@@ -725,6 +727,10 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
     // p_k = z_k + beta_k p_{k-1} (p_0 = z_0: beta = 0 with z as the old p)
     const double* Po = Z;
     double beta = 0.0;
+    // x += alpha p is applied one iteration late, by the next stencil pass,
+    // which reads that p at every node anyway; the last one after the loop
+    double xa = 0.0;
+    const double* Pl = nullptr;
     while (st == 1 && it < C.max_iters) {
         double* Pn = Pb[it & 1];
         // the p update and q = A p in one pass: the four neighbours' new p
@@ -732,10 +738,12 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         // stored at those nodes), so the pass needs no barrier in between
         double pq = 0.0;
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
+        double* Xu = it > 0 ? X : nullptr;
         if (WK && F.n >= 64 && BS % F.n == 0) {
-            pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
+            pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q, Xu, xa);
         } else {
             MLS_FOR_INTERIOR(F, {
+                if (Xu) Xu[c] += xa * Po[c];
                 const double pc = pn(c);
                 const double v = diag_at(F.wx, F.wy, c, s) * pc
                                - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + F.wy[c - s] * pn(c - s)
@@ -747,9 +755,10 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         }
         pq = block_sum<BS>(pq, red);
         const double alpha = rz / pq;
-        // x and r updates fused with the first red sweep of the V-cycle
+        xa = alpha;
+        Pl = Pn;
+        // the r update fused with the first red sweep of the V-cycle
         MLS_FOR_INTERIOR(F, {
-            X[c] += alpha * Pn[c];
             const double rn = R[c] - alpha * Q[c];
             R[c] = rn;
             Z[c] = (((i + j) & 1) == 0) ? rn / ldiag(FV, c) : 0.0;  // black: taken as zero
@@ -762,6 +771,10 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         beta = rzn / rz;
         rz = rzn;
         Po = Pn;
+    }
+    if (Pl) {  // the last pending x += alpha p
+        MLS_FOR_INTERIOR(F, { X[c] += xa * Pl[c]; })
+        __syncthreads();
     }
     observe_and_store<BS>(J, C, X, F.n, st, it, red);
 }
