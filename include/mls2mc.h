@@ -456,8 +456,9 @@ int mls2mc_philox_fill(mls2mc_ctx* ctx, uint64_t seed, uint32_t stream_id, uint3
 /* Autotune the solver for level l on N prior draws: every candidate
  * (persistent workgroups = w x CUs capped at N; block size; V-cycle
  * Gauss-Seidel sweeps per side nu in {1,2}; LDS residency of the multigrid
- * hierarchy and of the finest level's arrays: none, 64 KiB, 80 KiB or the
- * device's LDS per workgroup less 1 KiB) solves the batch to the context's
+ * hierarchy and of the finest level's arrays, for the flow cell of the
+ * coarse levels only: none, 64 KiB, 80 KiB or the device's LDS per
+ * workgroup less 1 KiB) solves the batch to the context's
  * tolerance, is timed with HIP events (best of 3), and the fastest is kept
  * in the context for level l.  best_ms (host, may be NULL) receives its
  * time.  Synchronous; allocates its own temporary buffers.                 */
