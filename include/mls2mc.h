@@ -219,6 +219,16 @@ int mls2mc_next_step(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, 
                      double tau_ess, double eps, double* out3, double* logw_out,
                      double* w_out, void* stream);
 
+/* Look-ahead statistic of the level-update test (Sec. 4.4): for the
+ * weights w_j = exp(-scale d_j) on the N entries of d (the first J_tilde
+ * particles, d = Phi_{l+1} - Phi_l, scale = beta, i.e. one bridging step
+ * from zeta = 0 to 1), out2[0] = ESS = (sum w)^2 / sum w^2 and out2[1] =
+ * cv^2 = N / ESS - 1, the squared coefficient of variation of the weights
+ * with the population variance.  d: N doubles (device); out2: 2 doubles
+ * (device).  A non-finite d_j gives NaN in both outputs.  Requires
+ * 1 <= N <= 2^26 and scale >= 0.                                           */
+int mls2mc_cv_lu(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, double* out2, void* stream);
+
 /* ---- update-scheme decision (host function, no device work) ---- */
 #define MLS2MC_DECIDE_ITU 0     /* tempering update                        */
 #define MLS2MC_DECIDE_LU 1      /* level update                            */
@@ -233,8 +243,8 @@ int mls2mc_next_step(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, 
  * MLS2MC_SCHEME_MLS2MC or MLS2MC_SCHEME_MLB (multilevel bridging: tempering
  * up to beta = 1, then only level updates); cv_lu: coefficient of variation
  * of the level-update weights exp(-beta (Phi_{l+1} - Phi_l)) on the
- * look-ahead particles (mls2mc_next_step with mode CV_LU gives cv^2), or a
- * negative value when not computed; tau_lu: level-update threshold; tau_min:
+ * look-ahead particles (mls2mc_cv_lu gives its square), or a negative value
+ * when not computed; tau_lu: level-update threshold; tau_min:
  * the adaptive maximum level's threshold (0: off).
  * Rules: at beta = 1 and l = l_max: DONE.  At beta = 1: with tau_min > 0,
  * DONE when cv_lu < tau_min; otherwise LU.  Below beta = 1: ITU for
@@ -278,6 +288,18 @@ int mls2mc_gather(mls2mc_ctx* ctx, int64_t N, int64_t ncols, const int32_t* anc,
  * for tempering).  y: N_obs data.  xi: N x K normals; u: N uniforms in
  * (0,1).  accepted_out: N uint8 (may be NULL).  A proposal whose solve
  * fails (status != 0) is rejected.                                         */
+/* Linear test model (the linear-Gaussian setting of Sec. 2.1, where every
+ * tempered (Sec. 3.1) and bridged (Sec. 3.2) posterior is Gaussian in closed
+ * form): after this call the forward map of level l is
+ *   G_l(theta) = (A + 2^{-2l} E) theta
+ * in every single-instance entry point that evaluates G (mls2mc_forward,
+ * mls2mc_pcn_step, mls2mc_pcn_step_da, mls2mc_run), in place of the PDE;
+ * solver status and iteration outputs read 0.  A, E: host arrays of
+ * N_obs x K doubles (row-major), copied.  A = E = NULL restores the PDE.
+ * mls2mc_forward_field, mls2mc_forward_batch and mls2mc_run_batch return
+ * EINVAL while it is set.  For testing the sampler; synchronous.         */
+int mls2mc_set_linear_model(mls2mc_ctx* ctx, const double* A, const double* E);
+
 #define MLS2MC_KERNEL_PCN 0
 #define MLS2MC_KERNEL_RWM 1
 
@@ -414,6 +436,15 @@ typedef struct {
     double* stage_zeta;
     double* stage_ess;
     double* stage_acc_rate;
+    /* delayed acceptance: error of the surrogate against the FEM solve that
+     * judges each stage-1 survivor, e = ||G~(theta') - G(theta')||_2 / sigma_n
+     * with G on the finer level of the move: mean and max over the run, the
+     * number of survivors, and per stage (host arrays of max_stage_log
+     * entries, or NULL; NaN for stages without delayed acceptance)         */
+    double sur_err_mean, sur_err_max;
+    int64_t sur_err_count;
+    double* stage_sur_err_mean;
+    double* stage_sur_err_max;
 } mls2mc_run_result;
 
 /* Run MLS^2MC from the prior to beta = 1 on level l_max.  y: N_obs data

@@ -68,7 +68,9 @@ class RunResult(C.Structure):
                 ("sur_train_seconds", C.c_double), ("sur_final_loss", C.c_double),
                 ("graphs_launched", C.c_int64), ("max_stage_log", C.c_int), ("stage_type", _ip),
                 ("stage_level", _ip), ("stage_beta", _dp), ("stage_zeta", _dp),
-                ("stage_ess", _dp), ("stage_acc_rate", _dp)]
+                ("stage_ess", _dp), ("stage_acc_rate", _dp), ("sur_err_mean", C.c_double),
+                ("sur_err_max", C.c_double), ("sur_err_count", C.c_int64),
+                ("stage_sur_err_mean", _dp), ("stage_sur_err_max", _dp)]
 
 
 class ProfEntry(C.Structure):
@@ -109,6 +111,8 @@ def lib():
         L.mls2mc_next_step.argtypes = [_vp, C.c_int64, _vp, C.c_double, C.c_double, C.c_double,
                                        C.c_double, _vp, _vp, _vp, _vp]
         L.mls2mc_resample.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp]
+        L.mls2mc_cv_lu.argtypes = [_vp, C.c_int64, _vp, C.c_double, _vp, _vp]
+        L.mls2mc_set_linear_model.argtypes = [_vp, _dp, _dp]
         L.mls2mc_gather.argtypes = [_vp, C.c_int64, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp]
         L.mls2mc_pcn_step.argtypes = [_vp, C.POINTER(Stage), C.c_int64, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp, _vp]
@@ -274,6 +278,26 @@ def mls2mc_next_step(h, d, scale, cur, tau_ess, eps, out3, logw_out=None, w_out=
            "mls2mc_next_step")
 
 
+def mls2mc_cv_lu(h, d, scale, out2):
+    N = d.shape[0]
+    _check(lib().mls2mc_cv_lu(h, N, _ptr(d, torch.float64, (N,), "d"), scale,
+                              _ptr(out2, torch.float64, (2,), "out2"), _stream()), "mls2mc_cv_lu")
+
+
+def mls2mc_set_linear_model(h, A=None, E=None):
+    """A, E: host float64 arrays of N_obs x K (both or neither)"""
+    import numpy as np
+    if A is None and E is None:
+        _check(lib().mls2mc_set_linear_model(h, None, None), "mls2mc_set_linear_model")
+        return
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    if A.shape != E.shape or A.ndim != 2 or A.shape[0] != mls2mc_n_obs(h):
+        raise ValueError(f"A and E must both be N_obs x K, got {A.shape} and {E.shape}")
+    _check(lib().mls2mc_set_linear_model(h, A.ctypes.data_as(_dp), E.ctypes.data_as(_dp)),
+           "mls2mc_set_linear_model")
+
+
 def mls2mc_resample(h, w, u, anc_out):
     N = w.shape[0]
     _check(lib().mls2mc_resample(h, N, _ptr(w, torch.float64, (N,), "w"),
@@ -317,21 +341,25 @@ def _result_dict(res, arrs):
                not_converged=res.not_converged, seconds=res.seconds,
                stage1_passed=res.stage1_passed, da_proposed=res.da_proposed,
                sur_train_seconds=res.sur_train_seconds, sur_final_loss=res.sur_final_loss,
-               graphs_launched=res.graphs_launched)
+               graphs_launched=res.graphs_launched, sur_err_mean=res.sur_err_mean,
+               sur_err_max=res.sur_err_max, sur_err_count=res.sur_err_count)
     for k, v in arrs.items():
         out[k] = v[:n].copy()
     return out
 
 
+_STAGE_F64 = ("stage_beta", "stage_zeta", "stage_ess", "stage_acc_rate", "stage_sur_err_mean",
+              "stage_sur_err_max")
+
+
 def _stage_arrays(res, ms):
     import numpy as np
-    arrs = dict(stage_type=np.zeros(ms, np.int32), stage_level=np.zeros(ms, np.int32),
-                stage_beta=np.zeros(ms), stage_zeta=np.zeros(ms), stage_ess=np.zeros(ms),
-                stage_acc_rate=np.zeros(ms))
+    arrs = dict(stage_type=np.zeros(ms, np.int32), stage_level=np.zeros(ms, np.int32))
+    arrs.update({k: np.zeros(ms) for k in _STAGE_F64})
     res.max_stage_log = ms
     res.stage_type = arrs["stage_type"].ctypes.data_as(_ip)
     res.stage_level = arrs["stage_level"].ctypes.data_as(_ip)
-    for k in ("stage_beta", "stage_zeta", "stage_ess", "stage_acc_rate"):
+    for k in _STAGE_F64:
         setattr(res, k, arrs[k].ctypes.data_as(_dp))
     return arrs
 
@@ -356,30 +384,12 @@ def mls2mc_run_batch(h, cfg: RunConfig, instances, use_graphs=True, max_stage_lo
 
 
 def mls2mc_run(h, cfg: RunConfig, y, theta_out, max_stage_log=4000):
-    import numpy as np
     res = RunResult()
-    ms = max_stage_log
-    arrs = dict(stage_type=np.zeros(ms, np.int32), stage_level=np.zeros(ms, np.int32),
-                stage_beta=np.zeros(ms), stage_zeta=np.zeros(ms), stage_ess=np.zeros(ms),
-                stage_acc_rate=np.zeros(ms))
-    res.max_stage_log = ms
-    res.stage_type = arrs["stage_type"].ctypes.data_as(_ip)
-    res.stage_level = arrs["stage_level"].ctypes.data_as(_ip)
-    for k in ("stage_beta", "stage_zeta", "stage_ess", "stage_acc_rate"):
-        setattr(res, k, arrs[k].ctypes.data_as(_dp))
+    arrs = _stage_arrays(res, max_stage_log)
     _check(lib().mls2mc_run(h, C.byref(cfg), _ptr(y, torch.float64, name="y"),
                             _ptr(theta_out, torch.float64, name="theta_out"), C.byref(res),
                             _stream()), "mls2mc_run")
-    n = min(res.n_stages, ms)
-    out = dict(n_stages=res.n_stages, final_level=res.final_level, final_beta=res.final_beta,
-               log_Z=res.log_Z, solves=list(res.solves), accepted=res.accepted,
-               proposed=res.proposed, iters_total=res.iters_total,
-               not_converged=res.not_converged, seconds=res.seconds,
-               stage1_passed=res.stage1_passed, da_proposed=res.da_proposed,
-               sur_train_seconds=res.sur_train_seconds, sur_final_loss=res.sur_final_loss)
-    for k, v in arrs.items():
-        out[k] = v[:n].copy()
-    return out
+    return _result_dict(res, arrs)
 
 
 def mls2mc_surrogate_init(h, hidden=256, capacity=20480, seed=0):
@@ -550,6 +560,18 @@ class Context:
         w = torch.empty(N, dtype=torch.float64, device=d.device)
         mls2mc_next_step(self.h, d, scale, cur, tau_ess, eps, out3, logw, w)
         return out3, logw, w
+
+    def cv_lu(self, d, scale):
+        """device tensor {ESS, cv^2} of the weights exp(-scale d)"""
+        out2 = torch.empty(2, dtype=torch.float64, device=d.device)
+        mls2mc_cv_lu(self.h, d, scale, out2)
+        return out2
+
+    def set_linear_model(self, A=None, E=None):
+        """G_l(theta) = (A + 2^{-2l} E) theta in place of the PDE (None, None: back to the PDE)"""
+        if A is not None and A.shape[1] != self.K:
+            raise ValueError(f"A must have K = {self.K} columns")
+        mls2mc_set_linear_model(self.h, A, E)
 
     def resample(self, w, u):
         anc = torch.empty(w.shape[0], dtype=torch.int32, device=w.device)

@@ -62,6 +62,8 @@ int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double
                   int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s,
                   const int64_t* N_dev)
 {
+    if (ctx->d_lin_A)  // linear test model in place of the PDE
+        return launch_linear_forward(ctx, l, N, theta, G, status, iters, y, phi, s, N_dev);
     const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     const int64_t ne = n_elem(l);
@@ -218,6 +220,7 @@ int mls2mc_destroy(mls2mc_ctx* ctx)
     if (ctx->h_list_ev) (void)hipEventDestroy(ctx->h_list_ev);
     surrogate_destroy(ctx);
     if (ctx->d_chunk_count) (void)hipFree(ctx->d_chunk_count);
+    if (ctx->d_lin_A) (void)hipFree(ctx->d_lin_A);
     prof_clear(ctx);
     if (ctx->d_prof_iters) (void)hipFree(ctx->d_prof_iters);
     delete ctx;
@@ -307,6 +310,7 @@ int mls2mc_forward_field(mls2mc_ctx* ctx, int l, int64_t N, const double* kappa,
     MLS_TRY(check_level(ctx, l));
     MLS_REQUIRE(N >= 0, "forward_field: N < 0");
     MLS_REQUIRE(N == 0 || (kappa && G_out), "forward_field: null pointer");
+    MLS_REQUIRE(!ctx->d_lin_A, "forward_field: not defined while the linear test model is set");
     if (N == 0) return MLS2MC_OK;
     const hipStream_t s = (hipStream_t)stream;
     const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
@@ -349,6 +353,46 @@ int mls2mc_next_step(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, 
     MLS_REQUIRE(eps > 0.0 && std::isfinite(scale) && scale >= 0.0, "next_step: need eps > 0, scale >= 0");
     return launch_next_step(ctx, N, d, scale, cur, tau_ess, eps, out3, logw_out, w_out,
                             (hipStream_t)stream);
+}
+
+int mls2mc_cv_lu(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, double* out2, void* stream)
+{
+    MLS_REQUIRE(ctx != nullptr, "null context");
+    MLS_REQUIRE(N >= 1 && N <= (int64_t(1) << 26), "cv_lu: need 1 <= N <= 2^26");
+    MLS_REQUIRE(d && out2, "cv_lu: null pointer");
+    MLS_REQUIRE(std::isfinite(scale) && scale >= 0.0, "cv_lu: need scale >= 0");
+    return launch_ess_cv(N, nullptr, d, scale, out2, (hipStream_t)stream);
+}
+
+int mls2mc_set_linear_model(mls2mc_ctx* ctx, const double* A, const double* E)
+{
+    MLS_REQUIRE(ctx != nullptr, "null context");
+    MLS_REQUIRE((A == nullptr) == (E == nullptr), "set_linear_model: give both A and E, or neither");
+    MLS_CHECK_HIP(hipDeviceSynchronize());  // work in flight may still read the old tables
+    if (ctx->d_lin_A) (void)hipFree(ctx->d_lin_A);
+    ctx->d_lin_A = ctx->d_lin_E = nullptr;
+    if (!A) return MLS2MC_OK;
+    const size_t n = (size_t)ctx->nobs * ctx->prob.K;
+    for (size_t i = 0; i < n; ++i)
+        MLS_REQUIRE(std::isfinite(A[i]) && std::isfinite(E[i]), "set_linear_model: non-finite entry");
+    double* d = nullptr;
+    if (hipMalloc(&d, 2 * n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("set_linear_model: device allocation failed");
+        return MLS2MC_ENOMEM;
+    }
+    int rc = MLS2MC_OK;
+    if (hipMemcpy(d, A, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d + n, E, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d);
+        set_error("set_linear_model: copy to the device failed");
+        rc = MLS2MC_EDEVICE;
+    } else {
+        ctx->d_lin_A = d;
+        ctx->d_lin_E = d + n;
+    }
+    return rc;
 }
 
 int mls2mc_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u, int32_t* anc_out,

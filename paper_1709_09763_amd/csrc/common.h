@@ -130,6 +130,10 @@ struct mls2mc_ctx {
     size_t h_list_bytes = 0;
     hipEvent_t h_list_ev = nullptr;   // last copy out of h_list
     int64_t* d_chunk_count = nullptr; // per-chunk device counts
+    double* d_lin_A = nullptr;        // linear test model (N_obs x K each), or null
+    double* d_lin_E = nullptr;
+    double* da_err = nullptr;         // while mls2mc_run runs with the surrogate: accumulator of the
+                                      // surrogate's error against stage-2 solves {sum, max, count}
 };
 
 namespace mls {
@@ -228,6 +232,9 @@ int launch_ess_cv(int64_t N, const double* dlo, const double* dhi, double scale,
                   hipStream_t s);
 int launch_reduce_i32(int64_t N, const int32_t* v, const int8_t* st, int64_t* out2,
                       hipStream_t s);
+int launch_linear_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
+                          int8_t* status, int32_t* iters, const double* y, double* phi,
+                          hipStream_t s, const int64_t* N_dev);
 int launch_d2f(const double* a, float* b, int64_t n, hipStream_t s);
 int prof_begin(mls2mc_ctx* ctx, int kclass, int l, int64_t items, hipStream_t s, ProfRec* rec);
 int prof_end(mls2mc_ctx* ctx, int kclass, int l, const ProfRec& rec, hipStream_t s);

@@ -43,6 +43,11 @@ __global__ void diff_kernel(int64_t n, const double* __restrict__ a, const doubl
     if (t < n) d[t] = a[t] - b[t];
 }
 
+__global__ void zero_kernel(int n, double* __restrict__ v)
+{
+    if ((int)threadIdx.x < n) v[threadIdx.x] = 0.0;
+}
+
 __global__ void count_u8_kernel(int64_t n, const uint8_t* __restrict__ v, int64_t* __restrict__ out)
 {
     __shared__ int64_t part[256];
@@ -60,7 +65,7 @@ __global__ void count_u8_kernel(int64_t n, const uint8_t* __restrict__ v, int64_
 struct RunState {
     double *theta, *Glo, *Ghi, *plo, *phi;      // current state
     double *theta2, *Glo2, *Ghi2, *plo2, *phi2; // gather targets
-    double *d, *w, *u, *xi, *upcn, *upcn2, *out3, *cv;
+    double *d, *w, *u, *xi, *upcn, *upcn2, *out3, *cv, *sur_err;
     int32_t* anc;
     uint8_t* acc;
     uint8_t* pass1;
@@ -97,7 +102,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
 
     // ---- state buffers
     size_t nd = 2 * ((size_t)J * K + 2 * (size_t)J * nobs + 2 * (size_t)J);  // state + gather
-    nd += 3 * (size_t)J + (size_t)J * K + 2 * (size_t)J + 8;                 // d w u xi upcn(2) out3 cv
+    nd += 3 * (size_t)J + (size_t)J * K + 2 * (size_t)J + 12;                // d w u xi upcn(2) out3 cv sur_err
     size_t bytes = nd * sizeof(double) + (size_t)J * (sizeof(int32_t) * 2 + 3) + 64 * sizeof(int64_t);
     const bool use_sur = cfg->surrogate != 0;
     const int sur_collect = cfg->sur_collect_max_level;
@@ -117,7 +122,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     R.plo2 = take(J); R.phi2 = take(J);
     R.d = take(J); R.w = take(J); R.u = take(J); R.xi = take((size_t)J * K); R.upcn = take(J);
     R.upcn2 = take(J);
-    R.out3 = take(4); R.cv = take(4);
+    R.out3 = take(4); R.cv = take(4); R.sur_err = take(4);
     R.counters = reinterpret_cast<int64_t*>(p); p += 32;
     R.it = reinterpret_cast<int32_t*>(p);
     R.anc = R.it + J;
@@ -125,6 +130,8 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     R.acc = reinterpret_cast<uint8_t*>(R.st + J);
     R.pass1 = R.acc + J;
     MLS_CHECK_HIP(hipMemsetAsync(R.counters, 0, 32 * sizeof(int64_t), s));
+    zero_kernel<<<1, 64, 0, s>>>(4, R.sur_err);
+    MLS_CHECK_HIP(hipGetLastError());
 
     res->n_stages = 0;
     res->log_Z = 0.0;
@@ -134,7 +141,16 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     res->sur_train_seconds = 0.0;
     res->sur_final_loss = 0.0;
     res->graphs_launched = 0;
+    res->sur_err_mean = res->sur_err_max = 0.0;
+    res->sur_err_count = 0;
+    double sur_err_sum = 0.0;
     bool sur_ready = false;
+    // the delayed-acceptance steps accumulate the surrogate's error here while the run lasts
+    struct ErrSlot {
+        mls2mc_ctx* c;
+        ~ErrSlot() { c->da_err = nullptr; }
+    } err_slot{ctx};
+    ctx->da_err = use_sur ? R.sur_err : nullptr;
     if (use_sur) {
         MLS_TRY(mls2mc_surrogate_init(ctx, cfg->sur_hidden > 0 ? cfg->sur_hidden : 256,
                                       cfg->sur_pairs > 0 ? cfg->sur_pairs : 20480, cfg->seed ^ 0x51u, stream));
@@ -237,6 +253,24 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
         *out = (double)c3[2];
         return MLS2MC_OK;
     };
+    // the stage's surrogate error {sum, max, count} -> per-stage log and run totals
+    auto log_sur_err = [&](int stage_idx) -> int {
+        double e[3] = {0.0, 0.0, 0.0};
+        if (use_sur) {
+            MLS_CHECK_HIP(hipMemcpyAsync(e, R.sur_err, sizeof(e), hipMemcpyDeviceToHost, s));
+            zero_kernel<<<1, 64, 0, s>>>(4, R.sur_err);
+            MLS_CHECK_HIP(hipGetLastError());
+            MLS_CHECK_HIP(hipStreamSynchronize(s));
+        }
+        if (stage_idx < res->max_stage_log) {
+            if (res->stage_sur_err_mean) res->stage_sur_err_mean[stage_idx] = e[2] > 0 ? e[0] / e[2] : NAN;
+            if (res->stage_sur_err_max) res->stage_sur_err_max[stage_idx] = e[2] > 0 ? e[1] : NAN;
+        }
+        sur_err_sum += e[0];
+        res->sur_err_count += (int64_t)e[2];
+        if (e[1] > res->sur_err_max) res->sur_err_max = e[1];
+        return MLS2MC_OK;
+    };
 
     // ---- prior draw and first evaluation
     MLS_TRY(launch_philox(cfg->seed, ST_PRIOR, 0, 0, J * K, 1, R.theta, s));
@@ -301,6 +335,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
             log_stage(checked ? 1 : 0, l, beta, 0.0, h[2]);
             if (res->stage_acc_rate && stage < res->max_stage_log)
                 res->stage_acc_rate[stage] = cfg->n_mcmc ? (acc_host - a0) / ((double)J * cfg->n_mcmc) : 0.0;
+            MLS_TRY(log_sur_err(stage));
             ++stage;
             prev_lu = false;
         } else {
@@ -328,6 +363,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
                 log_stage(first ? (checked ? 2 : 3) : 4, l + 1, beta, zeta, h[2]);
                 if (res->stage_acc_rate && stage < res->max_stage_log)
                     res->stage_acc_rate[stage] = cfg->n_mcmc ? (acc_host - a0) / ((double)J * cfg->n_mcmc) : 0.0;
+                MLS_TRY(log_sur_err(stage));
                 first = false;
                 ++stage;
             }
@@ -349,6 +385,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     res->accepted = c3[2];
     res->stage1_passed = c3[3];
     for (int lv = 0; lv <= kMaxLevel && lv < 16; ++lv) res->solves[lv] += c3[8 + lv];  // delayed-acceptance solves
+    res->sur_err_mean = res->sur_err_count ? sur_err_sum / (double)res->sur_err_count : 0.0;
     res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }

@@ -111,6 +111,7 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
     MLS_REQUIRE(ctx && cfg && inst && res, "run_batch: null argument");
     MLS_REQUIRE(n_inst >= 1 && n_inst <= 4096, "run_batch: need 1 <= n_inst <= 4096");
     MLS_REQUIRE(ctx->prob.bc == MLS2MC_BC_DIRICHLET, "run_batch: Dirichlet problem only");
+    MLS_REQUIRE(!ctx->d_lin_A, "run_batch: the linear test model runs through the single-instance entry points");
     MLS_REQUIRE(cfg->surrogate == 0 && cfg->s_adapt == 0 && cfg->scheme == MLS2MC_SCHEME_MLS2MC &&
                     cfg->tau_min == 0.0 && cfg->kernel == MLS2MC_KERNEL_PCN,
                 "run_batch: the surrogate form, pCN step adaptation, other schemes and kernels, and the "
@@ -152,6 +153,8 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
         r.n_stages = 0; r.log_Z = 0.0; r.accepted = r.proposed = 0; r.iters_total = 0; r.not_converged = 0;
         r.stage1_passed = r.da_proposed = 0; r.sur_train_seconds = 0; r.sur_final_loss = 0;
         r.graphs_launched = 0;
+        r.sur_err_mean = r.sur_err_max = 0.0;
+        r.sur_err_count = 0;
         for (int k = 0; k < 16; ++k) r.solves[k] = 0;
     }
     MLS_TRY(ctx->ws_batch.ensure(total));

@@ -346,6 +346,38 @@ __global__ void gather_count_kernel(int64_t N, int ncols, const int32_t* __restr
     dst[t] = src[(int64_t)idx[c] * ncols + k];
 }
 
+// Error of the surrogate against the FEM solve that judges it in stage 2:
+// e_c = ||G~(theta'_j) - G(theta'_j)||_2 / sigma_n for the survivors c <
+// count (j = idx[c]); acc[0] += sum e, acc[1] = max(acc[1], max e),
+// acc[2] += number of survivors.  One workgroup, deterministic sums.
+__global__ __launch_bounds__(256) void da_err_kernel(int64_t N, const int64_t* __restrict__ count,
+                                                     const int32_t* __restrict__ idx, int nobs,
+                                                     const double* __restrict__ Gs, const double* __restrict__ Gf,
+                                                     double inv_sigma, double* __restrict__ acc)
+{
+    __shared__ double red[4];
+    const int64_t n = count[0] < N ? count[0] : N;
+    double sum = 0.0, mx = 0.0;
+    for (int64_t c = threadIdx.x; c < n; c += 256) {
+        const int64_t j = idx[c];
+        double e2 = 0.0;
+        for (int o = 0; o < nobs; ++o) {
+            const double d = Gs[j * nobs + o] - Gf[c * nobs + o];
+            e2 += d * d;
+        }
+        const double e = sqrt(e2) * inv_sigma;
+        sum += e;
+        mx = fmax(mx, e);
+    }
+    sum = block_sum<256>(sum, red);
+    mx = block_max<256>(mx, red);
+    if (threadIdx.x == 0) {
+        acc[0] += sum;
+        acc[1] = fmax(acc[1], mx);
+        acc[2] += (double)n;
+    }
+}
+
 // stage 2 for the survivors: Psi of the FEM solve corrected by the surrogate
 __global__ void da_stage2_kernel(int64_t N, const int64_t* __restrict__ count, const int32_t* __restrict__ idx,
                                  int K, int nobs, int mode, double beta, double zeta,
@@ -641,6 +673,10 @@ int mls2mc_pcn_step_da(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, doubl
     MLS_CHECK_HIP(hipGetLastError());
     if (need_lo) MLS_TRY(forward_theta(ctx, st->l_lo, N, thc, Gcl, stl, itl, y, pcl, s, count));
     if (need_hi) MLS_TRY(forward_theta(ctx, st->l_hi, N, thc, Gch, sth, ith, y, pch, s, count));
+    if (ctx->da_err) {  // the surrogate's error against the finer level's solve
+        da_err_kernel<<<1, 256, 0, s>>>(N, count, idx, nobs, Gs2, need_hi ? Gch : Gcl, inv_sigma, ctx->da_err);
+        MLS_CHECK_HIP(hipGetLastError());
+    }
     const int mode = !bridge ? 0 : (st->zeta < 1.0 ? 1 : 2);
     da_stage2_kernel<<<gN, 256, 0, s>>>(N, count, idx, K, nobs, mode, st->beta, st->zeta, u2, ps_old, ps_new, thn,
                                        Gcl, Gch, pcl, pch, stl, sth, theta, G_lo, G_hi, phi_lo, phi_hi,

@@ -120,8 +120,9 @@ int launch_next_step(mls2mc_ctx*, int64_t N, const double* d, double scale, doub
     return MLS2MC_OK;
 }
 
-// ESS at t = 1 of d = dhi - dlo with the given scale (the look-ahead cv^LU
-// of Sec. 4.4 is sqrt(N/ESS - 1)).
+// ESS at t = 1 of the weights exp(-scale d), d = dhi - dlo (dlo may be null:
+// d = dhi); out[0] = ESS, out[1] = N / ESS - 1 = (cv^LU)^2 of the level-update
+// test of Sec. 4.4 (population variance, so ESS = N / (1 + cv^2)).
 __global__ __launch_bounds__(kNS) void ess_diff_kernel(int64_t N, const double* __restrict__ dlo,
                                                        const double* __restrict__ dhi,
                                                        double scale, double* __restrict__ out)
@@ -129,23 +130,79 @@ __global__ __launch_bounds__(kNS) void ess_diff_kernel(int64_t N, const double* 
     __shared__ double red[kNS / 64];
     const double a = -1.0 * scale;
     double mx = -INFINITY;
-    for (int64_t j = threadIdx.x; j < N; j += kNS) mx = fmax(mx, a * (dhi[j] - dlo[j]));
+    int bad = 0;
+    for (int64_t j = threadIdx.x; j < N; j += kNS) {
+        const double v = dlo ? dhi[j] - dlo[j] : dhi[j];
+        if (!isfinite(v)) bad = 1;
+        mx = fmax(mx, a * v);
+    }
     mx = block_max<kNS>(mx, red);
+    const double nbad = block_sum<kNS>((double)bad, red);
+    if (nbad > 0.0) {
+        if (threadIdx.x == 0) out[0] = out[1] = NAN;
+        return;
+    }
     double s1 = 0.0, s2 = 0.0;
     for (int64_t j = threadIdx.x; j < N; j += kNS) {
-        const double v = exp(a * (dhi[j] - dlo[j]) - mx);
+        const double v = exp(a * (dlo ? dhi[j] - dlo[j] : dhi[j]) - mx);
         s1 += v;
         s2 += v * v;
     }
     s1 = block_sum<kNS>(s1, red);
     s2 = block_sum<kNS>(s2, red);
-    if (threadIdx.x == 0) out[0] = s1 * s1 / s2;
+    if (threadIdx.x == 0) {
+        const double e = s1 * s1 / s2;
+        out[0] = e;
+        out[1] = (double)N / e - 1.0;
+    }
 }
 
 int launch_ess_cv(int64_t N, const double* dlo, const double* dhi, double scale, double* out,
                   hipStream_t s)
 {
     ess_diff_kernel<<<1, kNS, 0, s>>>(N, dlo, dhi, scale, out);
+    MLS_CHECK_HIP(hipGetLastError());
+    return MLS2MC_OK;
+}
+
+// ------------------------------------------------ linear test model --
+// G_l(theta) = (A + 2^{-2l} E) theta (A, E: N_obs x K, row-major), with the
+// fused potential when y is given: a stand-in forward map for which the
+// tempered and bridged posteriors are Gaussian in closed form.  One thread
+// per particle; only the first min(N, *N_dev) rows when N_dev is given.
+__global__ void linear_forward_kernel(int64_t N, const int64_t* __restrict__ N_dev, int K, int nobs,
+                                      double sc, const double* __restrict__ A,
+                                      const double* __restrict__ E, const double* __restrict__ th,
+                                      double* __restrict__ G, const double* __restrict__ y,
+                                      double inv_sigma, double* __restrict__ phi,
+                                      int8_t* __restrict__ status, int32_t* __restrict__ iters)
+{
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n = N_dev ? (*N_dev < N ? *N_dev : N) : N;
+    if (q >= n) return;
+    double ph = 0.0;
+    for (int o = 0; o < nobs; ++o) {
+        double g = 0.0;
+        for (int k = 0; k < K; ++k) g += (A[o * K + k] + sc * E[o * K + k]) * th[q * K + k];
+        G[q * nobs + o] = g;
+        if (y) {
+            const double r = (y[o] - g) * inv_sigma;
+            ph += r * r;
+        }
+    }
+    if (y && phi) phi[q] = 0.5 * ph;
+    if (status) status[q] = 0;
+    if (iters) iters[q] = 0;
+}
+
+int launch_linear_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
+                          int8_t* status, int32_t* iters, const double* y, double* phi,
+                          hipStream_t s, const int64_t* N_dev)
+{
+    if (N == 0) return MLS2MC_OK;
+    linear_forward_kernel<<<(unsigned)((N + 127) / 128), 128, 0, s>>>(
+        N, N_dev, ctx->prob.K, ctx->nobs, std::ldexp(1.0, -2 * l), ctx->d_lin_A, ctx->d_lin_E, theta, G, y,
+        1.0 / ctx->prob.sigma_n, phi, status, iters);
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
 }

@@ -1379,6 +1379,7 @@ extern "C" int mls2mc_forward_batch(mls2mc_ctx* ctx, int n_items, const mls2mc_f
     MLS_REQUIRE(ctx != nullptr, "null context");
     MLS_REQUIRE(n_items >= 0 && n_items <= 65536, "forward_batch: need 0 <= n_items <= 65536");
     MLS_REQUIRE(n_items == 0 || items, "forward_batch: null items");
+    MLS_REQUIRE(!ctx->d_lin_A, "forward_batch: the linear test model runs through the single-instance entry points");
     std::vector<FwdItem> v;
     for (int i = 0; i < n_items; ++i) {
         const mls2mc_forward_item& it = items[i];

@@ -70,3 +70,40 @@ def test_run_batch_reproduces_single_runs():
             assert abs(o["log_Z"] - r["log_Z"]) < 1e-9 * max(1, abs(r["log_Z"]))
             assert rel_err(host(o["theta"]), host(r["theta"])) < 1e-12
         assert torch.equal(og["theta"], oe["theta"])
+
+
+def test_run_batch_matches_oracle_at_configured_sizes():
+    """Three instances of the batched workload's problem (K = 100 KL terms,
+    49 observations, sigma_n = 0.002, h = 1/8 up to 1/64 or 1/128, J of 256
+    to 512) in one fused run_batch with HIP graphs: every instance equals the
+    oracle's sampler on the same Philox streams, stage for stage."""
+    device()
+    K, m, sn = 100, 7, 0.002
+    specs = [(384, 6, 0), (512, 6, 1), (256, 7, 2)]
+    c = P.Context(3, 7, K, 1.0, 0.3, m, sn)
+    inst = []
+    for J, lmax, seed in specs:
+        th_true = inputs.theta_batch(800 + seed, 1, K)
+        y = oracle.forward(lmax, K, 1.0, 0.3, m, th_true)[0] + sn * inputs.rng(900 + seed).standard_normal(m * m)
+        inst.append(dict(J=J, l_max=lmax, y=to_dev(y), seed=seed, y_host=y))
+    case("run_batch K=100 Nobs=49 J 256..512, l_max 6/7")
+    out = c.run_batch([dict(J=d["J"], l_max=d["l_max"], y=d["y"], seed=d["seed"]) for d in inst],
+                      use_graphs=True)
+    for d, o in zip(inst, out):
+        case(f"oracle run J={d['J']} l_max={d['l_max']} seed={d['seed']}")
+        r = oracle.run_sampler(d["y_host"], l_min=3, l_max=d["l_max"], K=K, m=m, sigma_n=sn, J=d["J"],
+                               J_tilde=100, seed=d["seed"], n_mcmc=5, s_pcn=0.5)
+        print(f"  stages {o['n_stages']} / {r['n_stages']}, solves {o['solves'][3:8]} / {r['solves'][3:8]}")
+        assert o["n_stages"] == r["n_stages"]
+        assert o["final_level"] == r["final_level"] == d["l_max"] and o["final_beta"] == r["final_beta"]
+        np.testing.assert_array_equal(o["stage_type"], r["stage_type"])
+        np.testing.assert_array_equal(o["stage_level"], r["stage_level"])
+        np.testing.assert_allclose(o["stage_beta"], r["stage_beta"], rtol=1e-8)
+        np.testing.assert_allclose(o["stage_zeta"], r["stage_zeta"], rtol=1e-8, atol=1e-12)
+        assert o["solves"] == r["solves"]
+        assert o["accepted"] == r["accepted"]
+        assert abs(o["log_Z"] - r["log_Z"]) < 1e-7 * max(1, abs(r["log_Z"]))
+        th = host(o["theta"])
+        assert rel_err(th.mean(0), r["theta"].mean(0)) < 1e-8
+        assert rel_err(th.var(0), r["theta"].var(0)) < 1e-8
+        assert o["not_converged"] == 0

@@ -168,6 +168,32 @@ def test_mixed_bf16_field_error_bound():
     print(f"  max |a_bf16 - a| = {err.max():.3e}")
 
 
+@pytest.mark.parametrize("l,N", [(3, 64), (5, 64), (6, 32), (7, 16), (8, 8)])
+def test_mixed_forward_error_against_oracle_per_level(l, N):
+    """The whole mixed form (BF16 KL GEMM, FP32 solver with FP64 residual
+    replacement) against the FP64 oracle on prior draws, K = 100, 49
+    observations.  Its error is the BF16 field's: every element's log-field
+    is off by at most eps_q = 2^-7 sum_k |theta_qk B_ke| (1.05 for the FP32
+    sum), so kappa by a factor within exp(+-eps_q); the observations, weighted
+    averages of p, stay within 2 eps_q of the FP64 values relative to their
+    size.  The measured error is printed per level."""
+    device()
+    K, m = 100, 7
+    case(f"mixed forward vs oracle l={l} N={N}")
+    ctx = P.Context(l, l, K, 1.0, 0.3, m, 0.002, precision=P.MIXED)
+    th = inputs.theta_batch(600 + l, N, K)
+    G, st, it = ctx.forward(l, to_dev(th), with_stats=True)
+    Gr = oracle.forward(l, K, 1.0, 0.3, m, th)
+    B = oracle.kl_basis(l, K, 1.0, 0.3)
+    eps = 2.0 ** -7 * 1.05 * (np.abs(th) @ np.abs(B)).max(1)
+    Gh = host(G)
+    assert (host(st) == 0).all()
+    err = np.abs(Gh - Gr).max(1) / np.abs(Gr).max(1)
+    print(f"  h=1/{1 << l}: max rel G error {err.max():.2e} (median {np.median(err):.2e}), "
+          f"max bound 2 eps {2 * eps.max():.2e}, mean iters {host(it).mean():.1f}")
+    assert np.all(err <= 2 * eps)
+
+
 LDS_MAX = 160 * 1024 - 1024  # gfx950: 160 KiB of LDS per workgroup, 1 KiB kept for static arrays
 
 

@@ -203,6 +203,37 @@ def test_run_matches_oracle(cfg):
     assert g["not_converged"] == 0
 
 
+def test_run_matches_oracle_on_the_stage_benchmark_problem():
+    """The stage benchmark's problem end to end: h = 1/8 ... 1/64, K = 50,
+    25 observations (barycentric points), sigma_n = 0.005, J = 1000, with the
+    launch shapes the benchmark's tuner picks for it."""
+    device()
+    K, m, sn, J = 50, 5, 0.005, 1000
+    case("run h=1/8..1/64 K=50 Nobs=25 J=1000")
+    th_true = inputs.theta_batch(4242, 1, K)
+    y = oracle.forward(6, K, 1.0, 0.3, m, th_true)[0] + sn * inputs.rng(4243).standard_normal(m * m)
+    ctx = P.Context(3, 6, K, 1.0, 0.3, m, sn)
+    for lv in range(3, 7):
+        ctx.autotune(lv, J)
+    g = ctx.run(to_dev(y), J, J_tilde=100, tau_star=1.0, n_mcmc=5, s_pcn=0.5, seed=11)
+    r = oracle.run_sampler(y, l_min=3, l_max=6, K=K, m=m, sigma_n=sn, J=J, J_tilde=100, seed=11, n_mcmc=5,
+                           s_pcn=0.5)
+    print(f"  stages gpu {g['n_stages']} oracle {r['n_stages']}, solves {g['solves'][3:7]}, "
+          f"launches {[ctx.get_launch(lv) for lv in range(3, 7)]}")
+    assert g["n_stages"] == r["n_stages"] and g["final_level"] == r["final_level"] == 6
+    np.testing.assert_array_equal(g["stage_type"], r["stage_type"])
+    np.testing.assert_array_equal(g["stage_level"], r["stage_level"])
+    np.testing.assert_allclose(g["stage_beta"], r["stage_beta"], rtol=1e-8)
+    np.testing.assert_allclose(g["stage_zeta"], r["stage_zeta"], rtol=1e-8, atol=1e-12)
+    assert g["solves"] == r["solves"]
+    assert g["accepted"] == r["accepted"]
+    assert abs(g["log_Z"] - r["log_Z"]) < 1e-7 * max(1, abs(r["log_Z"]))
+    th = host(g["theta"])
+    assert rel_err(th.mean(0), r["theta"].mean(0)) < 1e-8
+    assert rel_err(th.var(0), r["theta"].var(0)) < 1e-8
+    assert g["not_converged"] == 0
+
+
 def test_run_is_deterministic():
     device()
     case("run determinism")

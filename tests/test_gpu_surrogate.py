@@ -155,31 +155,55 @@ def test_delayed_acceptance_decisions_match_oracle_rule(mode):
     assert rel_err(host(GL), np.where(acc_ref[:, None], Glp, Glo)) < 1e-10
 
 
+def _moves_at(r, J, n_mcmc, lmin):
+    """accepted pCN moves on the stages whose level is >= lmin"""
+    sel = r["stage_level"] >= lmin
+    return float(np.sum(r["stage_acc_rate"][sel]) * J * n_mcmc)
+
+
+def _rel_err_paper(mean, ref, lam):
+    """the paper's relative error of a posterior mean, Lambda^{1/2}-weighted l1 (Sec. 5.1)"""
+    w = np.sqrt(lam)
+    return float(np.abs(w * (mean - ref)).sum() / np.abs(w * ref).sum())
+
+
 def test_surrogate_gain_in_the_sampler():
-    """the trained network screens proposals: far fewer FEM solves per
-    proposal on the delayed-acceptance levels, same posterior (MC error)"""
+    """What the trained network gains on the delayed-acceptance levels
+    (h = 1/32, 1/64): the chain still moves (accepted moves comparable to
+    the plain sampler's) while far fewer proposals reach the FEM solve, so
+    accepted moves per FEM solve improve; and the posterior mean is as
+    accurate (the paper's relative error against the mean pooled over four
+    seeds of each form)."""
     device()
-    case("sampler with vs without surrogate")
-    K, m, sn, J = 20, 5, 0.005, 1000
+    case("sampler with vs without surrogate, 4 seeds")
+    K, m, sn, J, n_mcmc = 20, 5, 0.005, 1000, 5
     c = P.Context(3, 6, K, 1.0, 0.3, m, sn)
+    lam = c.kl_eigenvalues()
     th_true = inputs.theta_batch(30, 1, K)
     y = to_dev(oracle.forward(6, K, 1.0, 0.3, m, th_true)[0] + sn * inputs.rng(31).standard_normal(m * m))
-    plain = c.run(y, J, seed=4)
-    da = c.run(y, J, seed=4, surrogate=True, sur_collect_max_level=4, sur_da_min_level=5, sur_pairs=20480,
-               sur_epochs=30, sur_hidden=128)
-    frac = da["stage1_passed"] / max(1, da["da_proposed"])
-    acc_plain = plain["accepted"] / plain["proposed"]
-    print(f"  plain: {plain['seconds']:.2f}s solves {plain['solves'][3:7]} acc {acc_plain:.3f}")
-    print(f"  DA:    {da['seconds']:.2f}s solves {da['solves'][3:7]} stage-1 pass {frac:.3f} "
-          f"train {da['sur_train_seconds']:.2f}s loss {da['sur_final_loss']:.4f}")
-    assert da["da_proposed"] > 0
-    assert frac < 0.6  # most proposals never reach the FEM solve
-    assert sum(da["solves"][5:7]) < 0.7 * sum(plain["solves"][5:7])
-    a = host(plain["theta"])
-    b = host(da["theta"])
-    sd = np.sqrt(0.5 * (a.var(0) + b.var(0)))
-    # pCN particles are correlated: allow an effective sample size of J/10
-    assert np.all(np.abs(a.mean(0) - b.mean(0)) < 5 * sd * np.sqrt(2 / (J / 10)))
+    plain, da = [], []
+    for seed in (4, 5, 6, 7):
+        plain.append(c.run(y, J, seed=seed))
+        da.append(c.run(y, J, seed=seed, surrogate=True, sur_collect_max_level=4, sur_da_min_level=5,
+                        sur_pairs=20480, sur_epochs=30, sur_hidden=128))
+    for p_, d_ in zip(plain, da):
+        frac = d_["stage1_passed"] / max(1, d_["da_proposed"])
+        mp, md = _moves_at(p_, J, n_mcmc, 5), _moves_at(d_, J, n_mcmc, 5)
+        sp, sd_ = sum(p_["solves"][5:7]), sum(d_["solves"][5:7])
+        print(f"  plain {p_['seconds']:.2f}s: {mp:.0f} moves / {sp} solves on h <= 1/32; "
+              f"DA {d_['seconds']:.2f}s: {md:.0f} moves / {sd_} solves, stage-1 pass {frac:.3f}, "
+              f"surrogate error {d_['sur_err_mean']:.2f} (max {d_['sur_err_max']:.2f}) sigma_n")
+        assert d_["da_proposed"] > 0
+        assert frac < 0.6  # most proposals never reach the FEM solve
+        assert sd_ < 0.7 * sp
+        assert md > 0.5 * mp  # the chain does not stall behind the screen
+        assert md / sd_ > 1.3 * (mp / sp)  # more accepted moves per FEM solve
+        assert d_["sur_err_count"] == d_["stage1_passed"] and d_["sur_err_mean"] > 0
+    pooled = np.mean([host(r["theta"]).mean(0) for r in plain + da], axis=0)
+    e_plain = np.mean([_rel_err_paper(host(r["theta"]).mean(0), pooled, lam) for r in plain])
+    e_da = np.mean([_rel_err_paper(host(r["theta"]).mean(0), pooled, lam) for r in da])
+    print(f"  RelErr vs the pooled mean: plain {e_plain:.3f}, DA {e_da:.3f}")
+    assert e_da < 1.5 * e_plain + 0.02
 
 
 def test_delayed_acceptance_across_forward_chunks():
@@ -232,3 +256,113 @@ def test_delayed_acceptance_across_forward_chunks():
     np.testing.assert_array_equal(GLh[~acc_ref], Glo[~acc_ref])
     assert rel_err(GLh[acc_ref], Glp[acc_ref]) < 1e-10
     assert rel_err(host(T), np.where(acc_ref[:, None], thp, th)) < 1e-15
+
+
+# ---- the network of the configured surrogate: 100 -> 256 -> 256 -> 49 ----
+# Element-by-element tolerances from the arithmetic: every matrix product
+# rounds both operands to BF16 (relative error <= 2^-8 each) and accumulates
+# in FP32, so one product sum_k a_k b_k is off by at most
+# GAMMA * sum_k |a_k b_k|.  The bounds below carry that through the layers
+# with |GELU'| <= 1.13 and |GELU''| <= 0.8, starting from the FP64 reference
+# activations (a first-order running error bound; SAFETY covers the
+# neglected second-order terms).
+GAMMA = 2.0 ** -7 * 1.05
+SAFETY = 1.5
+L1, L2 = 1.13, 0.8
+BIG = (100, 256, 256, 49)
+
+
+def _split(p, dims):
+    D, H1, H2, O = dims
+    sizes = [H1 * D, H1, H2 * H1, H2, O * H2, O]
+    W1, b1, W2, b2, W3, b3 = np.split(p, np.cumsum(sizes)[:-1])
+    return W1.reshape(H1, D), b1, W2.reshape(H2, H1), b2, W3.reshape(O, H2), b3
+
+
+def _gelu_parts(z):
+    from scipy.special import erf
+    cdf = 0.5 * (1.0 + erf(z / np.sqrt(2.0)))
+    pdf = np.exp(-0.5 * z * z) / np.sqrt(2.0 * np.pi)
+    return z * cdf, cdf + z * pdf
+
+
+def _forward_bounds(p, x):
+    """reference activations and the per-element error bounds of z1, z2, out"""
+    W1, b1, W2, b2, W3, b3 = _split(p, BIG)
+    z1 = x @ W1.T + b1
+    h1, d1 = _gelu_parts(z1)
+    z2 = h1 @ W2.T + b2
+    h2, d2 = _gelu_parts(z2)
+    e1 = GAMMA * (np.abs(x) @ np.abs(W1).T)
+    e2 = (L1 * e1) @ np.abs(W2).T + GAMMA * (np.abs(h1) @ np.abs(W2).T)
+    e3 = (L1 * e2) @ np.abs(W3).T + GAMMA * (np.abs(h2) @ np.abs(W3).T)
+    return dict(z1=z1, h1=h1, d1=d1, z2=z2, h2=h2, d2=d2, e1=e1, e2=e2, e3=e3)
+
+
+def test_configured_surrogate_forward_elementwise():
+    device()
+    case("surrogate 100-256-256-49 forward, element by element")
+    c = P.Context(3, 4, 100, 1.0, 0.3, 7, 0.002)
+    P.mls2mc_surrogate_init(c.h, 256, 4096, 11)
+    assert P.mls2mc_surrogate_n_params(c.h) == 100 * 256 + 256 + 256 * 256 + 256 + 49 * 256 + 49
+    x = inputs.theta_batch(40, 1000, 100)
+    G = torch.empty((1000, 49), dtype=torch.float64, device="cuda:0")
+    P.mls2mc_surrogate_predict(c.h, to_dev(x), G)
+    p = _params(c)
+    ref = oracle.mlp_forward(BIG, p, x)
+    bound = SAFETY * _forward_bounds(p, x)["e3"]
+    err = np.abs(host(G) - ref)
+    print(f"  max err / bound {np.max(err / bound):.3f}, max rel err {rel_err(host(G), ref):.2e}")
+    assert np.all(err <= bound)
+
+
+def test_configured_surrogate_gradient_elementwise():
+    """per-parameter gradients of the 100-256-256-49 network at batch 512
+    (two 128-wide k rounds in the hidden-layer products) against the oracle"""
+    device()
+    case("surrogate 100-256-256-49 gradient, element by element")
+    B = 512
+    c = P.Context(3, 4, 100, 1.0, 0.3, 7, 0.002)
+    P.mls2mc_surrogate_init(c.h, 256, 4096, 12)
+    x = inputs.theta_batch(41, B, 100)
+    t = inputs.theta_batch(42, B, 49)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda:0")
+    g = torch.empty(P.mls2mc_surrogate_n_params(c.h), dtype=torch.float32, device="cuda:0")
+    P.mls2mc_surrogate_loss_grad(c.h, to_dev(x), to_dev(t), loss, g)
+    p = _params(c)
+    L_ref, g_ref = oracle.mlp_loss_grad(BIG, p, x, t)
+    F = _forward_bounds(p, x)
+    W1, b1, W2, b2, W3, b3 = _split(p, BIG)
+    scale = 1.0 / (B * 49)
+    out = F["h2"] @ W3.T + b3
+    g3 = (out - t) * scale
+    dg3 = F["e3"] * scale
+    s2 = g3 @ W3
+    ds2 = dg3 @ np.abs(W3) + GAMMA * (np.abs(g3) @ np.abs(W3))
+    g2 = s2 * F["d2"]
+    dg2 = L1 * ds2 + L2 * np.abs(s2) * F["e2"]
+    s1 = g2 @ W2
+    ds1 = dg2 @ np.abs(W2) + GAMMA * (np.abs(g2) @ np.abs(W2))
+    g1 = s1 * F["d1"]
+    dg1 = L1 * ds1 + L2 * np.abs(s1) * F["e1"]
+    dh1, dh2 = L1 * F["e1"], L1 * F["e2"]
+    bounds = [
+        dg1.T @ np.abs(x) + GAMMA * (np.abs(g1).T @ np.abs(x)),
+        dg1.sum(0) + GAMMA * np.abs(g1).sum(0),
+        dg2.T @ np.abs(F["h1"]) + np.abs(g2).T @ dh1 + GAMMA * (np.abs(g2).T @ np.abs(F["h1"])),
+        dg2.sum(0) + GAMMA * np.abs(g2).sum(0),
+        dg3.T @ np.abs(F["h2"]) + np.abs(g3).T @ dh2 + GAMMA * (np.abs(g3).T @ np.abs(F["h2"])),
+        dg3.sum(0) + GAMMA * np.abs(g3).sum(0),
+    ]
+    bound = SAFETY * np.concatenate([b.ravel() for b in bounds])
+    gg = host(g).astype(np.float64)
+    err = np.abs(gg - g_ref)
+    names = ["W1", "b1", "W2", "b2", "W3", "b3"]
+    cuts = np.cumsum([b.size for b in bounds])[:-1]
+    for nm, e, b in zip(names, np.split(err, cuts), np.split(bound, cuts)):
+        print(f"  {nm}: max err / bound {np.max(e / b):.3f}")
+    print(f"  loss {host(loss)[0]:.6f} vs {L_ref:.6f}")
+    assert np.all(err <= bound)
+    # the loss: sum of squares of the outputs, each off by at most e3
+    dL = scale * np.sum(np.abs(out - t) * F["e3"] + 0.5 * F["e3"] ** 2)
+    assert abs(host(loss)[0] - L_ref) <= SAFETY * dL + 1e-6 * L_ref
