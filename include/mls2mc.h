@@ -265,6 +265,18 @@ int mls2mc_decide(double beta, int l, int l_max, int prev_lu, int scheme, double
 int mls2mc_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u,
                     int32_t* anc_out, void* stream);
 
+/* mls2mc_resample for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernel and the same ancestors for the same (w, u),
+ * with the prefix sums in a static array the library holds on each GPU
+ * (8 MiB, kept until the process ends) instead of context scratch; no
+ * context is needed.  N <= 2^20 (EINVAL beyond, with a message).  It calls
+ * no allocating routine (the array's address is looked up once per device,
+ * on the first call there).  All calls on one GPU share the array: calls
+ * that overlap in time on that GPU (on different streams or threads) race. */
+int mls2mc_resample_noalloc(int64_t N, const double* w, const double* u, int32_t* anc_out,
+                            void* stream);
+
 /* Gather rows by ancestor: dst[i, :] = src[anc[i], :] for i < N, ncols
  * doubles per row; src has n_src rows; an ancestor outside [0, n_src) gives
  * a row of NaN.  src and dst must not overlap.                             */

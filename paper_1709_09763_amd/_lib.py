@@ -111,6 +111,7 @@ def lib():
         L.mls2mc_next_step.argtypes = [_vp, C.c_int64, _vp, C.c_double, C.c_double, C.c_double,
                                        C.c_double, _vp, _vp, _vp, _vp]
         L.mls2mc_resample.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp]
+        L.mls2mc_resample_noalloc.argtypes = [C.c_int64, _vp, _vp, _vp, _vp]
         L.mls2mc_cv_lu.argtypes = [_vp, C.c_int64, _vp, C.c_double, _vp, _vp]
         L.mls2mc_set_linear_model.argtypes = [_vp, _dp, _dp]
         L.mls2mc_gather.argtypes = [_vp, C.c_int64, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp]
@@ -304,6 +305,15 @@ def mls2mc_resample(h, w, u, anc_out):
                                  _ptr(u, torch.float64, (N,), "u"),
                                  _ptr(anc_out, torch.int32, (N,), "anc_out"), _stream()),
            "mls2mc_resample")
+
+
+def mls2mc_resample_noalloc(w, u, anc_out):
+    """resampling with the library's static scratch (no context, no allocation)"""
+    N = w.shape[0]
+    _check(lib().mls2mc_resample_noalloc(N, _ptr(w, torch.float64, (N,), "w"),
+                                         _ptr(u, torch.float64, (N,), "u"),
+                                         _ptr(anc_out, torch.int32, (N,), "anc_out"), _stream()),
+           "mls2mc_resample_noalloc")
 
 
 def mls2mc_gather(h, anc, src, dst):

@@ -217,6 +217,8 @@ int launch_next_step(mls2mc_ctx* ctx, int64_t N, const double* d, double scale, 
                      double tau, double eps, double* out3, double* logw, double* w, hipStream_t s);
 int launch_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u, int32_t* anc,
                     hipStream_t s);
+int launch_resample_into(int64_t N, const double* w, const double* u, uint64_t* C, int32_t* anc,
+                         hipStream_t s);
 int launch_gather(int64_t N, int64_t ncols, const int32_t* anc, int64_t n_src, const double* src,
                   double* dst, hipStream_t s);
 int launch_philox(uint64_t seed, uint32_t stream_id, uint32_t stage, uint32_t sub, int64_t n,

@@ -273,13 +273,21 @@ __global__ __launch_bounds__(kNS) void resample_kernel(int64_t N, const double* 
     }
 }
 
+// C: N uint64 of scratch for the prefix sums (every entry is written before
+// it is read, so it needs no clearing)
+int launch_resample_into(int64_t N, const double* w, const double* u, uint64_t* C, int32_t* anc,
+                         hipStream_t s)
+{
+    resample_kernel<<<1, kNS, 0, s>>>(N, w, u, C, anc);
+    MLS_CHECK_HIP(hipGetLastError());
+    return MLS2MC_OK;
+}
+
 int launch_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u, int32_t* anc,
                     hipStream_t s)
 {
     MLS_TRY(ctx->ws_misc.ensure(sizeof(uint64_t) * (size_t)N));
-    resample_kernel<<<1, kNS, 0, s>>>(N, w, u, ctx->ws_misc.as<uint64_t>(), anc);
-    MLS_CHECK_HIP(hipGetLastError());
-    return MLS2MC_OK;
+    return launch_resample_into(N, w, u, ctx->ws_misc.as<uint64_t>(), anc, s);
 }
 
 // --------------------------------------------------------------- gather --
