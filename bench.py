@@ -1,19 +1,25 @@
 """Benchmark of the MLS^2MC hot path on one MI355X.
 
-Workload (synthetic, seeded): MLS^2MC on levels h = 1/8 .. 1/64 (l = 3..6),
-K = 50 separable-exponential KL terms (sigma^2 = 1, correlation length 0.3),
-25 observations on a 5x5 interior grid, sigma_n = 0.005, J = 1000 particles,
-5 pCN steps per stage with s = 0.5, ESS target 0.5 J.
+Default workload (synthetic, seeded): the largest single-GPU configuration,
+MLS^2MC on levels h = 1/16 .. 1/512 (l = 4..9; 261,121 unknowns per
+particle on the finest level), K = 200 separable-exponential KL terms
+(sigma^2 = 1, correlation length 0.1), 100 observations on a 10x10 interior
+grid, sigma_n = 0.001, J = 8192 particles, 5 pCN steps per stage with
+s = 0.5, ESS target 0.5 J.
 
-A step is one SMC stage at the finest level (l = 6) over the whole particle
-batch: adaptive next temperature (log-sum-exp weights), integer-CDF
-resampling, gather, and 5 pCN steps, each proposal going through the KL
-field GEMM, the multigrid-PCG solve, the observations and the potential.
-`value` = forward solves/s at l = 6 inside these stages (5 J solves per
-step).  Extra fields: per-level solves/s of plain forward batches,
-time-to-posterior of the whole sampler (plain FP64 and mixed precision),
-the roofline of the solver kernel measured live with HIP events recorded by
-the library on its launch stream, and the CPU oracle on a bounded sample.
+A step is one SMC sub-step on the finest level over all J particles:
+adaptive next temperature (log-sum-exp weights), integer-CDF resampling,
+gather, and one pCN move whose J proposals go through the KL field GEMM,
+the multigrid-PCG solve, the observations, the potential and the
+acceptance (a configured stage makes five such moves).  The timed steps run
+the plain FP64 form; `value` = forward solves/s at h = 1/512 inside them.
+Extra fields: the same step in the mixed-precision form, per-level
+forward solves/s of both forms with the mixed form's error against the FP64
+path, time-to-posterior of plain FP64 against mixed precision + surrogate
+(with the paper's RelErr and RelMisfit of each posterior mean), the roofline
+of the h = 1/512 solver kernel measured live with HIP events recorded by the
+library on its launch stream, and the CPU oracle on a bounded sample with
+an extrapolated CPU time-to-posterior.
 """
 import argparse
 import json
@@ -39,8 +45,11 @@ def b_iter(nu, fp32=False):
 
 B_ITER_FP64 = b_iter(1)
 B_ITER_MIXED = b_iter(1, True)
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "solve_h64_K50_J1000_pmc.md")
-TUNED_DEFAULT = os.path.join(ROOT, "paper_1709_09763_amd", "tuned", "mi355x_h8-64_K50_J1000.json")
+PMC_H64 = os.path.join(ROOT, "profiles", "solve_h64_K50_J1000_pmc.md")
+PMC_H512 = os.path.join(ROOT, "profiles", "solve_h512_K200_J8192_pmc.md")
+TUNED_DIR = os.path.join(ROOT, "paper_1709_09763_amd", "tuned")
+TUNED_H64 = os.path.join(TUNED_DIR, "mi355x_h8-64_K50_J1000.json")
+TUNED_H512 = os.path.join(TUNED_DIR, "mi355x_h16-512_K200_J8192.json")
 
 
 def solver_sha():
@@ -52,21 +61,59 @@ def solver_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(shape):
-    """HBM bytes per solver launch from the committed rocprofv3 counter
+def measured_traffic(summary, shape, form="fp64"):
+    """HBM bytes per solver launch from a committed rocprofv3 counter
     summary, or None once the solver source or the launch shape
-    (grid, block, nu, lds) differs from the one measured"""
+    (grid, block, nu, lds) differs from the one measured.  The summary
+    holds lines `solver_source_sha256_16: ...`, `launch_shape[_<form>]:
+    g,b,nu,lds` and `traffic_bytes_per_launch[_<form>]: B`."""
     try:
-        txt = open(PMC_SUMMARY).read()
+        txt = open(summary).read()
     except OSError:
         return None
-    vals = dict(ln.split(":", 1) for ln in txt.splitlines()
-                if ln.startswith(("traffic_bytes", "solver_source", "launch_shape")))
-    if vals.get("solver_source_sha256_16", "").strip() != solver_sha():
+    vals = {}
+    for ln in txt.splitlines():
+        if ":" in ln and ln.split(":", 1)[0].strip().replace("_", "").isalnum():
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("solver_source_sha256_16", "") != solver_sha():
         return None
-    if vals.get("launch_shape", "").strip() != ",".join(str(v) for v in shape):
+    suf = "" if form == "fp64" and "launch_shape" in vals else f"_{form}"
+    if vals.get("launch_shape" + suf, "") != ",".join(str(v) for v in shape):
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    try:
+        return float(vals["traffic_bytes_per_launch" + suf])
+    except (KeyError, ValueError):
+        return None
+
+
+def load_tuned(path, ctxs):
+    """apply committed launch shapes {form: {level: shape}} when they were
+    tuned on this device for this solver source; returns the path or None"""
+    import torch
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("device") != torch.cuda.get_device_name(0) or rec.get("solver_source_sha256_16") != solver_sha():
+        return None
+    for form, c in ctxs.items():
+        for lv, sh in rec.get(form, {}).items():
+            c.set_launch(int(lv), sh["grid"], sh["block"], sh.get("nu", 0), sh.get("lds", 0))
+    return path
+
+
+def cpu_model():
+    """the host CPU's model name (what lscpu reports, read from /proc/cpuinfo)"""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
 
 WL = dict(name="mls2mc h=1/8..1/64 K=50 Nobs=25 J=1000", l_min=3, l_max=6, K=50, m=5,
           sigma_n=0.005, J=1000, corr=0.3, n_mcmc=5, s_pcn=0.5, tau_star=1.0)
@@ -118,10 +165,48 @@ def cpu_baseline(l, K, m, corr, budget_s=15.0):
         oracle.forward(l, K, 1.0, corr, m, rng.standard_normal((chunk, K)), nthreads=cores)
         n += chunk
     dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="forward solves/s", cores=cores, kind="oracle",
+    return dict(value=n / dt, unit="forward solves/s", cores=cores, kind="oracle", cpu=cpu_model(),
                 sample=f"{n} forward solves at h=1/{1 << l}, K={K} from the prior, in chunks of "
                        f"{chunk} (KL field, generic P1 assembly, banded Cholesky, observation), "
                        f"OpenMP over particles, {dt:.1f}s")
+
+
+def cpu_levels(levels, K, m, corr, budget_s=2.0, single_core_level=None):
+    """The oracle (KL field, generic P1 assembly, banded Cholesky, observation)
+    on the host cores, one solve per thread: per level, chunks of `cores`
+    prior draws until `budget_s` is used (at least one chunk); optionally one
+    solve on one thread at `single_core_level`.  Returns {level: solves/s on
+    all cores}, the single-core solves/s, cores and the CPU model."""
+    import numpy as np
+
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    rng = np.random.default_rng(7)
+    rates, samples = {}, {}
+    for lv in levels:
+        n, t0 = 0, time.perf_counter()
+        while n == 0 or time.perf_counter() - t0 < budget_s:
+            oracle.forward(lv, K, 1.0, corr, m, rng.standard_normal((cores, K)), nthreads=cores)
+            n += cores
+        dt = time.perf_counter() - t0
+        rates[lv] = n / dt
+        samples[lv] = f"{n} solves in {dt:.1f}s"
+        log(f"cpu oracle h=1/{1 << lv}: {rates[lv]:.3g} solves/s ({samples[lv]})")
+    single = None
+    if single_core_level is not None:
+        t0 = time.perf_counter()
+        oracle.forward(single_core_level, K, 1.0, corr, m, rng.standard_normal((1, K)), nthreads=1)
+        single = 1.0 / (time.perf_counter() - t0)
+        log(f"cpu oracle single core h=1/{1 << single_core_level}: {single:.3g} solves/s")
+    return rates, samples, single, cores, cpu_model()
+
+
+def rel_misfit(G, y):
+    """the paper's relative misfit |Gamma^{-1/2}(y - G)|^2 / |Gamma^{-1/2} y|^2
+    (Sec. 5.1; Gamma = sigma_n^2 I cancels)"""
+    import numpy as np
+    G, y = np.asarray(G, dtype=np.float64), np.asarray(y, dtype=np.float64)
+    return float(((y - G) ** 2).sum() / (y ** 2).sum())
 
 
 def rel_err_paper(mean, truth, lam):
@@ -137,6 +222,223 @@ def tune_levels(ctx, levels, J):
         ms, (g, b, nu, lds) = ctx.autotune(lv, min(J, 512 if lv >= 7 else J))
         out[f"h=1/{1 << lv}"] = dict(grid=g, block=b, nu=nu, lds=lds, ms=round(ms, 4))
     return out
+
+
+W4 = dict(name="mls2mc h=1/16..1/512 K=200 corr=0.1 Nobs=100 sigma_n=0.001 J=8192", l_min=4, l_max=9, K=200,
+          m=10, sigma_n=0.001, J=8192, corr=0.1, n_mcmc=5, s_pcn=0.5, tau_star=1.0)
+
+
+def run_summary(r, mean, th_true, lam, misfit):
+    """the fields every time-to-posterior record carries"""
+    return dict(seconds=round(r["seconds"], 3), stages=r["n_stages"],
+                solves={str(i): v for i, v in enumerate(r["solves"]) if v},
+                accept_rate=round(r["accepted"] / max(1, r["proposed"]), 5), log_Z=r["log_Z"],
+                rel_err_vs_truth=round(rel_err_paper(mean, th_true, lam), 4), rel_misfit=round(misfit, 6),
+                mean_pcg_iters=round(r["iters_total"] / max(1, sum(r["solves"])), 2),
+                not_converged=r["not_converged"])
+
+
+def leg_largest_stage(args):
+    """The default benchmark (see the module docstring)."""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    W = W4
+    K, m, J, L, sn = W["K"], W["m"], W["J"], W["l_max"], W["sigma_n"]
+    lv_all = range(W["l_min"], L + 1)
+    ctx = P.Context(W["l_min"], L, K, 1.0, W["corr"], m, sn)
+    ctxm = P.Context(W["l_min"], L, K, 1.0, W["corr"], m, sn, precision=P.MIXED)
+    nobs = ctx.nobs
+    lam = ctx.kl_eigenvalues()
+    rng = np.random.default_rng(99)
+    th_true = rng.standard_normal(K)
+    y = ctx.forward(L, torch.tensor(th_true[None, :], device=dev))[0]
+    y = (y + sn * torch.tensor(rng.standard_normal(nobs), device=dev)).contiguous()
+    extras = {}
+    src = None if args.retune else load_tuned(args.tuned or TUNED_H512, {"fp64": ctx, "mixed": ctxm})
+    if src:
+        extras["solver_launch_source"] = os.path.relpath(src, ROOT)
+        log(f"solver launch shapes from {src}")
+    elif not args.no_autotune:
+        tuned = {}
+        for name, c in (("fp64", ctx), ("mixed", ctxm)):
+            tuned[name] = {}
+            for lv in lv_all:
+                ms, (g, b, nu, lds) = c.autotune(lv, 512)
+                tuned[name][str(lv)] = dict(grid=g, block=b, nu=nu, lds=lds)
+                log(f"autotuned {name} h=1/{1 << lv}: {tuned[name][str(lv)]} {ms:.3f} ms")
+        if args.save_tuned:
+            json.dump({"device": torch.cuda.get_device_name(0), "workload": W["name"],
+                       "solver_source_sha256_16": solver_sha(), **tuned}, open(args.save_tuned, "w"), indent=1)
+        extras["solver_launch_source"] = "autotuned in this run on 512 prior draws per level"
+    else:
+        extras["solver_launch_source"] = "library defaults"
+    extras["solver_launch"] = {name: {f"h=1/{1 << lv}": list(c.get_launch(lv)) for lv in lv_all}
+                               for name, c in (("fp64", ctx), ("mixed", ctxm))}
+
+    thp = None
+    if not args.no_extras:
+        # ---- time-to-posterior, plain FP64 against mixed precision + surrogate,
+        # at the configured fixed pCN step (one untimed short run of each first)
+        sur = dict(surrogate=True, sur_collect_max_level=6, sur_da_min_level=7, sur_pairs=20480, sur_epochs=15,
+                   sur_hidden=256)
+        ctx.run(y, 256, seed=1)
+        ctxm.run(y, 256, seed=1, **sur)
+        torch.cuda.synchronize()
+        runs = {}
+        for name, c, kw in (("plain_fp64", ctx, {}), ("mixed_surrogate", ctxm, sur)):
+            r = c.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=31,
+                      **kw)
+            th = r["theta"]
+            mean = th.mean(0, keepdim=True).contiguous()
+            Gm = ctx.forward(L, mean)[0]
+            rec = run_summary(r, mean[0].cpu().numpy(), th_true, lam, rel_misfit(Gm.cpu().numpy(), y.cpu().numpy()))
+            if kw:
+                rec.update(surrogate_train_s=round(r["sur_train_seconds"], 3),
+                           stage1_pass_frac=round(r["stage1_passed"] / max(1, r["da_proposed"]), 4),
+                           surrogate_err_over_sigma_n=dict(mean=round(r["sur_err_mean"], 4),
+                                                           max=round(r["sur_err_max"], 4),
+                                                           solves_judged=r["sur_err_count"]))
+            runs[name] = (r, rec, mean[0].cpu().numpy())
+            log(f"time-to-posterior {name}: {rec}")
+            if name == "plain_fp64":
+                thp = th.contiguous()
+        extras["time_to_posterior_s"] = {k: v[1]["seconds"] for k, v in runs.items()}
+        extras["speedup_mixed_surrogate_vs_plain_fp64"] = round(
+            runs["plain_fp64"][1]["seconds"] / runs["mixed_surrogate"][1]["seconds"], 3)
+        extras["run_plain_fp64"] = runs["plain_fp64"][1]
+        extras["run_mixed_surrogate"] = runs["mixed_surrogate"][1]
+        extras["rel_err_between_forms"] = round(rel_err_paper(runs["mixed_surrogate"][2], runs["plain_fp64"][2], lam), 4)
+        solves_fp64 = runs["plain_fp64"][0]["solves"]
+
+        # ---- per-level forward solves/s of both forms on J prior draws, and the
+        # mixed form's error against the FP64 path (itself rel 1e-10 of the oracle)
+        per = {"fp64": {}, "mixed": {}, "mixed_rel_err_vs_fp64": {}}
+        thr = torch.tensor(rng.standard_normal((J, K)), device=dev)
+        for lv in lv_all:
+            Gs = {}
+            for name, c in (("fp64", ctx), ("mixed", ctxm)):
+                c.forward(lv, thr[:512].contiguous())
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                Gs[name] = c.forward(lv, thr)
+                torch.cuda.synchronize()
+                per[name][f"h=1/{1 << lv}"] = round(J / (time.perf_counter() - t0), 1)
+            d = (Gs["mixed"] - Gs["fp64"]).abs().amax(1) / Gs["fp64"].abs().amax(1)
+            per["mixed_rel_err_vs_fp64"][f"h=1/{1 << lv}"] = dict(max=float(d.max()), median=float(d.median()))
+            log(f"per-level h=1/{1 << lv}: fp64 {per['fp64'][f'h=1/{1 << lv}']}, mixed {per['mixed'][f'h=1/{1 << lv}']}"
+                f" solves/s, mixed rel err max {float(d.max()):.2e}")
+        extras["forward_solves_per_s_by_level"] = per
+
+    # ---- state for the timed steps: the FP64 run's posterior particles at h = 1/512
+    theta = thp if thp is not None else torch.tensor(rng.standard_normal((J, K)), device=dev)
+
+    def make_state(c):
+        th = theta.clone()
+        G = c.forward(L, th)
+        return dict(theta=th, G=G, phi=c.loglik(G, y), theta2=torch.empty_like(th), G2=torch.empty_like(G),
+                    phi2=torch.empty_like(G[:, 0]).contiguous())
+
+    beta0 = 0.5
+
+    def step(c, S, k):
+        out3, logw, w = c.next_step(S["phi"], 1.0, beta0, J / (1 + W["tau_star"] ** 2))
+        u = c.philox(99, 3, k, 0, J, normal=False)
+        anc = c.resample(w, u)
+        P.mls2mc_gather(c.h, anc, S["theta"], S["theta2"])
+        P.mls2mc_gather(c.h, anc, S["G"], S["G2"])
+        P.mls2mc_gather(c.h, anc, S["phi"].view(-1, 1), S["phi2"].view(-1, 1))
+        for a, b in (("theta", "theta2"), ("G", "G2"), ("phi", "phi2")):
+            S[a], S[b] = S[b], S[a]
+        xi = c.philox(99, 4, k, 0, J * K, normal=True).view(J, K)
+        uu = c.philox(99, 5, k, 0, J, normal=False)
+        c.pcn_step(L, L, 0.75, 1.0, W["s_pcn"], S["theta"], S["G"], None, S["phi"], None, y, xi, uu)
+
+    def timed(c, steps, warmup):
+        S = make_state(c)
+        for k in range(warmup):
+            step(c, S, 10_000 + k)
+        torch.cuda.synchronize()
+        c.profile(True)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(c, S, k)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c.profile(False)
+        return dt, c.profile_read(P.PROF_SOLVE, L), c.profile_read(P.PROF_GEMM, L)
+
+    # mixed form first (not the driver's step count), then the timed FP64 steps
+    msteps = max(2, min(args.steps, 5))
+    dtm, psm, pgm = timed(ctxm, msteps, 1)
+    extras["mixed_stage"] = dict(steps=msteps, solves_per_s=round(msteps * J / dtm, 1),
+                                 ms_per_step=round(dtm / msteps * 1e3, 3),
+                                 solver_avg_ms=round(psm["ms"] / max(1, psm["launches"]), 3),
+                                 mean_pcg_iters=round(psm["iters"] / max(1, psm["items"]), 3),
+                                 solver_algorithmic_GBs=round(
+                                     solve_bytes(L, nobs, psm["items"], psm["iters"],
+                                                 b_iter(ctxm.get_launch(L)[2], True)) / (psm["ms"] * 1e-3) / 1e9, 1))
+    gflop = 2.0 * pgm["items"] * K * (2 << (2 * L))
+    extras["mixed_stage"]["kl_gemm_bf16_tflops"] = round(gflop / max(pgm["ms"] * 1e-3, 1e-12) / 1e12, 2)
+    log(f"mixed stage {extras['mixed_stage']}")
+    dt, ps, pg = timed(ctx, args.steps, args.warmup)
+    value = args.steps * J / dt
+    nu_l = ctx.get_launch(L)[2]
+    alg = solve_bytes(L, nobs, ps["items"], ps["iters"], b_iter(nu_l))
+    avg_ms = ps["ms"] / max(1, ps["launches"])
+    achieved = alg / ps["launches"] / (avg_ms * 1e-3) / 1e9 if ps["launches"] else 0.0
+    traffic = measured_traffic(PMC_H512, ctx.get_launch(L), "fp64")
+    gflop = 2.0 * pg["items"] * K * (2 << (2 * L))
+    extras["solver_kernel"] = dict(launches=ps["launches"], particles_per_launch=ps["items"] / max(1, ps["launches"]),
+                                   avg_ms=round(avg_ms, 4), mean_pcg_iters=round(ps["iters"] / max(1, ps["items"]), 3),
+                                   share_of_step_time=round(ps["ms"] * 1e-3 / dt, 3))
+    extras["kl_gemm"] = dict(launches=pg["launches"], avg_ms=round(pg["ms"] / max(1, pg["launches"]), 4),
+                             tflops=round(gflop / max(pg["ms"] * 1e-3, 1e-12) / 1e12, 3),
+                             frac_of_fp64_peak=round(gflop / max(pg["ms"] * 1e-3, 1e-12) / 1e12 / FP64_PEAK_TFLOPS, 4))
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+            "algorithmic_bytes_per_launch": round(alg / max(1, ps["launches"]), 0),
+            "kernel": "solve_kernel (h=1/512, FP64)", "launch_shape": list(ctx.get_launch(L))}
+    if traffic:
+        roof["measured_rate_GBs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+        roof["traffic_over_algorithmic"] = round(traffic / (alg / ps["launches"]), 3)
+    cpu = None
+    if not args.no_cpu_baseline:
+        rates, samples, single, cores, model = cpu_levels(
+            [L] if args.no_extras else list(lv_all), K, m, W["corr"], budget_s=1.5,
+            single_core_level=None if args.quick_cpu else L)
+        cpu = dict(value=rates[L], unit="forward solves/s (h=1/512)", cores=cores, kind="oracle",
+                   sample=f"{samples[L]} at h=1/512 (K=200, corr 0.1, prior draws; KL field, generic P1 assembly, "
+                          f"banded Cholesky, observation), one solve per thread on all {cores} threads",
+                   cpu_model=model, single_core_solves_per_s=single,
+                   by_level={f"h=1/{1 << lv}": round(v, 3) for lv, v in rates.items()})
+        if not args.no_extras:
+            t_cpu = sum(n / rates[lv] for lv, n in enumerate(solves_fp64) if n and lv in rates)
+            cpu["time_to_posterior_s_extrapolated"] = round(t_cpu, 1)
+            cpu["extrapolation"] = ("sum over levels of the plain FP64 GPU run's solve count times the oracle's "
+                                    "measured seconds per solve on all cores")
+        log(f"cpu baseline {cpu}")
+    out = {
+        "metric": "forward solves/s per level; MLS²MC time-to-posterior, plain vs surrogate+FP32",
+        "value": round(value, 2),
+        "unit": "forward solves/s (h=1/512, inside SMC sub-steps)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["name"], "levels": "h=1/16..1/512", "K": K, "corr_len": W["corr"], "n_obs": nobs,
+                   "J": J, "sigma_n": sn, "pcn_step": W["s_pcn"],
+                   "step": "one SMC sub-step at h=1/512 over all J particles: next_step, resample, gather, one pCN "
+                           "move (KL GEMM + MG-PCG solve + observation + potential + accept); a configured stage "
+                           "makes 5 such moves"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        **extras,
+    }
+    print(json.dumps(out))
 
 
 def leg_fast(args):
@@ -214,6 +516,125 @@ def leg_fast(args):
         "data": "synthetic", "speedup_vs_plain_fp64": round(out["plain_fp64"]["seconds"] / out["mixed_surrogate"]["seconds"], 3),
         "config": {"workload": "mls2mc h=1/8..1/256 K=100 Nobs=49 sigma_n=0.002 J=4096",
                    "pcn_step": "adapted" if args.s_adapt else "fixed 0.5", "seeds": seeds}, **out}))
+
+
+def interp_time_at(err_target, errs, times):
+    """time at which a form reaches err_target, by linear interpolation of
+    log time against log error along its (N-sweep) curve; extrapolated from
+    the two nearest points when the target lies outside the curve"""
+    import numpy as np
+    e, t = np.log(np.asarray(errs, float)), np.log(np.asarray(times, float))
+    order = np.argsort(e)
+    e, t = e[order], t[order]
+    x = np.log(err_target)
+    inside = bool(e[0] <= x <= e[-1])
+    if inside:
+        return float(np.exp(np.interp(x, e, t))), False
+    i = 0 if x < e[0] else len(e) - 2
+    slope = (t[i + 1] - t[i]) / (e[i + 1] - e[i]) if e[i + 1] != e[i] else 0.0
+    return float(np.exp(t[i] + slope * (x - e[i]))), True
+
+
+def leg_equal_error(args):
+    """Equal posterior-mean error on h=1/8..1/256, K=100 (corr 0.3), 49 obs,
+    sigma_n=0.002: a reference posterior mean from plain FP64 runs with 4 x
+    4096 particles (--ref-seeds of them, averaged); then, for plain FP64 and
+    for mixed precision + surrogate, --seeds runs at every N of --sizes.
+    Reports per form and N the mean and standard error of the paper's RelErr
+    (Sec. 5.1, Lambda^{1/2}-weighted l1) against the reference mean and
+    against the truth, RelMisfit, the log-evidence spread and the median time
+    to posterior; and the fast form's time at the plain form's error at the
+    largest N (log-log interpolation along its N sweep)."""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    K, m, sn, lmin, lmax, corr = 100, 7, 0.002, 3, 8, 0.3
+    sizes = [int(v) for v in args.sizes.split(",")]
+    rng = np.random.default_rng(77)
+    th_true = rng.standard_normal(K)
+    ctx = P.Context(lmin, lmax, K, 1.0, corr, m, sn)
+    lam = ctx.kl_eigenvalues()
+    y = ctx.forward(lmax, torch.tensor(th_true[None, :], device=dev))[0]
+    y = (y + sn * torch.tensor(rng.standard_normal(m * m), device=dev)).contiguous()
+    y_h = y.cpu().numpy()
+    ctxm = P.Context(lmin, lmax, K, 1.0, corr, m, sn, precision=P.MIXED)
+    tune_levels(ctx, range(lmin, lmax + 1), max(sizes))
+    tune_levels(ctxm, range(lmin, lmax + 1), max(sizes))
+    step = dict(s_adapt=args.s_adapt, s_pcn=0.5)
+    sur = dict(surrogate=True, sur_collect_max_level=6, sur_da_min_level=7, sur_pairs=20480, sur_epochs=15,
+               sur_hidden=256)
+    ctx.run(y, 256, seed=1, **step)
+    ctxm.run(y, 256, seed=1, **step, **sur)
+
+    def misfit(mean):
+        G = ctx.forward(lmax, torch.tensor(mean[None, :], device=dev))[0]
+        return rel_misfit(G.cpu().numpy(), y_h)
+
+    # reference posterior mean
+    Jref = 4 * max(sizes)
+    ref_means, ref_t = [], []
+    for i in range(args.ref_seeds):
+        r = ctx.run(y, Jref, seed=1000 + i, **step)
+        ref_means.append(r["theta"].mean(0).cpu().numpy())
+        ref_t.append(r["seconds"])
+        log(f"reference run {i}: J={Jref} {r['seconds']:.2f}s stages {r['n_stages']}")
+    ref = np.mean(ref_means, axis=0)
+    ref_spread = [rel_err_paper(mu, ref, lam) for mu in ref_means]
+    out = {"reference": dict(J=Jref, runs=args.ref_seeds, seconds=[round(t, 3) for t in ref_t],
+                             rel_err_of_each_run_vs_their_mean=[round(v, 4) for v in ref_spread],
+                             rel_err_vs_truth=round(rel_err_paper(ref, th_true, lam), 4),
+                             rel_misfit=round(misfit(ref), 6))}
+    seeds = [21 + i for i in range(args.seeds)]
+    forms = (("plain_fp64", ctx, {}), ("mixed_surrogate", ctxm, sur))
+    for name, c, kw in forms:
+        out[name] = {}
+        for N in sizes:
+            rows = []
+            for sd in seeds:
+                r = c.run(y, N, seed=sd, **step, **kw)
+                mu = r["theta"].mean(0).cpu().numpy()
+                row = dict(seconds=r["seconds"], rel_err_ref=rel_err_paper(mu, ref, lam),
+                           rel_err_truth=rel_err_paper(mu, th_true, lam), rel_misfit=misfit(mu), log_Z=r["log_Z"],
+                           solves=sum(r["solves"]))
+                if kw:
+                    row.update(stage1_pass=r["stage1_passed"] / max(1, r["da_proposed"]),
+                               sur_err_mean=r["sur_err_mean"], sur_err_max=r["sur_err_max"],
+                               train_s=r["sur_train_seconds"])
+                rows.append(row)
+            R = len(rows)
+            agg = dict(runs=R, seconds_median=round(float(np.median([q["seconds"] for q in rows])), 4),
+                       seconds_all=[round(q["seconds"], 3) for q in rows])
+            for k in ("rel_err_ref", "rel_err_truth", "rel_misfit"):
+                v = np.array([q[k] for q in rows])
+                agg[k] = dict(mean=round(float(v.mean()), 5),
+                              se=round(float(v.std(ddof=1) / np.sqrt(R)) if R > 1 else 0.0, 5))
+            lz = np.array([q["log_Z"] for q in rows])
+            agg["log_Z"] = dict(mean=round(float(lz.mean()), 3), sd=round(float(lz.std(ddof=1)) if R > 1 else 0.0, 3))
+            agg["solves_mean"] = float(np.mean([q["solves"] for q in rows]))
+            if kw:
+                for k in ("stage1_pass", "sur_err_mean", "sur_err_max", "train_s"):
+                    agg[k] = round(float(np.mean([q[k] for q in rows])), 4)
+            out[name][str(N)] = agg
+            log(f"{name} N={N}: t {agg['seconds_median']}s RelErr(ref) {agg['rel_err_ref']} "
+                f"RelErr(truth) {agg['rel_err_truth']}")
+    Nmax = str(max(sizes))
+    e_plain = out["plain_fp64"][Nmax]["rel_err_ref"]["mean"]
+    t_plain = out["plain_fp64"][Nmax]["seconds_median"]
+    errs = [out["mixed_surrogate"][str(N)]["rel_err_ref"]["mean"] for N in sizes]
+    times = [out["mixed_surrogate"][str(N)]["seconds_median"] for N in sizes]
+    t_fast, extrap = interp_time_at(e_plain, errs, times)
+    out["equal_error"] = dict(plain_error=e_plain, plain_seconds=t_plain, fast_seconds_at_plain_error=round(t_fast, 4),
+                              extrapolated=extrap, speedup=round(t_plain / t_fast, 3))
+    log(f"equal error {out['equal_error']}")
+    print(json.dumps({
+        "metric": "MLS²MC time-to-posterior at equal posterior-mean error, plain FP64 vs surrogate+FP32",
+        "value": out["equal_error"]["speedup"], "unit": "time ratio plain / fast at the plain form's RelErr",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64 vs bf16/f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "mls2mc h=1/8..1/256 K=100 Nobs=49 sigma_n=0.002", "sizes": sizes, "seeds": seeds,
+                   "pcn_step": "adapted" if args.s_adapt else "fixed 0.5"}, **out}))
 
 
 def leg_compare(args):
@@ -522,10 +943,14 @@ def main():
                     help="autotune even when the committed shapes match this device and solver")
     ap.add_argument("--tuned", default=None, help="JSON of solver launch shapes to use instead of tuning")
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
-    ap.add_argument("--workload", default="cfg1",
-                    choices=["cfg1", "fast", "batched", "largest", "largest-run", "compare", "levels", "matern"],
-                    help="cfg1: the default stage benchmark; others: the extra workloads")
-    ap.add_argument("--seeds", type=int, default=1, help="fast: independent runs per form")
+    ap.add_argument("--workload", default="largest-stage",
+                    choices=["largest-stage", "stages-h64", "fast", "batched", "largest", "largest-run", "compare",
+                             "levels", "matern", "equal-error"],
+                    help="largest-stage: the default benchmark; others: the extra workloads")
+    ap.add_argument("--quick-cpu", action="store_true", help="skip the single-core oracle solve at h=1/512")
+    ap.add_argument("--seeds", type=int, default=1, help="fast / equal-error: independent runs per form (and N)")
+    ap.add_argument("--ref-seeds", type=int, default=4, help="equal-error: runs averaged for the reference mean")
+    ap.add_argument("--sizes", default="1024,2048,4096", help="equal-error: particle counts swept")
     ap.add_argument("--fp64-surrogate", action="store_true",
                     help="fast: also run the surrogate form with the FP64 solver")
     ap.add_argument("--s-adapt", action="store_true",
@@ -545,10 +970,10 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.workload != "cfg1":
-        {"fast": leg_fast, "batched": leg_batched, "largest": leg_largest,
+    if args.workload != "stages-h64":
+        {"largest-stage": leg_largest_stage, "fast": leg_fast, "batched": leg_batched, "largest": leg_largest,
          "largest-run": leg_largest_run, "compare": leg_compare, "levels": leg_levels,
-         "matern": leg_matern}[args.workload](args)
+         "matern": leg_matern, "equal-error": leg_equal_error}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     W = WL
@@ -563,10 +988,10 @@ def main():
     extras = {}
     shapes, shapes_m = {}, {}
     tuned_file = args.tuned
-    if tuned_file is None and not args.retune and not args.no_autotune and os.path.exists(TUNED_DEFAULT):
-        rec = json.load(open(TUNED_DEFAULT))
+    if tuned_file is None and not args.retune and not args.no_autotune and os.path.exists(TUNED_H64):
+        rec = json.load(open(TUNED_H64))
         if rec.get("device") == torch.cuda.get_device_name(0) and rec.get("solver_source_sha256_16") == solver_sha():
-            tuned_file = TUNED_DEFAULT  # the committed shapes were tuned on this device for this solver
+            tuned_file = TUNED_H64  # the committed shapes were tuned on this device for this solver
     ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
     if tuned_file:
         rec = json.load(open(tuned_file))
@@ -676,7 +1101,7 @@ def main():
     extras["kl_gemm"] = dict(launches=pg["launches"], avg_ms=round(pg["ms"] / max(1, pg["launches"]), 4),
                              tflops=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12, 3),
                              frac_of_fp64_peak=round(gemm_flops / max(pg["ms"] * 1e-3, 1e-12) / 1e12 / FP64_PEAK_TFLOPS, 4))
-    traffic = measured_traffic(ctx.get_launch(l))
+    traffic = measured_traffic(PMC_H64, ctx.get_launch(l))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(l, K, m, W["corr"])

@@ -72,6 +72,7 @@ def test_run_batch_reproduces_single_runs():
         assert torch.equal(og["theta"], oe["theta"])
 
 
+@pytest.mark.timeout(900)
 def test_run_batch_matches_oracle_at_configured_sizes():
     """Three instances of the batched workload's problem (K = 100 KL terms,
     49 observations, sigma_n = 0.002, h = 1/8 up to 1/64 or 1/128, J of 256

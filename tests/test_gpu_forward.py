@@ -172,11 +172,15 @@ def test_mixed_bf16_field_error_bound():
 def test_mixed_forward_error_against_oracle_per_level(l, N):
     """The whole mixed form (BF16 KL GEMM, FP32 solver with FP64 residual
     replacement) against the FP64 oracle on prior draws, K = 100, 49
-    observations.  Its error is the BF16 field's: every element's log-field
-    is off by at most eps_q = 2^-7 sum_k |theta_qk B_ke| (1.05 for the FP32
-    sum), so kappa by a factor within exp(+-eps_q); the observations, weighted
-    averages of p, stay within 2 eps_q of the FP64 values relative to their
-    size.  The measured error is printed per level."""
+    observations.  Its error is the BF16 field's.  Rounding theta and B to
+    BF16 (relative error up to u = 2^-8 each, independent from term to term)
+    perturbs an element's log-field with standard deviation
+    sigma_e = sqrt(2 u^2 / 3 * sum_k (theta_k B_ke)^2), so kappa by a factor
+    exp(+-sigma_e); the observations, weighted averages of p, move by less
+    than the largest such factor: |dG| / |G| <= 6 max_e sigma_e (8 sigma_e is
+    the Gaussian tail of the largest of 10^5 elements).  Besides that
+    derived bound, the measured errors (3.3e-3 at most, 1.6e-3 from h = 1/128
+    on, on the box this was written on) must stay below 5e-3."""
     device()
     K, m = 100, 7
     case(f"mixed forward vs oracle l={l} N={N}")
@@ -185,13 +189,14 @@ def test_mixed_forward_error_against_oracle_per_level(l, N):
     G, st, it = ctx.forward(l, to_dev(th), with_stats=True)
     Gr = oracle.forward(l, K, 1.0, 0.3, m, th)
     B = oracle.kl_basis(l, K, 1.0, 0.3)
-    eps = 2.0 ** -7 * 1.05 * (np.abs(th) @ np.abs(B)).max(1)
+    sig = np.sqrt(2.0 * (2.0 ** -8) ** 2 / 3.0 * ((th * th) @ (B * B)).max(1))
     Gh = host(G)
     assert (host(st) == 0).all()
     err = np.abs(Gh - Gr).max(1) / np.abs(Gr).max(1)
     print(f"  h=1/{1 << l}: max rel G error {err.max():.2e} (median {np.median(err):.2e}), "
-          f"max bound 2 eps {2 * eps.max():.2e}, mean iters {host(it).mean():.1f}")
-    assert np.all(err <= 2 * eps)
+          f"derived bound 6 sigma {6 * sig.max():.2e}, mean iters {host(it).mean():.1f}")
+    assert np.all(err <= 6 * sig)
+    assert err.max() < 5e-3
 
 
 LDS_MAX = 160 * 1024 - 1024  # gfx950: 160 KiB of LDS per workgroup, 1 KiB kept for static arrays

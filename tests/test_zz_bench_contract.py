@@ -37,7 +37,8 @@ def test_default_line_keeps_the_contract(monkeypatch, capsys):
     from tests.gpu_util import case, device
     device()
     case("bench default line, 2 steps")
-    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "2", "--warmup", "1", "--no-extras"])
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "2", "--warmup", "1", "--no-extras", "--no-autotune",
+                                      "--quick-cpu"])
     bench.main()
     line = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("{")][-1]
     d = json.loads(line)
