@@ -280,38 +280,44 @@ def leg_largest_stage(args):
 
     thp = None
     if not args.no_extras:
-        # ---- time-to-posterior, plain FP64 against mixed precision + surrogate,
-        # at the configured fixed pCN step (one untimed short run of each first)
+        # ---- time-to-posterior, plain FP64 against mixed precision + surrogate:
+        # at the configured fixed pCN step, and with the step adapted between
+        # stages (an extension; with sigma_n = 0.001 the fixed step's
+        # acceptance collapses on the fine levels, so the chains barely move
+        # there).  One untimed short run of each form first.
         sur = dict(surrogate=True, sur_collect_max_level=6, sur_da_min_level=7, sur_pairs=20480, sur_epochs=15,
                    sur_hidden=256)
         ctx.run(y, 256, seed=1)
         ctxm.run(y, 256, seed=1, **sur)
         torch.cuda.synchronize()
-        runs = {}
-        for name, c, kw in (("plain_fp64", ctx, {}), ("mixed_surrogate", ctxm, sur)):
-            r = c.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=31,
-                      **kw)
-            th = r["theta"]
-            mean = th.mean(0, keepdim=True).contiguous()
-            Gm = ctx.forward(L, mean)[0]
-            rec = run_summary(r, mean[0].cpu().numpy(), th_true, lam, rel_misfit(Gm.cpu().numpy(), y.cpu().numpy()))
-            if kw:
-                rec.update(surrogate_train_s=round(r["sur_train_seconds"], 3),
-                           stage1_pass_frac=round(r["stage1_passed"] / max(1, r["da_proposed"]), 4),
-                           surrogate_err_over_sigma_n=dict(mean=round(r["sur_err_mean"], 4),
-                                                           max=round(r["sur_err_max"], 4),
-                                                           solves_judged=r["sur_err_count"]))
-            runs[name] = (r, rec, mean[0].cpu().numpy())
-            log(f"time-to-posterior {name}: {rec}")
-            if name == "plain_fp64":
-                thp = th.contiguous()
-        extras["time_to_posterior_s"] = {k: v[1]["seconds"] for k, v in runs.items()}
-        extras["speedup_mixed_surrogate_vs_plain_fp64"] = round(
-            runs["plain_fp64"][1]["seconds"] / runs["mixed_surrogate"][1]["seconds"], 3)
-        extras["run_plain_fp64"] = runs["plain_fp64"][1]
-        extras["run_mixed_surrogate"] = runs["mixed_surrogate"][1]
-        extras["rel_err_between_forms"] = round(rel_err_paper(runs["mixed_surrogate"][2], runs["plain_fp64"][2], lam), 4)
-        solves_fp64 = runs["plain_fp64"][0]["solves"]
+        extras["time_to_posterior_s"] = {}
+        for step_rule, adapt in (("fixed_step", False), ("adapted_step", True)):
+            runs = {}
+            for name, c, kw in (("plain_fp64", ctx, {}), ("mixed_surrogate", ctxm, sur)):
+                r = c.run(y, J, J_tilde=100, tau_star=W["tau_star"], n_mcmc=W["n_mcmc"], s_pcn=W["s_pcn"], seed=31,
+                          s_adapt=adapt, **kw)
+                th = r["theta"]
+                mean = th.mean(0, keepdim=True).contiguous()
+                Gm = ctx.forward(L, mean)[0]
+                rec = run_summary(r, mean[0].cpu().numpy(), th_true, lam,
+                                  rel_misfit(Gm.cpu().numpy(), y.cpu().numpy()))
+                if kw:
+                    rec.update(surrogate_train_s=round(r["sur_train_seconds"], 3),
+                               stage1_pass_frac=round(r["stage1_passed"] / max(1, r["da_proposed"]), 4),
+                               surrogate_err_over_sigma_n=dict(mean=round(r["sur_err_mean"], 4),
+                                                               max=round(r["sur_err_max"], 4),
+                                                               solves_judged=r["sur_err_count"]))
+                runs[name] = (r, rec, mean[0].cpu().numpy())
+                log(f"time-to-posterior {step_rule} {name}: {rec}")
+                if name == "plain_fp64" and not adapt:
+                    thp = th.contiguous()
+                    solves_fp64 = r["solves"]
+            extras["time_to_posterior_s"][step_rule] = {k: v[1]["seconds"] for k, v in runs.items()}
+            extras["time_to_posterior_s"][step_rule]["speedup_mixed_surrogate_vs_plain_fp64"] = round(
+                runs["plain_fp64"][1]["seconds"] / runs["mixed_surrogate"][1]["seconds"], 3)
+            extras[f"run_{step_rule}"] = {k: v[1] for k, v in runs.items()}
+            extras[f"run_{step_rule}"]["rel_err_between_forms"] = round(
+                rel_err_paper(runs["mixed_surrogate"][2], runs["plain_fp64"][2], lam), 4)
 
         # ---- per-level forward solves/s of both forms on J prior draws, and the
         # mixed form's error against the FP64 path (itself rel 1e-10 of the oracle)

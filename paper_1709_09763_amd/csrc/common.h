@@ -265,6 +265,16 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
+// A value every lane of the wave holds bitwise alike, moved to scalar
+// registers (frees vector registers in the large solver kernels).
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Deterministic block reduction (fixed butterfly within waves, waves summed
 // in order by every thread).  `red` must hold BS/64 doubles; the result is
 // returned to all threads.
@@ -279,7 +289,7 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 #pragma unroll
     for (int k = 0; k < BS / 64; ++k) s += red[k];
     __syncthreads();
-    return s;
+    return wave_uniform(s);  // every thread summed the same terms in the same order
 }
 
 template <int BS>
@@ -293,7 +303,7 @@ __device__ __forceinline__ double block_max(double v, double* red)
 #pragma unroll
     for (int k = 1; k < BS / 64; ++k) s = fmax(s, red[k]);
     __syncthreads();
-    return s;
+    return wave_uniform(s);
 }
 
 }  // namespace mls

@@ -27,6 +27,7 @@
 // a symmetric positive definite preconditioner.  Coarsest level l = 1 has one
 // unknown and is solved exactly.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -124,6 +125,7 @@ struct Map {
     int lds_top;
     int fine_n;
     double* cinv;  // 9 x 9 inverse of the h = 1/4 operator (LDS or the slot), FP64 only
+    T* ring;       // LDS rows of the fused row walks (null: the walks are off)
 };
 
 __host__ __device__ inline int64_t lds_coarse_elems(int top)
@@ -163,13 +165,15 @@ int64_t solver_lds_elems_used(int l, bool mixed, int64_t budget_elems)
 }
 
 template <typename T>
-__device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems, double* cinv)
+__device__ inline Map<T> make_map(T* slot, T* lds, int l, int64_t lds_budget_elems, double* cinv,
+                                  T* ring = nullptr)
 {
     Map<T> M;
     M.slot = slot;
     M.lds = lds;
     M.l = l;
     M.cinv = cinv;
+    M.ring = ring;
     lds_policy(l, sizeof(T) == 8, lds ? lds_budget_elems : 0, &M.lds_top, &M.fine_n);
     return M;
 }
@@ -491,6 +495,292 @@ __device__ double up_step(const Lv<T, W>& L, const Lv<T>& C, const T* __restrict
     return dot;
 }
 
+// ------------------------------------------------------- fused row walks --
+// On a large level (n >= 256) the down-leg (optional residual update r -= a q,
+// red sweep from a zero start, black sweep, restriction of the residual)
+// and the up-leg (black sweep with the coarse correction, red sweep, the
+// dot (b, z)) each run as one pass over the rows instead of three and two.
+// Thread t of a band owns the column pair (2t, 2t+1) of every row of the
+// band, so each row step gives every thread one red and one black node.
+// Going up row j, the down walk updates the residual of row j and its red
+// node, the black node of row j-1 (its red neighbours are final), the red
+// residual of row j-2 (its black neighbours are final) and, one step later
+// (the residuals of a row come from neighbouring threads), the coarse
+// right-hand side of coarse row (j-4)/2.  A node's own column lives in the
+// thread's registers, the neighbouring threads' values pass through a ring
+// of LDS rows, with one barrier per row step.  Every node evaluates the
+// same expression as the separate sweeps, so the iterates are bitwise
+// theirs; only the order of the terms of (b, z) differs.
+//
+// The m = BS / (n/2) bands walk their row ranges [j0, j1) in lock step.  A
+// band first recomputes, without storing, the three rows below j0 from the
+// residual update's inputs, which the band below overwrites only at the end
+// of its walk; above j1 it recomputes the red and black values from the
+// updated residual, which the band above stored in its first steps.  The up
+// walk reads only values that no band writes during it (the down walk's z,
+// the right-hand side, the coarse correction) and writes the new z to a
+// second array, so its bands need no ordering at all.
+template <int BS>
+__device__ __forceinline__ bool walk_level(int n, int nu)
+{
+    return nu == 1 && n >= 256 && BS % (n >> 1) == 0;
+}
+
+// LDS elements of the walks on a level of width n: per band four rows of
+// the node values and four rows of the red residuals (one per thread)
+__host__ __device__ inline int64_t walk_ring_elems_level(int bs, int n)
+{
+    const int64_t m = bs / (n >> 1);
+    return m * (4 * (int64_t)(n + 1) + 4 * (int64_t)((n >> 1) + 1));
+}
+// the most any walked level of a hierarchy with finest level l needs
+__host__ __device__ inline int64_t walk_ring_elems(int bs, int l)
+{
+    int64_t e = 0;
+    for (int L = l; L >= 8; --L) {
+        const int n = 1 << L;
+        if (bs % (n >> 1) == 0) {
+            const int64_t v = walk_ring_elems_level(bs, n);
+            if (v > e) e = v;
+        }
+    }
+    return e;
+}
+
+// One band's rows: [j0, j1), the ring offset of the band, this thread's
+// pair.  A band has n / m rows, an even number, so every band starts on an
+// odd row and the walks can unroll two row steps of fixed parity.
+struct WalkRows {
+    int t, j0, j1;
+    int64_t ring_off;
+};
+template <int BS>
+__device__ __forceinline__ WalkRows walk_rows(int n)
+{
+    const int P = n >> 1, m = BS / P;
+    const int band = threadIdx.x / P;
+    WalkRows w;
+    w.t = threadIdx.x - band * P;
+    const int rows = n / m;
+    w.j0 = 1 + band * rows;
+    w.j1 = min(n, w.j0 + rows);
+    w.ring_off = (int64_t)band * (4 * (n + 1) + 4 * (P + 1));
+    return w;
+}
+
+template <int K>
+using Par = std::integral_constant<int, K>;
+
+// The walked levels never sit in LDS (a row of 257 values already exceeds
+// the residency budgets), so the walks address their arrays as global
+// memory and their rows as LDS: global and LDS instructions instead of flat
+// ones, which also lets the compiler keep them apart.
+template <typename T>
+using gmem = T __attribute__((address_space(1)))*;
+template <typename T>
+using lmem = T __attribute__((address_space(3)))*;
+
+// The barrier between row steps: it orders the LDS ring only, so the
+// global loads and stores of a step stay in flight across it (a full
+// barrier would wait for every store to be acknowledged).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Down-leg of a V(1,1) cycle on level L into the coarser level's right-hand
+// side C.b.  With Q: b -= alpha Q first (the CG residual update; b is
+// updated in place) and, with X and Pn, also X += alpha Pn (the mixed
+// solver's iterate).  Without Q, b is only read.  x receives z.  In a step
+// on row j every phase works on the thread's column of parity j: the red
+// node of row j, the black node of row j-1 and the red node of row j-2 all
+// sit in it.  The node values of the last four rows are kept in the LDS
+// ring (the thread's own ones too), the weights are read where needed (the
+// rows were read a step or two before, so these reads hit the caches).
+template <int BS, typename T, typename W>
+__device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, const T* __restrict__ Q, T alpha,
+                          T* __restrict__ x, T* __restrict__ X, const T* __restrict__ Pn, T* __restrict__ ring)
+{
+    const int n = L.n, s = L.s, P = n >> 1, sc = C.s, nc = C.n;
+    const WalkRows w = walk_rows<BS>(n);
+    const int t = w.t, j0 = w.j0, j1 = w.j1, ca = 2 * t;
+    const lmem<T> lring = (lmem<T>)ring;
+    const lmem<T> zr = lring + w.ring_off;  // node values, 4 rows of s
+    const lmem<T> rr = zr + 4 * s;          // red residuals, 4 rows of P + 1
+    // columns 0 and n of the rows are never written: they read as the zero boundary
+    for (int k = threadIdx.x; k < walk_ring_elems_level(BS, n); k += BS) lring[k] = T(0);
+    __syncthreads();
+    const gmem<const W> wx = (gmem<const W>)L.wx;
+    const gmem<const W> wy = (gmem<const W>)L.wy;
+    const gmem<T> gb = (gmem<T>)b;
+    const gmem<const T> gQ = (gmem<const T>)Q;
+    const gmem<T> gx = (gmem<T>)x;
+    const gmem<T> gX = (gmem<T>)X;
+    const gmem<const T> gPn = (gmem<const T>)Pn;
+    const gmem<T> gCb = (gmem<T>)C.b;
+    T r0[2] = {T(0), T(0)}, r1[2] = {T(0), T(0)}, r2[2] = {T(0), T(0)};  // updated residual, rows j .. j-2
+    auto body = [&](auto par, int j) {
+        constexpr int k = decltype(par)::value;  // the active column: ca + k
+        r2[0] = r1[0]; r2[1] = r1[1]; r1[0] = r0[0]; r1[1] = r0[1]; r0[0] = T(0); r0[1] = T(0);
+        const bool active = ca + k > 0;  // column 0 is the boundary
+        auto Z = [&](int jj, int i) -> T __attribute__((address_space(3)))& { return zr[(jj & 3) * s + i]; };
+        if (j == n) {  // the top boundary row, read by the black sweep and the residuals below it
+            Z(n, ca) = T(0);
+            Z(n, ca + 1) = T(0);
+        }
+        // ---- row j: residual update and the red node
+        if (j >= 1 && j <= n - 1 && j <= j1 + 2) {
+            const int c = j * s + ca;
+            if (Q && j < j1) {
+                r0[0] = gb[c] - alpha * gQ[c];
+                r0[1] = gb[c + 1] - alpha * gQ[c + 1];
+                if (j >= j0) {
+                    if (ca > 0) gb[c] = r0[0];
+                    gb[c + 1] = r0[1];
+                    if (X) {
+                        gX[c] += alpha * gPn[c];
+                        gX[c + 1] += alpha * gPn[c + 1];
+                    }
+                }
+            } else {  // no update, or rows above the band (updated there already)
+                r0[0] = gb[c];
+                r0[1] = gb[c + 1];
+            }
+            if (active) {
+                const int q = c + k;
+                Z(j, ca + k) = r0[k] / (T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]));
+            }
+        }
+        // ---- row j-1: the black node (red neighbours final)
+        const int jb = j - 1;
+        if (jb >= 1 && jb <= n - 1 && jb >= j0 - 2 && jb <= j1 + 1) {
+            const int i = ca + k;
+            if (active) {
+                const int q = jb * s + i;
+                const T nb = T(wx[q - 1]) * Z(jb, i - 1) + T(wx[q]) * Z(jb, i + 1) + T(wy[q - s]) * Z(jb - 1, i)
+                           + T(wy[q]) * Z(j, i);
+                Z(jb, i) = (r1[k] + nb) / (T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]));
+            }
+            if (jb >= j0 && jb < j1) {  // row j-1 is final: store both columns
+                if (ca > 0) gx[jb * s + ca] = Z(jb, ca);
+                gx[jb * s + ca + 1] = Z(jb, ca + 1);
+            }
+        }
+        // ---- row j-2: the red residual (black neighbours final)
+        const int jc = j - 2;
+        if (jc >= 1 && jc <= n - 1 && jc >= j0 - 1 && jc <= j1 && active) {
+            const int i = ca + k, q = jc * s + i;
+            const T d = T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]);
+            const T lnb = T(wx[q - 1]) * Z(jc, i - 1) + T(wx[q]) * Z(jc, i + 1) + T(wy[q - s]) * Z(jc - 1, i)
+                        + T(wy[q]) * Z(jc + 1, i);
+            rr[(jc & 3) * (P + 1) + t] = r2[k] - (d * Z(jc, i) - lnb);
+        }
+        // ---- coarse row (j-4)/2: restriction of the red residuals
+        if (k == 0) {
+            const int J = (j - 4) >> 1;
+            if (J >= 1 && J <= nc - 1 && 2 * J >= j0 && 2 * J < j1 && t >= 1 && t <= nc - 1) {
+                const T a0 = rr[((2 * J) & 3) * (P + 1) + t];
+                const T ap = rr[((2 * J + 1) & 3) * (P + 1) + t];
+                const T am = rr[((2 * J - 1) & 3) * (P + 1) + t - 1];
+                gCb[J * sc + t] = a0 + T(0.5) * (ap + am);
+            }
+        }
+        // the band above stored its first three rows (the rows this band's
+        // walk ends on) in steps 3 to 5: one full barrier after them makes
+        // those stores visible; every other step orders the LDS ring only
+        if (j - (j0 - 3) == 6) __syncthreads();
+        else lds_barrier();
+    };
+    // rows j0 - 3 (even) .. j1 + 3
+#pragma unroll 1
+    for (int j = j0 - 3; j <= j0 + (n / (BS / P)) + 4; j += 2) {
+        body(Par<0>{}, j);
+        body(Par<1>{}, j + 1);
+    }
+    __syncthreads();  // z, the updated residual and C.b are complete
+}
+
+// Up-leg of a V(1,1) cycle on level L after the coarser level was solved
+// (its correction e, row stride sc): the black sweep with the correction
+// interpolated at the red neighbours, then the red sweep, reading the down
+// walk's z from xo and writing the new z to xn.  Returns (b, z) over the
+// interior nodes when want_dot.  In a step on row j both phases work on the
+// thread's column of parity j + 1: the black node of row j and the red node
+// of row j - 1.  New values pass through the LDS ring as in walk_down.
+template <int BS, typename T, typename W>
+__device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, const T* __restrict__ b,
+                          const T* __restrict__ xo, T* __restrict__ xn, bool want_dot, T* __restrict__ ring,
+                          double* red)
+{
+    const int n = L.n, s = L.s;
+    const WalkRows w = walk_rows<BS>(n);
+    const int j0 = w.j0, j1 = w.j1, ca = 2 * w.t;
+    const lmem<T> lring = (lmem<T>)ring;
+    const lmem<T> zb = lring + w.ring_off;  // new values, 4 rows of s
+    for (int k = threadIdx.x; k < walk_ring_elems_level(BS, n); k += BS) lring[k] = T(0);
+    __syncthreads();
+    const gmem<const W> wx = (gmem<const W>)L.wx;
+    const gmem<const W> wy = (gmem<const W>)L.wy;
+    const gmem<const T> ge = (gmem<const T>)e;
+    const gmem<const T> gbv = (gmem<const T>)b;
+    const gmem<const T> xo_ = (gmem<const T>)xo;
+    const gmem<T> xn_ = (gmem<T>)xn;
+    auto pe = [&](int ii, int jj) -> T {
+        const int q = (jj >> 1) * sc + (ii >> 1);
+        return (ii & 1) ? T(0.5) * (ge[q] + ge[q + sc + 1]) : ge[q];
+    };
+    T b0[2] = {T(0), T(0)}, b1[2] = {T(0), T(0)};  // right-hand side of rows j, j-1
+    double dot = 0.0;
+    auto body = [&](auto par, int j) {
+        constexpr int k = 1 - decltype(par)::value;  // the active column: ca + k
+        b1[0] = b0[0]; b1[1] = b0[1]; b0[0] = T(0); b0[1] = T(0);
+        auto Z = [&](int jj, int i) -> T __attribute__((address_space(3)))& { return zb[(jj & 3) * s + i]; };
+        const int i = ca + k;
+        if (j == n) {  // the top boundary row, read by the red sweep below it
+            Z(n, ca) = T(0);
+            Z(n, ca + 1) = T(0);
+        }
+        // ---- row j: the black node, corrected
+        if (j >= 1 && j <= n - 1 && j <= j1) {
+            const int c0 = j * s + ca;
+            b0[0] = gbv[c0];
+            b0[1] = gbv[c0 + 1];
+            if (i > 0) {
+                const int c = c0 + k;
+                const T xe = xo_[c + 1];
+                const T nb = T(wx[c - 1]) * (xo_[c - 1] + pe(i - 1, j)) + T(wx[c]) * (xe + pe(i + 1, j))
+                           + T(wy[c - s]) * (xo_[c - s] + pe(i, j - 1)) + T(wy[c]) * (xo_[c + s] + pe(i, j + 1));
+                Z(j, i) = (b0[k] + nb) / (T(wx[c - 1]) + T(wx[c]) + T(wy[c - s]) + T(wy[c]));
+            }
+        }
+        // ---- row j-1: the red node (black neighbours new); the row is then final
+        const int jr = j - 1;
+        if (jr >= j0 && jr < j1) {
+            if (i > 0) {
+                const int q = jr * s + i;
+                const T lnb = T(wx[q - 1]) * Z(jr, i - 1) + T(wx[q]) * Z(jr, i + 1) + T(wy[q - s]) * Z(jr - 1, i)
+                            + T(wy[q]) * Z(j, i);
+                Z(jr, i) = (b1[k] + lnb) / (T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]));
+            }
+            const T za = Z(jr, ca), zbb = Z(jr, ca + 1);
+            if (ca > 0) xn_[jr * s + ca] = za;
+            xn_[jr * s + ca + 1] = zbb;
+            if (want_dot) dot += (double)b1[0] * (double)za + (double)b1[1] * (double)zbb;
+        }
+        lds_barrier();  // the walk reads no global value another thread writes
+    };
+    // rows j0 - 1 (even) .. j1
+#pragma unroll 1
+    for (int j = j0 - 1; j <= j0 + (n / (BS / (n >> 1))); j += 2) {
+        body(Par<0>{}, j);
+        body(Par<1>{}, j + 1);
+    }
+    __syncthreads();  // the new z is complete
+    return want_dot ? block_sum<BS>(dot, red) : 0.0;
+}
+
 // The V-cycle's coarsest level is h = 1/4 (nine unknowns), solved exactly
 // with the inverse of its operator, formed once per particle in FP64 by the
 // first wave: Gauss-Jordan sweeps in place over the 9 x 9 array (the
@@ -606,10 +896,60 @@ __device__ double vcycle(const Map<T>& M, const Lv<T, W>& F, const T* __restrict
     return up_step<BS>(F, coarse_level(M, l - 1), rhs, sol, nu, want_dot, red);
 }
 
+// The V(1,1) cycle with the fused row walks on every level that has them
+// (walk_down / walk_up); the smaller levels keep the separate sweeps.  The
+// finest level's up-leg writes z into zn, which the caller then takes as its
+// z; a walked coarse level keeps its up-leg's result in its coarsening
+// buffer (free after the set-up).  With Q the finest down walk first
+// updates rhs -= alpha Q (and X += alpha Pn).  Returns (rhs, z) when
+// want_dot.
+template <int BS, typename T, typename W>
+__device__ double vcycle_walk(const Map<T>& M, const Lv<T, W>& F, T* rhs, const T* Q, T alpha, T* X, const T* Pn,
+                              T* sol, T* zn, bool want_dot, double* red)
+{
+    const int l = M.l;
+    constexpr int Lc = kExactCoarse<T> ? 2 : 1;
+    auto walked = [&](int L) { return walk_level<BS>(1 << L, 1); };
+    auto result = [&](int L) {  // level L's z after its up-leg
+        Lv<T> V = coarse_level(M, L);
+        if (walked(L)) V.x = V.kap;
+        return V;
+    };
+    walk_down<BS>(F, coarse_level(M, l - 1), rhs, Q, alpha, sol, X, Pn, M.ring);
+    for (int Lk = l - 1; Lk > Lc; --Lk) {
+        const Lv<T> L = coarse_level(M, Lk);
+        if (walked(Lk))
+            walk_down<BS>(L, coarse_level(M, Lk - 1), L.b, (const T*)nullptr, T(0), L.x, (T*)nullptr,
+                          (const T*)nullptr, M.ring);
+        else
+            down_step<BS>(L, coarse_level(M, Lk - 1), L.b, L.x, 1, false);
+    }
+    {
+        const Lv<T> C = coarse_level(M, Lc);
+        if constexpr (kExactCoarse<T>) {
+            coarse_exact<BS>(C, C.b, C.x, M.cinv);
+        } else {  // one unknown at (1,1), solved in FP64
+            if (threadIdx.x == 0) {
+                const int c = C.s + 1;
+                C.x[c] = T((double)C.b[c] / (double)diag_at(C.wx, C.wy, c, C.s));
+            }
+            __syncthreads();
+        }
+    }
+    for (int Lk = Lc + 1; Lk <= l - 1; ++Lk) {
+        const Lv<T> L = coarse_level(M, Lk);
+        const Lv<T> Cc = result(Lk - 1);
+        if (walked(Lk)) walk_up<BS>(L, Cc.x, Cc.s, L.b, L.x, L.kap, false, M.ring, red);
+        else up_step<BS>(L, Cc, L.b, L.x, 1, false, red);
+    }
+    const Lv<T> Cf = result(l - 1);
+    return walk_up<BS>(F, Cf.x, Cf.s, rhs, sol, zn, want_dot, M.ring, red);
+}
+
 // ------------------------------------------------------- setup & obs --
 template <int BS, typename T, typename KT>
 __device__ void setup_hierarchy(const Map<T>& M, const Lv<T>& F, const KT* __restrict__ kap,
-                                float* wx32 = nullptr, float* wy32 = nullptr)
+                                float* wx32 = nullptr, float* wy32 = nullptr, bool walks = false)
 {
     const int l = M.l;
     edge_weights<BS>(kap, F.wx, F.wy, F.n, F.lg, wx32, wy32);
@@ -624,6 +964,12 @@ __device__ void setup_hierarchy(const Map<T>& M, const Lv<T>& F, const KT* __res
             if (L >= 2) coarsen_kappa<BS>(V.kap, coarse_level(M, L - 1).kap, L - 1);
             __syncthreads();
         }
+        // a walked level's coefficients are dead now: the buffer takes the
+        // up-leg's z, whose boundary must read zero
+        if (walks)
+            for (int L = l - 1; L >= 8; --L)
+                if (walk_level<BS>(1 << L, 1)) zero_boundary<BS>(coarse_level(M, L).kap, 1 << L);
+        __syncthreads();
     }
 }
 
@@ -691,7 +1037,7 @@ __device__ inline Lv<T> fine_level(const Map<T>& M)
 }
 
 // ---------------------------------------------------------- FP64 solve --
-template <int BS, bool WK>
+template <int BS, int WK>
 __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
@@ -707,16 +1053,27 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
     const int s = F.s;
     const double h2 = 1.0 / (double)(F.n * F.n);
     const double* kap = (const double*)J.kap;
+    // WK = 2 instances run the fused row walks (their launch guarantees a
+    // walked level, V(1,1) and the LDS ring); the new z goes to Q's array,
+    // and the two swap after every cycle
+    constexpr bool walks = WK == 2;
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
     zero_boundary<BS>(Pb[0], F.n);
     zero_boundary<BS>(Pb[1], F.n);
-    setup_hierarchy<BS>(M, F, kap, FV.wx, FV.wy);
+    if (walks) zero_boundary<BS>(Q, F.n);
+    setup_hierarchy<BS>(M, F, kap, FV.wx, FV.wy, walks);
     if (l == 2) build_coarse_inverse<BS>(FV, M.cinv);
     else if (l >= 3) build_coarse_inverse<BS>(coarse_level(M, 2), M.cinv);
     MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
     __syncthreads();
-    vcycle<BS>(M, FV, R, Z, C.nu, false, false, red);
+    if (walks) {
+        vcycle_walk<BS>(M, FV, R, (const double*)nullptr, 0.0, (double*)nullptr, (const double*)nullptr, Z, Q,
+                        false, red);
+        double* t_ = Z; Z = Q; Q = t_;
+    } else {
+        vcycle<BS>(M, FV, R, Z, C.nu, false, false, red);
+    }
     double rz = 0.0;
     MLS_FOR_INTERIOR(F, { rz += R[c] * Z[c]; })
     rz = block_sum<BS>(rz, red);
@@ -739,7 +1096,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         double pq = 0.0;
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
         double* Xu = it > 0 ? X : nullptr;
-        if (WK && F.n >= 64 && BS % F.n == 0) {
+        if (WK >= 1 && F.n >= 64 && BS % F.n == 0) {
             pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q, Xu, xa);
         } else {
             MLS_FOR_INTERIOR(F, {
@@ -757,14 +1114,20 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         const double alpha = rz / pq;
         xa = alpha;
         Pl = Pn;
-        // the r update fused with the first red sweep of the V-cycle
-        MLS_FOR_INTERIOR(F, {
-            const double rn = R[c] - alpha * Q[c];
-            R[c] = rn;
-            Z[c] = (((i + j) & 1) == 0) ? rn / ldiag(FV, c) : 0.0;  // black: taken as zero
-        })
-        __syncthreads();
-        const double rzn = vcycle<BS>(M, FV, R, Z, C.nu, l > 1, true, red);
+        double rzn;
+        if (walks) {  // the r update rides on the down walk
+            rzn = vcycle_walk<BS>(M, FV, R, Q, alpha, (double*)nullptr, (const double*)nullptr, Z, Q, true, red);
+            double* t_ = Z; Z = Q; Q = t_;
+        } else {
+            // the r update fused with the first red sweep of the V-cycle
+            MLS_FOR_INTERIOR(F, {
+                const double rn = R[c] - alpha * Q[c];
+                R[c] = rn;
+                Z[c] = (((i + j) & 1) == 0) ? rn / ldiag(FV, c) : 0.0;  // black: taken as zero
+            })
+            __syncthreads();
+            rzn = vcycle<BS>(M, FV, R, Z, C.nu, l > 1, true, red);
+        }
         ++it;
         if (!isfinite(rzn)) { st = 2; break; }
         if (rzn <= C.tol2 * rz0) { st = 0; break; }
@@ -794,7 +1157,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
 // done in FP64.
 constexpr double kDrift2 = 1e-6;  // replace r after (r, z) fell by this factor (1e-3 in norm)
 
-template <int BS, bool WK>
+template <int BS, int WK>
 __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
@@ -806,12 +1169,14 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
     double* X64 = (double*)(M.slot + ((hier + 1) & ~int64_t(1)));
     const double h2 = 1.0 / (double)(F.n * F.n);
     const float* kap = (const float*)J.kap;
+    constexpr bool walks = WK == 2;  // as in the FP64 solver
     zero_boundary<BS>(X, F.n);
     zero_boundary<BS>(Z, F.n);
     zero_boundary<BS>(Pb[0], F.n);
     zero_boundary<BS>(Pb[1], F.n);
     zero_boundary<BS>(X64, F.n);
-    setup_hierarchy<BS>(M, F, kap);
+    if (walks) zero_boundary<BS>(Q, F.n);
+    setup_hierarchy<BS>(M, F, kap, nullptr, nullptr, walks);
     MLS_FOR_INTERIOR(F, { X64[c] = 0.0; X[c] = 0.f; R[c] = (float)h2; })
     __syncthreads();
     // x64 += x32, x32 = 0, then r = b - A x64 in FP64 (rounded to FP32)
@@ -830,6 +1195,12 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         __syncthreads();
     };
     auto precondition = [&]() {  // z = V r and (r, z)
+        if (walks) {
+            const double d = vcycle_walk<BS>(M, F, R, (const float*)nullptr, 0.f, (float*)nullptr,
+                                             (const float*)nullptr, Z, Q, true, red);
+            float* t_ = Z; Z = Q; Q = t_;
+            return d;
+        }
         vcycle<BS>(M, F, R, Z, C.nu, false, false, red);
         double rz = 0.0;
         MLS_FOR_INTERIOR(F, { rz += (double)R[c] * (double)Z[c]; })
@@ -849,7 +1220,7 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         float* Pn = Pb[it & 1];
         double pq = 0.0;
         auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
-        if (WK && F.n >= 64 && BS % F.n == 0) {
+        if (WK >= 1 && F.n >= 64 && BS % F.n == 0) {
             pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
         } else {
             MLS_FOR_INTERIOR(F, {
@@ -864,14 +1235,20 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         }
         pq = block_sum<BS>(pq, red);
         const float alpha = (float)(rz / pq);
-        MLS_FOR_INTERIOR(F, {
-            X[c] += alpha * Pn[c];
-            const float rn = R[c] - alpha * Q[c];
-            R[c] = rn;
-            Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.f;  // black: taken as zero
-        })
-        __syncthreads();
-        const double rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
+        double rzn;
+        if (walks) {  // the x and r updates ride on the down walk
+            rzn = vcycle_walk<BS>(M, F, R, Q, alpha, X, Pn, Z, Q, true, red);
+            float* t_ = Z; Z = Q; Q = t_;
+        } else {
+            MLS_FOR_INTERIOR(F, {
+                X[c] += alpha * Pn[c];
+                const float rn = R[c] - alpha * Q[c];
+                R[c] = rn;
+                Z[c] = (((i + j) & 1) == 0) ? rn / diag_at(F.wx, F.wy, c, s) : 0.f;  // black: taken as zero
+            })
+            __syncthreads();
+            rzn = vcycle<BS>(M, F, R, Z, C.nu, l > 1, true, red);
+        }
         ++it;
         if (!isfinite(rzn)) { st = 2; break; }
         const bool conv = rzn <= C.tol2 * rz0;
@@ -919,6 +1296,7 @@ struct SolveParams {
     const double* obs_w;
     int64_t lds_elems;  // LDS budget in elements of the working type
     int cinv_lds;       // FP64: the coarse inverse follows the budget in LDS (else in the slot)
+    int64_t ring_off;   // element offset of the row walks' LDS rows, or -1 (no walks)
     Common C;
 };
 
@@ -930,9 +1308,9 @@ extern __shared__ __align__(16) char mls_lds[];
 // column-walk instances run two 512-wide workgroups per CU at h = 1/512 and
 // at the tuned h = 1/64 shape, which four waves per SIMD hold without
 // spilling.
-#define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(MIXED ? 1 : (WK ? 4 : 6))))
+#define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(WK == 2 ? (MIXED ? 4 : 3) : (MIXED ? 1 : (WK ? 4 : 6)))))
 
-template <int BS, bool MIXED, bool WK>
+template <int BS, bool MIXED, int WK>
 __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P)
 {
     __shared__ double red[BS / 64];
@@ -953,12 +1331,14 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P
         J.obs_idx = P.obs_idx;
         J.obs_w = P.obs_w;
         if (MIXED) {
+            float* ring = (WK == 2 && P.ring_off >= 0) ? (float*)mls_lds + P.ring_off : nullptr;
             solve_one_mixed<BS, WK>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
-                                         P.lds_elems, nullptr), J, P.C, red);
+                                         P.lds_elems, nullptr, ring), J, P.C, red);
         } else {
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
-            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+            double* ring = (WK == 2 && P.ring_off >= 0) ? (double*)mls_lds + P.ring_off : nullptr;
+            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C, red);
         }
     }
 }
@@ -978,10 +1358,11 @@ struct ListParams {
     const double* obs_w[kMaxLevel + 1];
     int64_t lds_elems;
     int cinv_lds;
+    int64_t ring_off;
     Common C;
 };
 
-template <int BS, bool MIXED, bool WK>
+template <int BS, bool MIXED, int WK>
 __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListParams P)
 {
     __shared__ double red[BS / 64];
@@ -1007,12 +1388,14 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListPara
         J.obs_idx = P.obs_idx[l];
         J.obs_w = P.obs_w[l];
         if (MIXED) {
+            float* ring = (WK == 2 && P.ring_off >= 0) ? (float*)mls_lds + P.ring_off : nullptr;
             solve_one_mixed<BS, WK>(make_map((float*)P.ws + (int64_t)blockIdx.x * P.slot_elems, (float*)mls_lds, l,
-                                         P.lds_elems, nullptr), J, P.C, red);
+                                         P.lds_elems, nullptr, ring), J, P.C, red);
         } else {
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
-            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv), J, P.C, red);
+            double* ring = (WK == 2 && P.ring_off >= 0) ? (double*)mls_lds + P.ring_off : nullptr;
+            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C, red);
         }
     }
 }
@@ -1068,15 +1451,31 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
 // launch takes no more LDS than the budget (or than the inverse's 648 bytes
 // under a smaller one), so the workgroups per CU that a budget was chosen
 // for still fit.
-static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int64_t* alloc_elems, int* cinv_lds)
+static size_t lds_bytes_for(const mls2mc_ctx* ctx, int l, bool mixed, int bs, bool walks, int64_t* alloc_elems,
+                            int* cinv_lds, int64_t* ring_off)
 {
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     int64_t budget = ctx->solver_lds[l] >= 0 ? (ctx->solver_lds[l] ? ctx->solver_lds[l] : 65536) : 0;
     if (budget > ctx->max_lds) budget = ctx->max_lds;
+    // the row walks' rows come first: the residency gets what is left
+    const int64_t ring = walks ? walk_ring_elems(bs, l) : 0;
+    const int64_t ring_bytes = ring * (int64_t)esz;
+    const int64_t cinv_bytes = mixed ? 0 : kCinvElems * 8;
+    if (walks && budget > ctx->max_lds - ring_bytes - cinv_bytes)
+        budget = std::max<int64_t>(0, ctx->max_lds - ring_bytes - cinv_bytes);
     *alloc_elems = lds_elems_used(l, !mixed, (int64_t)(budget / esz));
     const int64_t room = budget > kCinvElems * 8 ? budget : kCinvElems * 8;
-    *cinv_lds = !mixed && (*alloc_elems + kCinvElems) * 8 <= room;
-    return (size_t)(*alloc_elems + (*cinv_lds ? kCinvElems : 0)) * esz;
+    *cinv_lds = !mixed && (walks || (*alloc_elems + kCinvElems) * 8 <= room);
+    const int64_t off = *alloc_elems + (*cinv_lds ? kCinvElems : 0);
+    *ring_off = walks ? off : -1;
+    return (size_t)(off + ring) * esz;
+}
+
+// the fused row walks of the V-cycle run for V(1,1) from h = 1/256 on when
+// half the row width divides the workgroup (walk_level)
+static bool launch_walks(int l, int bs, int nu)
+{
+    return nu == 1 && l >= 8 && bs % (1 << (l - 1)) == 0;
 }
 
 int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
@@ -1102,7 +1501,8 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
     P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w;
     P.C = make_common(ctx, l);
-    const size_t lds = lds_bytes_for(ctx, l, mixed, &P.lds_elems, &P.cinv_lds);
+    const bool fused = launch_walks(l, bs, P.C.nu);
+    const size_t lds = lds_bytes_for(ctx, l, mixed, bs, fused, &P.lds_elems, &P.cinv_lds, &P.ring_off);
     ProfRec rec;
     if (ctx->prof_on) {
         if (!P.iters) {  // the iteration totals need per-particle counts
@@ -1116,12 +1516,15 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     // stencil pass walks columns (measured faster from there; the smaller
     // levels are latency bound)
     const bool walk = l >= 6 && bs % (1 << l) == 0;
-    if (walk) {
-        if (mixed) { MLS_SWITCH_SOLVE(bs, true, true, g, lds, s, P) }
-        else { MLS_SWITCH_SOLVE(bs, false, true, g, lds, s, P) }
+    if (fused) {
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 2, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, 2, g, lds, s, P) }
+    } else if (walk) {
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 1, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, 1, g, lds, s, P) }
     } else {
-        if (mixed) { MLS_SWITCH_SOLVE(bs, true, false, g, lds, s, P) }
-        else { MLS_SWITCH_SOLVE(bs, false, false, g, lds, s, P) }
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 0, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, 0, g, lds, s, P) }
     }
     MLS_CHECK_HIP(hipGetLastError());
     if (ctx->prof_on) {
@@ -1156,16 +1559,17 @@ int launch_solve_list(mls2mc_ctx* ctx, const SolveItem* items_dev, int n_items, 
         P.obs_w[l] = ctx->obs[l].w;
     }
     P.C = make_common(ctx, lmax);
-    const size_t lds = lds_bytes_for(ctx, lmax, mixed, &P.lds_elems, &P.cinv_lds);
+    // the work list mixes levels, so it keeps the separate V-cycle passes
+    const size_t lds = lds_bytes_for(ctx, lmax, mixed, bs, false, &P.lds_elems, &P.cinv_lds, &P.ring_off);
     dim3 g((unsigned)grid);
     // items of h = 1/64 and finer walk columns in the CG stencil pass (the
     // instance decides per item)
     if (lmax >= 6) {
-        if (mixed) { MLS_SWITCH_LIST(bs, true, true, g, lds, s, P) }
-        else { MLS_SWITCH_LIST(bs, false, true, g, lds, s, P) }
+        if (mixed) { MLS_SWITCH_LIST(bs, true, 1, g, lds, s, P) }
+        else { MLS_SWITCH_LIST(bs, false, 1, g, lds, s, P) }
     } else {
-        if (mixed) { MLS_SWITCH_LIST(bs, true, false, g, lds, s, P) }
-        else { MLS_SWITCH_LIST(bs, false, false, g, lds, s, P) }
+        if (mixed) { MLS_SWITCH_LIST(bs, true, 0, g, lds, s, P) }
+        else { MLS_SWITCH_LIST(bs, false, 0, g, lds, s, P) }
     }
     MLS_CHECK_HIP(hipGetLastError());
     return MLS2MC_OK;
