@@ -70,6 +70,7 @@ def lib():
         L.orc_forward.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_int64,
                                   _dp, _dp, C.c_int]
         L.orc_forward_kappa.argtypes = [C.c_int, C.c_int, C.c_int64, _dp, _dp, _dp, C.c_int]
+        L.orc_flow_forward_kappa.argtypes = [C.c_int, C.c_int, C.c_int64, _dp, _dp, _dp, C.c_int]
         L.orc_kl_field.argtypes = [C.c_int, C.c_int, C.c_int64, _dp, _dp, _dp]
         L.orc_resample.argtypes = [C.c_int64, _dp, _dp, _i32p]
         L.orc_pcn_propose.argtypes = [C.c_int64, C.c_int, C.c_double, _dp, _dp, _dp]
@@ -227,6 +228,19 @@ def forward_kappa(l, m, kappa, want_p=False, nthreads=0):
     return (G, p) if want_p else G
 
 
+def flow_forward_kappa(l, m, kappa, want_p=False, nthreads=0):
+    """flow cell (Example 5.3) by banded Cholesky: G and optionally the
+    unknowns' pressure, u = j (n-1) + (i-1) for 1 <= i <= n-1, 0 <= j <= n"""
+    kappa = _f64(np.atleast_2d(kappa))
+    N = kappa.shape[0]
+    n = 1 << l
+    G = np.zeros((N, m * m))
+    p = np.zeros((N, (n - 1) * (n + 1))) if want_p else None
+    _check(lib().orc_flow_forward_kappa(l, m, N, _d(kappa), _d(G), _d(p) if want_p else None, nthreads),
+           "flow_forward_kappa")
+    return (G, p) if want_p else G
+
+
 # ------------------------------------------------------------------- SMC --
 def ess(d, scale, t):
     d = _f64(d)
@@ -289,7 +303,7 @@ def run_sampler(y, *, model="pde", l_min=4, l_max=4, K=10, sigma2=1.0, corr_len=
     """Run the MLS^2MC sampler; returns a dict of results and final particles."""
     y = _f64(y)
     cfg = Config()
-    cfg.model = 0 if model == "pde" else 1
+    cfg.model = {"pde": 0, "linear": 1, "flowcell": 2}[model]
     cfg.l_min, cfg.l_max, cfg.K = l_min, l_max, K
     cfg.sigma2, cfg.corr_len, cfg.m = sigma2, corr_len, m
     cfg.nobs = nobs if nobs is not None else len(y)

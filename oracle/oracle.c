@@ -452,6 +452,114 @@ int orc_forward_kappa(int l, int m, int64_t N, const double* kappa, double* G, d
     return err;
 }
 
+/* ======================================================================
+ * Flow cell (Sec. 5, Example 5.3): Dirichlet p = 0 / p = 1 on the left /
+ * right edge, natural (no-flow) conditions on the bottom and top edges.
+ * The same generic per-triangle assembly; the unknowns are the nodes off
+ * the two Dirichlet edges, bottom and top rows included.
+ * ==================================================================== */
+static int orc_flow_unknown(int n, int i, int j)
+{
+    if (i < 1 || i > n - 1 || j < 0 || j > n) return -1;
+    return j * (n - 1) + (i - 1);
+}
+
+/* nodal values (n+1)^2 (node j (n+1) + i) of one coefficient field */
+static int orc_flow_solve_nodes(int l, const double* kappa, double* pn)
+{
+    int n = 1 << l, ne = 2 * n * n, M = (n - 1) * (n + 1), bw = n;
+    double h = 1.0 / n;
+    double* band = (double*)calloc((size_t)M * (bw + 1), sizeof(double));
+    double* b = (double*)calloc((size_t)M, sizeof(double));
+    double* x = (double*)malloc(sizeof(double) * (size_t)M);
+    if (!band || !b || !x) { free(band); free(b); free(x); return ORC_ENOMEM; }
+    int rc = 0;
+    for (int e = 0; e < ne && rc == 0; ++e) {
+        int vi[3], vj[3], gu[3];
+        double xx[3], yy[3], g[3];
+        orc_tri_nodes(n, e, vi, vj);
+        for (int a = 0; a < 3; ++a) {
+            xx[a] = vi[a] * h;
+            yy[a] = vj[a] * h;
+            gu[a] = orc_flow_unknown(n, vi[a], vj[a]);
+            g[a] = vi[a] == n ? 1.0 : 0.0; /* Dirichlet value where gu < 0 */
+        }
+        double det = (xx[1] - xx[0]) * (yy[2] - yy[0]) - (xx[2] - xx[0]) * (yy[1] - yy[0]);
+        double area = 0.5 * fabs(det), gx[3], gy[3];
+        for (int a = 0; a < 3; ++a) {
+            int bb = (a + 1) % 3, c = (a + 2) % 3;
+            gx[a] = (yy[bb] - yy[c]) / det;
+            gy[a] = (xx[c] - xx[bb]) / det;
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (gu[a] < 0) continue;
+            for (int bb = 0; bb < 3; ++bb) {
+                double kab = kappa[e] * area * (gx[a] * gx[bb] + gy[a] * gy[bb]);
+                if (gu[bb] < 0) {
+                    b[gu[a]] -= kab * g[bb]; /* lift the known value */
+                    continue;
+                }
+                if (gu[bb] > gu[a]) continue;
+                int k = gu[a] - gu[bb];
+                if (k > bw) { rc = ORC_EINVAL; break; }
+                band[(size_t)gu[a] * (bw + 1) + k] += kab;
+            }
+        }
+    }
+    if (rc == 0) rc = orc_band_cholesky(M, bw, band);
+    if (rc == 0) {
+        orc_band_solve(M, bw, band, b, x);
+        for (int j = 0; j <= n; ++j)
+            for (int i = 0; i <= n; ++i) {
+                int u = orc_flow_unknown(n, i, j);
+                pn[j * (n + 1) + i] = u >= 0 ? x[u] : (i == n ? 1.0 : 0.0);
+            }
+    }
+    free(band); free(b); free(x);
+    return rc;
+}
+
+int orc_flow_forward_kappa(int l, int m, int64_t N, const double* kappa, double* G, double* p_out,
+                           int nthreads)
+{
+    if (l < 1 || l > 12 || m < 1 || N < 0) return ORC_EINVAL;
+    int n = 1 << l, ne = 2 * n * n, M = (n - 1) * (n + 1);
+    int err = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(min : err)
+#endif
+    for (int64_t q = 0; q < N; ++q) {
+        double* pn = (double*)malloc(sizeof(double) * (size_t)(n + 1) * (n + 1));
+        int rc = pn ? orc_flow_solve_nodes(l, kappa + q * ne, pn) : ORC_ENOMEM;
+        if (rc == 0) {
+            for (int bb = 1; bb <= m; ++bb)
+                for (int a = 1; a <= m; ++a) {
+                    double x = (double)a / (double)(m + 1), y = (double)bb / (double)(m + 1);
+                    int i = (int)floor(x * n), j = (int)floor(y * n);
+                    if (i > n - 1) i = n - 1;
+                    if (j > n - 1) j = n - 1;
+                    double xi = x * n - i, eta = y * n - j;
+                    const double* P = pn;
+                    int s = n + 1;
+                    double v;
+                    if (xi >= eta)
+                        v = (1.0 - xi) * P[j * s + i] + (xi - eta) * P[j * s + i + 1] + eta * P[(j + 1) * s + i + 1];
+                    else
+                        v = (1.0 - eta) * P[j * s + i] + xi * P[(j + 1) * s + i + 1] + (eta - xi) * P[(j + 1) * s + i];
+                    G[q * m * m + (bb - 1) * m + (a - 1)] = v;
+                }
+            if (p_out)
+                for (int j = 0; j <= n; ++j)
+                    for (int i = 1; i <= n - 1; ++i) p_out[q * M + orc_flow_unknown(n, i, j)] = pn[j * (n + 1) + i];
+        }
+        if (rc < err) err = rc;
+        free(pn);
+    }
+    (void)nthreads;
+    return err;
+}
+
 int orc_forward(int l, int K, double sigma2, double corr_len, int m, int64_t N,
                 const double* theta, double* G, int nthreads)
 {
@@ -655,7 +763,8 @@ static int orc_model_eval(orc_model* md, int l, int64_t N, const double* theta, 
     if (!kap) return ORC_ENOMEM;
     orc_kl_field(l, K, N, md->B[l], theta, kap);
     for (int64_t i = 0; i < N * ne; ++i) kap[i] = exp(kap[i]);
-    int rc = orc_forward_kappa(l, cfg->m, N, kap, G, NULL, cfg->nthreads);
+    int rc = cfg->model == ORC_MODEL_FLOWCELL ? orc_flow_forward_kappa(l, cfg->m, N, kap, G, NULL, cfg->nthreads)
+                                              : orc_forward_kappa(l, cfg->m, N, kap, G, NULL, cfg->nthreads);
     free(kap);
     return rc;
 }
@@ -809,7 +918,7 @@ int orc_run_sampler(const orc_config* cfg, const double* y, double* theta_out, o
     if (!cfg || !y || !res || cfg->J <= 0 || cfg->K <= 0 || cfg->l_min < 0 || cfg->l_max < cfg->l_min
         || cfg->l_max > 12 || cfg->n_mcmc < 0 || cfg->J_tilde < 1 || cfg->J_tilde > cfg->J)
         return ORC_EINVAL;
-    if (cfg->model == ORC_MODEL_PDE && cfg->l_min < 1) return ORC_EINVAL;
+    if (cfg->model != ORC_MODEL_LINEAR && cfg->l_min < 1) return ORC_EINVAL;
     orc_model md;
     memset(&md, 0, sizeof(md));
     md.cfg = cfg;

@@ -117,11 +117,21 @@ int orc_mh_accept(double psi_old, double psi_new, double u);
 int orc_da_accept(double psi_old, double psi_new, double psis_old, double psis_new,
                   double u1, double u2, int* stage1);
 
+/* Flow cell of Example 5.3 (Sec. 5): -div(kappa grad p) = 0, p = 0 at
+ * x1 = 0, p = 1 at x1 = 1, no flow through x2 = 0 and x2 = 1, P1 elements
+ * on the mesh of level l (generic per-triangle assembly over the unknown
+ * nodes 1 <= i <= n-1, 0 <= j <= n, u = j (n-1) + (i-1), the value 1 of
+ * the right edge moved to the right-hand side, banded Cholesky), observed
+ * at (a/(m+1), b/(m+1)) by P1 interpolation of the nodal values, boundary
+ * values included.  p_out (may be NULL): the unknowns' values.           */
+int orc_flow_forward_kappa(int l, int m, int64_t N, const double* kappa, double* G, double* p_out,
+                           int nthreads);
+
 /* ---- the MLS^2MC sampler ---- */
-enum { ORC_MODEL_PDE = 0, ORC_MODEL_LINEAR = 1 };
+enum { ORC_MODEL_PDE = 0, ORC_MODEL_LINEAR = 1, ORC_MODEL_FLOWCELL = 2 };
 
 typedef struct {
-    int model;          /* ORC_MODEL_PDE or ORC_MODEL_LINEAR                 */
+    int model;          /* ORC_MODEL_PDE, ORC_MODEL_LINEAR or ORC_MODEL_FLOWCELL */
     int l_min, l_max;   /* level range (h = 2^-l)                            */
     int K;              /* parameter dimension                               */
     double sigma2, corr_len;

@@ -91,3 +91,31 @@ def test_second_order_convergence_at_the_nodes():
         st = 128 // n
         errs.append(np.abs(p - ref[::st, ::st]).max())
     assert errs[1] < 0.35 * errs[0] and errs[2] < 0.35 * errs[1]
+
+
+@pytest.mark.parametrize("l", [1, 3, 5])
+def test_sampler_flow_model_reproduces_the_exact_cases(l):
+    """The sampler's own flow-cell forward (compiled, banded Cholesky) on the
+    same exact cases: p = x1 for coefficients constant in each row of cells,
+    the harmonic profile for coefficients constant in each column, and the
+    observation of p = x1 is the first coordinate of each point."""
+    import oracle
+    n, m = 1 << l, 5
+    xy = fc.node_xy(l)
+    lay = _rows_of_cells(l, np.exp(np.random.default_rng(20 + l).normal(size=n)))
+    G, p = oracle.flow_forward_kappa(l, m, lay[None], want_p=True)
+    np.testing.assert_allclose(p[0], fc.unknowns_of(l, xy[:, 0]), atol=1e-12)
+    np.testing.assert_allclose(G[0], np.tile(np.arange(1, m + 1), m) / (m + 1), atol=1e-12)
+    kc = np.exp(np.random.default_rng(30 + l).normal(size=n))
+    prof = np.concatenate([[0.0], np.cumsum(1.0 / kc)]) / np.sum(1.0 / kc)
+    G, p = oracle.flow_forward_kappa(l, m, _cols_of_cells(l, kc)[None], want_p=True)
+    np.testing.assert_allclose(p[0], fc.unknowns_of(l, np.tile(prof, n + 1)), atol=1e-12)
+
+
+def test_sampler_flow_model_matches_the_sparse_flow_oracle():
+    import oracle
+    for l in (2, 4, 6):
+        kap = inputs.kappa_batch(40 + l, 3, 2 * 4 ** l, spread=1.0)
+        G, p = oracle.flow_forward_kappa(l, 7, kap, want_p=True)
+        Gr, pr = fc.forward_kappa(l, 7, kap, want_p=True)
+        assert np.abs(G - Gr).max() < 1e-12 and np.abs(p - pr).max() < 1e-12

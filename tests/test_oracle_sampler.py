@@ -286,3 +286,34 @@ def test_delayed_acceptance_keeps_linear_gaussian_posterior():
     assert np.all(np.abs(means.mean(0) - m) < 4 * se + 0.02 * np.sqrt(np.diag(C)))
     np.testing.assert_allclose(np.mean(vars_, 0), np.diag(C), rtol=0.1)
     assert 0.05 < np.mean(pass_frac) < 0.95  # the surrogate does filter
+
+
+@pytest.mark.slow
+def test_flowcell_brute_force_posterior_k1():
+    # the flow-cell model (Example 5.3) with K = 1 at h = 1/8: posterior mean
+    # and variance by quadrature against the SMC estimate of the sampler run
+    # on that model
+    l, K, m, sn = 3, 1, 3, 0.01
+    B = oracle.kl_basis(l, K, 1.0, 0.3)
+
+    def G_of(th):
+        return oracle.flow_forward_kappa(l, m, np.exp(oracle.kl_field(l, B, th[:, None])))
+
+    y = G_of(np.array([0.9]))[0] + sn * inputs.rng(1).standard_normal(m * m)
+    grid = np.linspace(-6, 6, 4001)
+    phi = 0.5 * (((G_of(grid) - y) / sn) ** 2).sum(1)
+    lp = -phi - 0.5 * grid ** 2
+    wq = np.exp(lp - lp.max())
+    wq /= wq.sum()
+    mq = (wq * grid).sum()
+    vq = (wq * (grid - mq) ** 2).sum()
+    R, J = 6, 1500
+    ms, vs = [], []
+    for seed in range(R):
+        r = oracle.run_sampler(y, model="flowcell", l_min=l, l_max=l, K=K, m=m, sigma_n=sn, J=J, seed=seed)
+        ms.append(r["theta"].mean())
+        vs.append(r["theta"].var())
+    ms = np.array(ms)
+    se = ms.std(ddof=1) / np.sqrt(R)
+    assert abs(ms.mean() - mq) < 4 * se + 0.02 * np.sqrt(vq), (ms.mean(), mq, se)
+    assert abs(np.mean(vs) / vq - 1) < 0.15, (np.mean(vs), vq)
