@@ -29,3 +29,22 @@ def rel_err(a, b):
 
 def case(msg):
     print(f"[case] {msg}", flush=True)
+
+
+def stored_oracle_run(name, data, run):
+    """An oracle sampler run stored in tests/golden/oracle_runs.json (written
+    by tests/golden/make_oracle_runs.py from oracle/ alone).  The caller
+    states the case it expects; a stored case with other data or sampler
+    arguments is an error, so a stale file cannot pass silently."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_runs.json")
+    rec = json.load(open(path))[name]
+    if rec["case"]["data"] != data or rec["case"]["run"] != run:
+        raise AssertionError(f"stored oracle run {name} was made for another case; rerun make_oracle_runs.py")
+    r = dict(rec["result"])
+    for k in ("stage_type", "stage_level"):
+        r[k] = np.asarray(r[k], dtype=np.int32)
+    for k in ("stage_beta", "stage_zeta", "stage_acc_rate", "theta_mean", "theta_var"):
+        r[k] = np.asarray(r[k], dtype=np.float64)
+    return r

@@ -9,7 +9,7 @@ import torch
 import oracle
 import paper_1709_09763_amd as P
 from tests import inputs
-from tests.gpu_util import case, device, host, rel_err, to_dev
+from tests.gpu_util import case, device, host, rel_err, stored_oracle_run, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -84,16 +84,18 @@ def test_run_batch_matches_oracle_at_configured_sizes():
     c = P.Context(3, 7, K, 1.0, 0.3, m, sn)
     inst = []
     for J, lmax, seed in specs:
+        data = dict(theta_seed=800 + seed, noise_seed=900 + seed, l=lmax, K=K, m=m, sigma_n=sn)
+        run = dict(l_min=3, l_max=lmax, K=K, m=m, sigma_n=sn, J=J, J_tilde=100, seed=seed, n_mcmc=5, s_pcn=0.5)
         th_true = inputs.theta_batch(800 + seed, 1, K)
         y = oracle.forward(lmax, K, 1.0, 0.3, m, th_true)[0] + sn * inputs.rng(900 + seed).standard_normal(m * m)
-        inst.append(dict(J=J, l_max=lmax, y=to_dev(y), seed=seed, y_host=y))
+        inst.append(dict(J=J, l_max=lmax, y=to_dev(y), seed=seed, name=f"batch_J{J}_l{lmax}_s{seed}", data=data,
+                         run=run))
     case("run_batch K=100 Nobs=49 J 256..512, l_max 6/7")
     out = c.run_batch([dict(J=d["J"], l_max=d["l_max"], y=d["y"], seed=d["seed"]) for d in inst],
                       use_graphs=True)
     for d, o in zip(inst, out):
-        case(f"oracle run J={d['J']} l_max={d['l_max']} seed={d['seed']}")
-        r = oracle.run_sampler(d["y_host"], l_min=3, l_max=d["l_max"], K=K, m=m, sigma_n=sn, J=d["J"],
-                               J_tilde=100, seed=d["seed"], n_mcmc=5, s_pcn=0.5)
+        case(f"stored oracle run J={d['J']} l_max={d['l_max']} seed={d['seed']}")
+        r = stored_oracle_run(d["name"], d["data"], d["run"])
         print(f"  stages {o['n_stages']} / {r['n_stages']}, solves {o['solves'][3:8]} / {r['solves'][3:8]}")
         assert o["n_stages"] == r["n_stages"]
         assert o["final_level"] == r["final_level"] == d["l_max"] and o["final_beta"] == r["final_beta"]
@@ -105,6 +107,6 @@ def test_run_batch_matches_oracle_at_configured_sizes():
         assert o["accepted"] == r["accepted"]
         assert abs(o["log_Z"] - r["log_Z"]) < 1e-7 * max(1, abs(r["log_Z"]))
         th = host(o["theta"])
-        assert rel_err(th.mean(0), r["theta"].mean(0)) < 1e-8
-        assert rel_err(th.var(0), r["theta"].var(0)) < 1e-8
+        assert rel_err(th.mean(0), r["theta_mean"]) < 1e-8
+        assert rel_err(th.var(0), r["theta_var"]) < 1e-8
         assert o["not_converged"] == 0

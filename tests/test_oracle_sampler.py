@@ -317,3 +317,19 @@ def test_flowcell_brute_force_posterior_k1():
     se = ms.std(ddof=1) / np.sqrt(R)
     assert abs(ms.mean() - mq) < 4 * se + 0.02 * np.sqrt(vq), (ms.mean(), mq, se)
     assert abs(np.mean(vs) / vq - 1) < 0.15, (np.mean(vs), vq)
+
+
+def test_stored_oracle_runs_are_the_oracles():
+    """tests/golden/oracle_runs.json holds what its generator's cases give:
+    the same cases, and for the cheapest one the same result as a fresh
+    oracle run, value for value."""
+    import json
+    import os
+    from tests.golden import make_oracle_runs as mk
+    rec = json.load(open(mk.OUT))
+    assert set(rec) == set(mk.CASES)
+    for name, c in mk.CASES.items():
+        assert rec[name]["case"] == json.loads(json.dumps(c))
+    fresh = json.loads(json.dumps(mk.run_case(mk.CASES["batch_J384_l6_s0"])))
+    assert fresh == rec["batch_J384_l6_s0"]["result"]
+    assert os.path.basename(mk.OUT) == "oracle_runs.json"
