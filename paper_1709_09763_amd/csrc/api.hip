@@ -58,6 +58,12 @@ __global__ void chunk_count_kernel(const int64_t* __restrict__ total, int64_t q0
 
 // theta -> KL field -> solve, in chunks that bound the field buffer to 2 GiB.
 // N_dev (optional, device): only the first min(N, *N_dev) rows are solved.
+// The coefficients go through a buffer of at most 8 GiB, so an h = 1/512
+// batch runs in launches of 2048 (FP64) or 4096 (mixed) particles: enough
+// per launch that the solver's dynamic hand-out of particles evens out
+// their differing iteration counts.
+constexpr size_t kCoefChunkBytes = 8ull << 30;
+
 int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
                   int8_t* status, int32_t* iters, const double* y, double* phi, hipStream_t s,
                   const int64_t* N_dev)
@@ -67,7 +73,7 @@ int forward_theta(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double
     const bool mixed = ctx->prob.precision == MLS2MC_MIXED;
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
     const int64_t ne = n_elem(l);
-    int64_t chunk = (int64_t)((2ull << 30) / (ne * esz));
+    int64_t chunk = (int64_t)(kCoefChunkBytes / (ne * esz));
     if (chunk < 1) chunk = 1;
     if (chunk > N) chunk = N;
     MLS_TRY(ctx->ws_kappa.ensure((size_t)chunk * ne * esz));
@@ -220,6 +226,7 @@ int mls2mc_destroy(mls2mc_ctx* ctx)
     if (ctx->h_list_ev) (void)hipEventDestroy(ctx->h_list_ev);
     surrogate_destroy(ctx);
     if (ctx->d_chunk_count) (void)hipFree(ctx->d_chunk_count);
+    if (ctx->d_queue) (void)hipFree(ctx->d_queue);
     if (ctx->d_lin_A) (void)hipFree(ctx->d_lin_A);
     prof_clear(ctx);
     if (ctx->d_prof_iters) (void)hipFree(ctx->d_prof_iters);
@@ -274,6 +281,14 @@ int mls2mc_create(const mls2mc_problem* p, mls2mc_ctx** out)
     ctx->max_iters = p->max_iters > 0 ? p->max_iters : 200;
     int rc = build_kl_tables(ctx);
     if (rc == MLS2MC_OK) rc = build_obs_tables(ctx);
+    if (rc == MLS2MC_OK) {  // the solver's work counter starts at zero and resets itself after each launch
+        if (hipMalloc(&ctx->d_queue, 2 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMemset(ctx->d_queue, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess) {
+            set_error("create: device allocation failed");
+            rc = MLS2MC_ENOMEM;
+        }
+    }
     if (rc != MLS2MC_OK) {
         std::string msg = g_last_error;
         mls2mc_destroy(ctx);

@@ -130,6 +130,7 @@ struct mls2mc_ctx {
     size_t h_list_bytes = 0;
     hipEvent_t h_list_ev = nullptr;   // last copy out of h_list
     int64_t* d_chunk_count = nullptr; // per-chunk device counts
+    unsigned long long* d_queue = nullptr;  // the solver's particle counter and finished-workgroup count
     double* d_lin_A = nullptr;        // linear test model (N_obs x K each), or null
     double* d_lin_E = nullptr;
     double* da_err = nullptr;         // while mls2mc_run runs with the surrogate: accumulator of the

@@ -767,7 +767,10 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
             const T za = Z(jr, ca), zbb = Z(jr, ca + 1);
             if (ca > 0) xn_[jr * s + ca] = za;
             xn_[jr * s + ca + 1] = zbb;
-            if (want_dot) dot += (double)b1[0] * (double)za + (double)b1[1] * (double)zbb;
+            // column 0 is the boundary: its right-hand side entry is never
+            // written and may hold a stale word of another level's layout
+            // (any bit pattern, NaN included), so it stays out of the dot
+            if (want_dot) dot += (ca > 0 ? (double)b1[0] * (double)za : 0.0) + (double)b1[1] * (double)zbb;
         }
         lds_barrier();  // the walk reads no global value another thread writes
     };
@@ -1297,6 +1300,7 @@ struct SolveParams {
     int64_t lds_elems;  // LDS budget in elements of the working type
     int cinv_lds;       // FP64: the coarse inverse follows the budget in LDS (else in the slot)
     int64_t ring_off;   // element offset of the row walks' LDS rows, or -1 (no walks)
+    unsigned long long* queue;  // [0]: particles handed out, [1]: workgroups done; zero between launches
     Common C;
 };
 
@@ -1318,7 +1322,19 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P
     const int64_t ne = int64_t(2) << (2 * l);
     const int64_t M = ((int64_t(1) << l) - 1) * ((int64_t(1) << l) - 1);
     const int64_t NN = P.N_dev ? min(P.N, *P.N_dev) : P.N;
-    for (int64_t q = blockIdx.x; q < NN; q += gridDim.x) {
+    // Particles are handed out one at a time from a counter in device
+    // memory, so a workgroup that drew quick solves takes more of them and
+    // the launch ends with the last particle, not with the unluckiest
+    // workgroup's share.  The draw is broadcast through the reduction
+    // array, which is free between particles.
+    auto draw = [&]() -> int64_t {
+        if (threadIdx.x == 0) *(int64_t*)red = (int64_t)atomicAdd(P.queue, 1ull);
+        __syncthreads();
+        const int64_t v = *(const int64_t*)red;
+        __syncthreads();
+        return v;
+    };
+    for (int64_t q = draw(); q < NN; q = draw()) {
         Job J;
         J.l = l;
         J.kap = MIXED ? (const void*)((const float*)P.kappa + q * ne) : (const void*)((const double*)P.kappa + q * ne);
@@ -1339,6 +1355,15 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
             double* ring = (WK == 2 && P.ring_off >= 0) ? (double*)mls_lds + P.ring_off : nullptr;
             solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C, red);
+        }
+    }
+    // every workgroup has drawn past the end; the last one to finish resets
+    // the counter for the next launch on this context
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(P.queue + 1, 1ull) == (unsigned long long)(gridDim.x - 1)) {
+            atomicExch(P.queue, 0ull);
+            atomicExch(P.queue + 1, 0ull);
         }
     }
 }
@@ -1500,6 +1525,7 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     P.l = l; P.N = a.N; P.N_dev = a.N_dev; P.kappa = a.kappa; P.ws = ctx->ws_solver.ptr; P.slot_elems = slot;
     P.G = a.G; P.p_out = a.p_out; P.status = a.status; P.iters = a.iters; P.y = a.y; P.phi = a.phi;
     P.obs_idx = ctx->obs[l].idx; P.obs_w = ctx->obs[l].w;
+    P.queue = ctx->d_queue;
     P.C = make_common(ctx, l);
     const bool fused = launch_walks(l, bs, P.C.nu);
     const size_t lds = lds_bytes_for(ctx, l, mixed, bs, fused, &P.lds_elems, &P.cinv_lds, &P.ring_off);

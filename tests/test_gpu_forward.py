@@ -151,14 +151,18 @@ def test_mixed_forward_field_parity():
         assert e < 1e-6
 
 
-def test_mixed_bf16_field_error_bound():
+@pytest.mark.parametrize("l,K,N", [(5, 100, 130), (3, 10, 1), (7, 200, 77), (2, 33, 64)])
+def test_mixed_bf16_field_error_bound(l, K, N):
     """BF16 KL GEMM with FP32 accumulation: |a_bf16 - a| is bounded by the
-    rounding of theta and B to 8-bit mantissas (2^-8 relative each)."""
+    rounding of theta and B to 8-bit mantissas (2^-8 relative each).  The
+    cases cover K padded to 32 and 224, ragged row tiles (N = 1, 77, 130) and
+    a level with fewer elements than one column tile (h = 1/4: 32).  Each
+    output element depends only on its row of theta, so the rows of a
+    sub-batch are bitwise those of the whole batch."""
     device()
-    l, K = 5, 100
-    case(f"bf16 kl_field l={l} K={K}")
+    case(f"bf16 kl_field l={l} K={K} N={N}")
     ctx = P.Context(l, l, K, 1.0, 0.3, 3, 0.01, precision=P.MIXED)
-    th = inputs.theta_batch(9, 130, K)
+    th = inputs.theta_batch(9, N, K)
     kap32 = host(ctx.kl_field(l, to_dev(th), P.FIELD_KAPPA_F32)).astype(np.float64)
     B = oracle.kl_basis(l, K, 1.0, 0.3)
     a = th @ B
@@ -166,6 +170,8 @@ def test_mixed_bf16_field_error_bound():
     err = np.abs(np.log(kap32) - a)
     assert np.all(err <= bound)
     print(f"  max |a_bf16 - a| = {err.max():.3e}")
+    sub = host(ctx.kl_field(l, to_dev(th[N // 2:]), P.FIELD_KAPPA_F32)).astype(np.float64)
+    np.testing.assert_array_equal(sub, kap32[N // 2:])
 
 
 @pytest.mark.parametrize("l,N", [(3, 64), (5, 64), (6, 32), (7, 16), (8, 8)])
@@ -283,3 +289,36 @@ def test_column_walk_instances_parity(l, N):
             assert rel_err(host(G)[idx], Gr) < tol
             assert rel_err(host(G), host(G_rl)) < tol_rl
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", [P.MIXED, P.FP64])
+def test_walked_levels_after_smaller_levels_in_one_context(prec):
+    """The solver's workspace is shared by the levels of a context, so a
+    solve on h = 1/256 or 1/512 finds the words that smaller levels' solves
+    left in it, FP64 words among them in the mixed form.  Boundary entries
+    that the walks never write must not reach the results: after solves on
+    h = 1/128 and 1/256 in the same context, every particle converges and G
+    equals, bit for bit, that of a fresh context for the same level."""
+    device()
+    K, m = 200, 10
+    th = to_dev(inputs.theta_batch(77, 4096, K))
+    shape = (256, 1024, 1, -1)
+    case(f"walked levels after smaller ones, precision={prec}")
+    ctx = P.Context(7, 9, K, 1.0, 0.1, m, 0.001, precision=prec)
+    for lv in (7, 8, 9):
+        ctx.set_launch(lv, *shape)
+    outs = {}
+    for lv, N in ((7, 4096), (8, 4096), (9, 2048)):
+        G, st, it = ctx.forward(lv, th[:N].contiguous(), with_stats=True)
+        bad = int((host(st) != 0).sum())
+        print(f"  h=1/{1 << lv}: {bad} of {N} not converged")
+        assert bad == 0
+        outs[lv] = host(G)
+    for lv, N in ((8, 4096), (9, 2048)):
+        fresh = P.Context(lv, lv, K, 1.0, 0.1, m, 0.001, precision=prec)
+        fresh.set_launch(lv, *shape)
+        G, st, it = fresh.forward(lv, th[:N].contiguous(), with_stats=True)
+        assert (host(st) == 0).all()
+        np.testing.assert_array_equal(outs[lv], host(G))
+        fresh.close()
+    ctx.close()
