@@ -740,6 +740,50 @@ def leg_levels(args):
         "config": {"workload": "h=1/8..1/512, K=100, corr 0.3, Nobs=49, N in {1024, 8192}"}, **res}))
 
 
+def leg_kl(args):
+    """The KL field kernels alone (a = theta B_l with the exp epilogue) at the
+    configured shapes: FP64 MFMA and BF16 MFMA (FP32 accumulation), N rows,
+    timed with HIP events on the stream they run on, 5 launches each"""
+    import numpy as np
+    import torch
+
+    import paper_1709_09763_amd as P
+    dev = torch.device("cuda:0")
+    res = {}
+    for l, K, corr, N in ((9, 200, 0.1, 2048), (8, 100, 0.3, 4096), (6, 50, 0.3, 1000)):
+        ne = 2 * 4 ** l
+        th = torch.tensor(np.random.default_rng(l).standard_normal((N, K)), device=dev)
+        for form, prec, kind in (("fp64", P.FP64, P.FIELD_KAPPA_F64), ("bf16", P.MIXED, P.FIELD_KAPPA_F32)):
+            c = P.Context(l, l, K, 1.0, corr, 7, 0.01, precision=prec)
+            out = torch.empty((N, ne), dtype=torch.float64 if form == "fp64" else torch.float32, device=dev)
+            P.mls2mc_kl_field(c.h, l, th, out, kind)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record()
+            for _ in range(reps):
+                P.mls2mc_kl_field(c.h, l, th, out, kind)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            flops = 2.0 * N * K * ne
+            Kp = (K + 31) // 32 * 32
+            # algorithmic bytes: theta read, basis read once, kappa written
+            byts = 8.0 * N * K + (8.0 * K * ne + 8.0 * N * ne if form == "fp64" else 2.0 * Kp * ne + 4.0 * N * ne)
+            res[f"{form}_h=1/{1 << l}_K{K}_N{N}"] = dict(
+                ms=round(ms, 3), tflops=round(flops / ms / 1e9, 1), algorithmic_GBs=round(byts / ms / 1e6, 1),
+                write_GBs=round((8.0 if form == "fp64" else 4.0) * N * ne / ms / 1e6, 1))
+            log(f"kl {form} h=1/{1 << l} K={K} N={N}: {ms:.3f} ms, {flops / ms / 1e9:.1f} TFLOP/s, "
+                f"{byts / ms / 1e6:.0f} GB/s")
+            del out
+            c.close()
+    print(json.dumps({
+        "metric": "KL field TFLOP/s", "value": res["bf16_h=1/512_K200_N2048"]["tflops"], "unit": "TFLOP/s",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64 / bf16 (f32 acc.)",
+        "data": "synthetic", "config": {"workload": "KL field h=1/512 K=200, h=1/256 K=100, h=1/64 K=50"},
+        **res}))
+
+
 def leg_batched(args):
     """32 instances, seeds 0..31, J ~ U{256..4096}, finest h in {1/64, 1/128,
     1/256}, K=100, 49 obs, sigma_n=0.002: fused rounds with HIP graphs"""
@@ -951,7 +995,7 @@ def main():
     ap.add_argument("--save-tuned", default=None, help="write the tuned launch shapes to this JSON")
     ap.add_argument("--workload", default="largest-stage",
                     choices=["largest-stage", "stages-h64", "fast", "batched", "largest", "largest-run", "compare",
-                             "levels", "matern", "equal-error"],
+                             "levels", "matern", "equal-error", "kl"],
                     help="largest-stage: the default benchmark; others: the extra workloads")
     ap.add_argument("--quick-cpu", action="store_true", help="skip the single-core oracle solve at h=1/512")
     ap.add_argument("--seeds", type=int, default=1, help="fast / equal-error: independent runs per form (and N)")
@@ -979,7 +1023,7 @@ def main():
     if args.workload != "stages-h64":
         {"largest-stage": leg_largest_stage, "fast": leg_fast, "batched": leg_batched, "largest": leg_largest,
          "largest-run": leg_largest_run, "compare": leg_compare, "levels": leg_levels,
-         "matern": leg_matern, "equal-error": leg_equal_error}[args.workload](args)
+         "matern": leg_matern, "equal-error": leg_equal_error, "kl": leg_kl}[args.workload](args)
         return
     dev = torch.device("cuda:0")
     W = WL

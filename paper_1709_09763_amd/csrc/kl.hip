@@ -339,6 +339,97 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ t
     gemm_bf16_tile(theta, Bt, out, N, K, Kp, ne, blockIdx.x, blockIdx.y, sm);
 }
 
+// The single-batch BF16 field.  theta is rounded to BF16 once, into an
+// N x Kp array (K padded to 32 with zeros).  Each workgroup owns one
+// 64-element column tile: it stages that tile of the transposed basis in
+// LDS once, and each of its four waves walks its own 16-row slabs of theta
+// (slabs w, w + 4, ...), loading a slab's operands straight from the BF16
+// copy (under half a MiB at K = 200 and N = 1024, so it is read from the
+// L2).  The basis fragments do not change from slab to slab, so the
+// compiler keeps them in registers across the loop.  The basis is read
+// from HBM once per launch instead of once per row tile, no barrier sits in
+// the row loop, and the kernel is bound by writing kappa.  The MFMA lanes,
+// the k order and the rounding are those of gemm_bf16_tile, so the results
+// are bitwise the same.  NKS = Kp / 32 is a template constant so that a
+// slab's operands are whole register arrays.
+__global__ void theta_bf16_kernel(const double* __restrict__ theta, __bf16* __restrict__ t16, int64_t N, int K,
+                                  int Kp)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N * Kp) return;
+    const int64_t q = t / Kp;
+    const int k = (int)(t - q * Kp);
+    t16[t] = (__bf16)(k < K ? (float)theta[q * K + k] : 0.f);
+}
+
+constexpr int kColsMaxKs = 8;  // Kp <= 256
+
+template <int NKS>
+__global__ __launch_bounds__(256) void kl_gemm_bf16_cols(const __bf16* __restrict__ t16,
+                                                         const __hip_bfloat16* __restrict__ Bt,
+                                                         float* __restrict__ out, int64_t N, int64_t ne,
+                                                         const int64_t* __restrict__ N_dev)
+{
+    constexpr int Kp = 32 * NKS;
+    constexpr int ld = Kp + 8;  // row padding against bank conflicts
+    __shared__ __align__(16) __bf16 sb[64 * ld];  // 64 basis columns x Kp
+    if (N_dev) N = min(N, *N_dev);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int r = lane & 15, kq = lane >> 4;
+    const int64_t e0 = (int64_t)blockIdx.x * 64;
+    constexpr int vk = Kp / 8;  // 16-byte vectors per row
+    for (int idx = tid; idx < 64 * vk; idx += 256) {
+        const int col = idx / vk, part = idx - col * vk;
+        bf16x8 v;
+        if (e0 + col < ne) {
+            v = *reinterpret_cast<const bf16x8*>(Bt + (e0 + col) * Kp + 8 * part);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = (__bf16)0.f;
+        }
+        *reinterpret_cast<bf16x8*>(sb + col * ld + 8 * part) = v;
+    }
+    __syncthreads();
+    const int64_t nslab = (N + 15) / 16;
+    auto load = [&](int64_t sl, bf16x8* a) {
+        const int64_t row = sl * 16 + r;
+        if (row < N) {
+            const bf16x8* src = reinterpret_cast<const bf16x8*>(t16 + row * Kp + 8 * kq);
+#pragma unroll
+            for (int q = 0; q < NKS; ++q) a[q] = src[4 * q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NKS; ++q)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[q][u] = (__bf16)0.f;
+        }
+    };
+    for (int64_t sl = wv; sl < nslab; sl += 4) {
+        bf16x8 a[NKS];
+        load(sl, a);
+        flt4 acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < NKS; ++q) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(sb + (c * 16 + r) * ld + 32 * q + 8 * kq);
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q], b, acc[c], 0, 0, 0);
+            }
+        }
+        const int64_t p0 = sl * 16;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = p0 + 4 * kq + v, col = e0 + c * 16 + r;
+                if (row < N && col < ne) out[row * ne + col] = expf(acc[c][v]);
+            }
+    }
+}
+
 // Grouped launch: one 1-D grid over the 64x64 tiles of several items (each
 // its own theta, level basis and output).
 __global__ __launch_bounds__(256) void kl_gemm_list(const GemmItem* __restrict__ items, int n_items, int K,
@@ -389,7 +480,27 @@ int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void
     } else if (kind == MLS2MC_FIELD_KAPPA_F32) {
         MLS_REQUIRE(ctx->d_B16[l] != nullptr, "kl_field: BF16 basis needs precision MIXED");
         const int Kp = (K + 31) / 32 * 32;
-        kl_gemm_bf16<<<grid, 256, 0, s>>>(theta, ctx->d_B16[l], (float*)out, N, K, Kp, ne, N_dev);
+        if (Kp <= 32 * kColsMaxKs) {  // theta in BF16 once, then one workgroup per column tile
+            MLS_TRY(ctx->ws_theta16.ensure(sizeof(__bf16) * (size_t)N * Kp));
+            __bf16* t16 = ctx->ws_theta16.as<__bf16>();
+            theta_bf16_kernel<<<(unsigned)((N * Kp + 255) / 256), 256, 0, s>>>(theta, t16, N, K, Kp);
+            MLS_CHECK_HIP(hipGetLastError());
+            const unsigned g = (unsigned)((ne + 63) / 64);
+            float* o = (float*)out;
+            const __hip_bfloat16* B16 = ctx->d_B16[l];
+            switch (Kp / 32) {
+            case 1: kl_gemm_bf16_cols<1><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            case 2: kl_gemm_bf16_cols<2><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            case 3: kl_gemm_bf16_cols<3><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            case 4: kl_gemm_bf16_cols<4><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            case 5: kl_gemm_bf16_cols<5><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            case 6: kl_gemm_bf16_cols<6><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            case 7: kl_gemm_bf16_cols<7><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            default: kl_gemm_bf16_cols<8><<<g, 256, 0, s>>>(t16, B16, o, N, ne, N_dev); break;
+            }
+        } else {
+            kl_gemm_bf16<<<grid, 256, 0, s>>>(theta, ctx->d_B16[l], (float*)out, N, K, Kp, ne, N_dev);
+        }
     } else {
         MLS_REQUIRE(false, "kl_field: unknown output kind");
     }
