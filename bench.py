@@ -87,15 +87,31 @@ def measured_traffic(summary, shape, form="fp64"):
         return None
 
 
+def device_key():
+    """the GPU's architecture and compute-unit count (its marketing name can
+    differ between runs, e.g. under a profiler)"""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    return f"{pr.gcnArchName.split(':')[0]}:{pr.multi_processor_count}cu"
+
+
+def tuned_matches(rec):
+    """a tuned-shape record applies when it was made on this kind of device
+    for this solver source"""
+    import torch
+    same_dev = (rec.get("device_key") == device_key() if "device_key" in rec
+                else rec.get("device") == torch.cuda.get_device_name(0))
+    return same_dev and rec.get("solver_source_sha256_16") == solver_sha()
+
+
 def load_tuned(path, ctxs):
     """apply committed launch shapes {form: {level: shape}} when they were
     tuned on this device for this solver source; returns the path or None"""
-    import torch
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("device") != torch.cuda.get_device_name(0) or rec.get("solver_source_sha256_16") != solver_sha():
+    if not tuned_matches(rec):
         return None
     for form, c in ctxs.items():
         for lv, sh in rec.get(form, {}).items():
@@ -270,7 +286,7 @@ def leg_largest_stage(args):
                 tuned[name][str(lv)] = dict(grid=g, block=b, nu=nu, lds=lds)
                 log(f"autotuned {name} h=1/{1 << lv}: {tuned[name][str(lv)]} {ms:.3f} ms")
         if args.save_tuned:
-            json.dump({"device": torch.cuda.get_device_name(0), "workload": W["name"],
+            json.dump({"device": torch.cuda.get_device_name(0), "device_key": device_key(), "workload": W["name"],
                        "solver_source_sha256_16": solver_sha(), **tuned}, open(args.save_tuned, "w"), indent=1)
         extras["solver_launch_source"] = "autotuned in this run on 512 prior draws per level"
     else:
@@ -1040,7 +1056,7 @@ def main():
     tuned_file = args.tuned
     if tuned_file is None and not args.retune and not args.no_autotune and os.path.exists(TUNED_H64):
         rec = json.load(open(TUNED_H64))
-        if rec.get("device") == torch.cuda.get_device_name(0) and rec.get("solver_source_sha256_16") == solver_sha():
+        if tuned_matches(rec):
             tuned_file = TUNED_H64  # the committed shapes were tuned on this device for this solver
     ctxm = P.Context(W["l_min"], W["l_max"], K, 1.0, W["corr"], m, W["sigma_n"], precision=P.MIXED)
     if tuned_file:
@@ -1064,7 +1080,7 @@ def main():
         extras["autotuned_solver_launch"] = tuned
         log(f"autotuned {tuned}")
         if args.save_tuned:
-            json.dump({"device": torch.cuda.get_device_name(0), "workload": W["name"],
+            json.dump({"device": torch.cuda.get_device_name(0), "device_key": device_key(), "workload": W["name"],
                        "solver_source_sha256_16": solver_sha(),
                        "fp64": {str(k): v for k, v in shapes.items()},
                        "mixed": {str(k): v for k, v in shapes_m.items()}}, open(args.save_tuned, "w"), indent=1)
