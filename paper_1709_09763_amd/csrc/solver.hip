@@ -370,8 +370,10 @@ __device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* _
         const T pp = pn(c + s), wyc = F.wy[c];
         const T v = (F.wx[c - 1] + F.wx[c] + wym + wyc) * p0
                   - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + wym * pm + wyc * pp);
-        Pn[c] = p0;
-        Q[c] = v;
+        // p and q are read again only in later passes: streaming stores
+        // keep them from pushing the rows the walks reuse out of the L2
+        __builtin_nontemporal_store(p0, &Pn[c]);
+        __builtin_nontemporal_store(v, &Q[c]);
         if (X) X[c] += xa * Po[c];
         pq += (double)p0 * (double)v;
         pm = p0;
@@ -621,9 +623,48 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
     const gmem<const T> gPn = (gmem<const T>)Pn;
     const gmem<T> gCb = (gmem<T>)C.b;
     T r0[2] = {T(0), T(0)}, r1[2] = {T(0), T(0)}, r2[2] = {T(0), T(0)};  // updated residual, rows j .. j-2
+    // On the FP64 solver's finest level (FP32 weights) the weights of the
+    // thread's columns are read from global memory once per row and carried
+    // through the three steps that use them: wx of columns ca-1 .. ca+1 for
+    // rows j .. j-2, wy of columns ca, ca+1 for rows j .. j-3.  Read again
+    // from memory, those rows fall out of the L2 when every CU of an XCD
+    // walks its own particle.  Elsewhere the registers are dearer than the
+    // re-reads, and the weights are read where they are used.
+    constexpr bool win = sizeof(W) < sizeof(T);
+    W x0[3], x1[3], x2[3], y0[2], y1[2], y2[2], y3[2];
+    // wx of row j - r, column ca - 1 + u; wy of row j - r, column ca + u
+    auto WX = [&](int j, int r, int u) -> T {
+        if constexpr (win) return T(r == 0 ? x0[u] : r == 1 ? x1[u] : x2[u]);
+        else return T(wx[(j - r) * s + ca - 1 + u]);
+    };
+    auto WY = [&](int j, int r, int u) -> T {
+        if constexpr (win) return T(r == 0 ? y0[u] : r == 1 ? y1[u] : r == 2 ? y2[u] : y3[u]);
+        else return T(wy[(j - r) * s + ca + u]);
+    };
+    auto load_w = [&](int jj, W* xr, W* yr) {
+        const bool in = jj >= 0 && jj <= n - 1;
+        const int c = jj * s + ca;
+        xr[0] = in && ca > 0 ? wx[c - 1] : W(0);
+        xr[1] = in ? wx[c] : W(0);
+        xr[2] = in ? wx[c + 1] : W(0);
+        yr[0] = in ? wy[c] : W(0);
+        yr[1] = in ? wy[c + 1] : W(0);
+    };
+    if constexpr (win) {
+        load_w(j0 - 4, x0, y0);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) x1[u] = x2[u] = W(0);
+        y1[0] = y1[1] = y2[0] = y2[1] = y3[0] = y3[1] = W(0);
+    }
     auto body = [&](auto par, int j) {
         constexpr int k = decltype(par)::value;  // the active column: ca + k
         r2[0] = r1[0]; r2[1] = r1[1]; r1[0] = r0[0]; r1[1] = r0[1]; r0[0] = T(0); r0[1] = T(0);
+        if constexpr (win) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) { x2[u] = x1[u]; x1[u] = x0[u]; }
+            y3[0] = y2[0]; y3[1] = y2[1]; y2[0] = y1[0]; y2[1] = y1[1]; y1[0] = y0[0]; y1[1] = y0[1];
+            load_w(j, x0, y0);
+        }
         const bool active = ca + k > 0;  // column 0 is the boundary
         auto Z = [&](int jj, int i) -> T __attribute__((address_space(3)))& { return zr[(jj & 3) * s + i]; };
         if (j == n) {  // the top boundary row, read by the black sweep and the residuals below it
@@ -648,33 +689,30 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
                 r0[0] = gb[c];
                 r0[1] = gb[c + 1];
             }
-            if (active) {
-                const int q = c + k;
-                Z(j, ca + k) = r0[k] / (T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]));
-            }
+            if (active)
+                Z(j, ca + k) = r0[k] / (WX(j, 0, k) + WX(j, 0, k + 1) + WY(j, 1, k) + WY(j, 0, k));
         }
         // ---- row j-1: the black node (red neighbours final)
         const int jb = j - 1;
         if (jb >= 1 && jb <= n - 1 && jb >= j0 - 2 && jb <= j1 + 1) {
             const int i = ca + k;
             if (active) {
-                const int q = jb * s + i;
-                const T nb = T(wx[q - 1]) * Z(jb, i - 1) + T(wx[q]) * Z(jb, i + 1) + T(wy[q - s]) * Z(jb - 1, i)
-                           + T(wy[q]) * Z(j, i);
-                Z(jb, i) = (r1[k] + nb) / (T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]));
+                const T nb = WX(j, 1, k) * Z(jb, i - 1) + WX(j, 1, k + 1) * Z(jb, i + 1) + WY(j, 2, k) * Z(jb - 1, i)
+                           + WY(j, 1, k) * Z(j, i);
+                Z(jb, i) = (r1[k] + nb) / (WX(j, 1, k) + WX(j, 1, k + 1) + WY(j, 2, k) + WY(j, 1, k));
             }
-            if (jb >= j0 && jb < j1) {  // row j-1 is final: store both columns
-                if (ca > 0) gx[jb * s + ca] = Z(jb, ca);
-                gx[jb * s + ca + 1] = Z(jb, ca + 1);
+            if (jb >= j0 && jb < j1) {  // row j-1 is final: store both columns (streaming)
+                if (ca > 0) __builtin_nontemporal_store((T)Z(jb, ca), &gx[jb * s + ca]);
+                __builtin_nontemporal_store((T)Z(jb, ca + 1), &gx[jb * s + ca + 1]);
             }
         }
         // ---- row j-2: the red residual (black neighbours final)
         const int jc = j - 2;
         if (jc >= 1 && jc <= n - 1 && jc >= j0 - 1 && jc <= j1 && active) {
-            const int i = ca + k, q = jc * s + i;
-            const T d = T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]);
-            const T lnb = T(wx[q - 1]) * Z(jc, i - 1) + T(wx[q]) * Z(jc, i + 1) + T(wy[q - s]) * Z(jc - 1, i)
-                        + T(wy[q]) * Z(jc + 1, i);
+            const int i = ca + k;
+            const T d = WX(j, 2, k) + WX(j, 2, k + 1) + WY(j, 3, k) + WY(j, 2, k);
+            const T lnb = WX(j, 2, k) * Z(jc, i - 1) + WX(j, 2, k + 1) * Z(jc, i + 1) + WY(j, 3, k) * Z(jc - 1, i)
+                        + WY(j, 2, k) * Z(jc + 1, i);
             rr[(jc & 3) * (P + 1) + t] = r2[k] - (d * Z(jc, i) - lnb);
         }
         // ---- coarse row (j-4)/2: restriction of the red residuals
@@ -733,9 +771,57 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
     };
     T b0[2] = {T(0), T(0)}, b1[2] = {T(0), T(0)};  // right-hand side of rows j, j-1
     double dot = 0.0;
+    // As in walk_down, on the FP64 solver's finest level each row's weights
+    // of the thread's columns (wx of columns ca-1 .. ca+1 for rows j, j-1;
+    // wy of columns ca, ca+1 for rows j .. j-2) and the down walk's z of its
+    // own two columns (rows j-1 .. j+1) are read from global memory once and
+    // carried in registers.
+    constexpr bool win = sizeof(W) < sizeof(T);
+    W x0[3], x1[3], y0[2], y1[2], y2[2];
+    T zm[2], zc[2], zp[2];  // xo of columns ca, ca+1: rows j-1, j, j+1
+    auto WX = [&](int j, int r, int u) -> T {  // wx of row j - r, column ca - 1 + u
+        if constexpr (win) return T(r == 0 ? x0[u] : x1[u]);
+        else return T(wx[(j - r) * s + ca - 1 + u]);
+    };
+    auto WY = [&](int j, int r, int u) -> T {  // wy of row j - r, column ca + u
+        if constexpr (win) return T(r == 0 ? y0[u] : r == 1 ? y1[u] : y2[u]);
+        else return T(wy[(j - r) * s + ca + u]);
+    };
+    auto XO = [&](int j, int r, int u) -> T {  // xo of row j + r (r = -1, 0, 1), column ca + u
+        if constexpr (win) return r < 0 ? zm[u] : r == 0 ? zc[u] : zp[u];
+        else return xo_[(j + r) * s + ca + u];
+    };
+    auto load_w = [&](int jj, W* xr, W* yr) {
+        const bool in = jj >= 0 && jj <= n - 1;
+        const int c = jj * s + ca;
+        xr[0] = in && ca > 0 ? wx[c - 1] : W(0);
+        xr[1] = in ? wx[c] : W(0);
+        xr[2] = in ? wx[c + 1] : W(0);
+        yr[0] = in ? wy[c] : W(0);
+        yr[1] = in ? wy[c + 1] : W(0);
+    };
+    auto load_z = [&](int jj, T* zr_) {
+        const bool in = jj >= 0 && jj <= n;
+        zr_[0] = in ? xo_[jj * s + ca] : T(0);
+        zr_[1] = in ? xo_[jj * s + ca + 1] : T(0);
+    };
+    if constexpr (win) {
+        load_w(j0 - 2, x0, y0);
+        y1[0] = y1[1] = W(0);
+        load_z(j0 - 2, zc);
+        load_z(j0 - 1, zp);
+    }
     auto body = [&](auto par, int j) {
         constexpr int k = 1 - decltype(par)::value;  // the active column: ca + k
         b1[0] = b0[0]; b1[1] = b0[1]; b0[0] = T(0); b0[1] = T(0);
+        if constexpr (win) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) x1[u] = x0[u];
+            y2[0] = y1[0]; y2[1] = y1[1]; y1[0] = y0[0]; y1[1] = y0[1];
+            load_w(j, x0, y0);
+            zm[0] = zc[0]; zm[1] = zc[1]; zc[0] = zp[0]; zc[1] = zp[1];
+            load_z(j + 1, zp);
+        }
         auto Z = [&](int jj, int i) -> T __attribute__((address_space(3)))& { return zb[(jj & 3) * s + i]; };
         const int i = ca + k;
         if (j == n) {  // the top boundary row, read by the red sweep below it
@@ -749,24 +835,26 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
             b0[1] = gbv[c0 + 1];
             if (i > 0) {
                 const int c = c0 + k;
-                const T xe = xo_[c + 1];
-                const T nb = T(wx[c - 1]) * (xo_[c - 1] + pe(i - 1, j)) + T(wx[c]) * (xe + pe(i + 1, j))
-                           + T(wy[c - s]) * (xo_[c - s] + pe(i, j - 1)) + T(wy[c]) * (xo_[c + s] + pe(i, j + 1));
-                Z(j, i) = (b0[k] + nb) / (T(wx[c - 1]) + T(wx[c]) + T(wy[c - s]) + T(wy[c]));
+                // the horizontal neighbour outside the pair is the
+                // neighbouring thread's: read from memory (this row, cached)
+                const T xw = k == 0 ? xo_[c - 1] : XO(j, 0, 0);
+                const T xe = k == 0 ? XO(j, 0, 1) : xo_[c + 1];
+                const T nb = WX(j, 0, k) * (xw + pe(i - 1, j)) + WX(j, 0, k + 1) * (xe + pe(i + 1, j))
+                           + WY(j, 1, k) * (XO(j, -1, k) + pe(i, j - 1)) + WY(j, 0, k) * (XO(j, 1, k) + pe(i, j + 1));
+                Z(j, i) = (b0[k] + nb) / (WX(j, 0, k) + WX(j, 0, k + 1) + WY(j, 1, k) + WY(j, 0, k));
             }
         }
         // ---- row j-1: the red node (black neighbours new); the row is then final
         const int jr = j - 1;
         if (jr >= j0 && jr < j1) {
             if (i > 0) {
-                const int q = jr * s + i;
-                const T lnb = T(wx[q - 1]) * Z(jr, i - 1) + T(wx[q]) * Z(jr, i + 1) + T(wy[q - s]) * Z(jr - 1, i)
-                            + T(wy[q]) * Z(j, i);
-                Z(jr, i) = (b1[k] + lnb) / (T(wx[q - 1]) + T(wx[q]) + T(wy[q - s]) + T(wy[q]));
+                const T lnb = WX(j, 1, k) * Z(jr, i - 1) + WX(j, 1, k + 1) * Z(jr, i + 1) + WY(j, 2, k) * Z(jr - 1, i)
+                            + WY(j, 1, k) * Z(j, i);
+                Z(jr, i) = (b1[k] + lnb) / (WX(j, 1, k) + WX(j, 1, k + 1) + WY(j, 2, k) + WY(j, 1, k));
             }
             const T za = Z(jr, ca), zbb = Z(jr, ca + 1);
-            if (ca > 0) xn_[jr * s + ca] = za;
-            xn_[jr * s + ca + 1] = zbb;
+            if (ca > 0) __builtin_nontemporal_store(za, &xn_[jr * s + ca]);
+            __builtin_nontemporal_store(zbb, &xn_[jr * s + ca + 1]);
             // column 0 is the boundary: its right-hand side entry is never
             // written and may hold a stale word of another level's layout
             // (any bit pattern, NaN included), so it stays out of the dot
