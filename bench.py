@@ -649,6 +649,29 @@ def leg_equal_error(args):
     t_fast, extrap = interp_time_at(e_plain, errs, times)
     out["equal_error"] = dict(plain_error=e_plain, plain_seconds=t_plain, fast_seconds_at_plain_error=round(t_fast, 4),
                               extrapolated=extrap, speedup=round(t_plain / t_fast, 3))
+    # the same runs read per particle count: time ratio and the difference of
+    # the forms' mean errors with its standard error (a difference within two
+    # standard errors is not resolved by this many seeds)
+    by_size = {}
+    for N in sizes:
+        a, b = out["plain_fp64"][str(N)], out["mixed_surrogate"][str(N)]
+        row = dict(time_ratio_plain_over_fast=round(a["seconds_median"] / b["seconds_median"], 3))
+        for k in ("rel_err_ref", "rel_err_truth", "rel_misfit"):
+            row[k + "_fast_minus_plain"] = dict(diff=round(b[k]["mean"] - a[k]["mean"], 5),
+                                                se=round(float(np.hypot(a[k]["se"], b[k]["se"])), 5))
+        by_size[str(N)] = row
+    out["by_size"] = by_size
+    # and at equal time: the plain form's error interpolated (log-log along
+    # its N sweep) at the fast form's time for the largest N
+    e_pl = [out["plain_fp64"][str(N)]["rel_err_ref"]["mean"] for N in sizes]
+    t_pl = [out["plain_fp64"][str(N)]["seconds_median"] for N in sizes]
+    tf = out["mixed_surrogate"][Nmax]["seconds_median"]
+    lt, le = np.log(t_pl), np.log(e_pl)
+    order = np.argsort(lt)
+    e_at = float(np.exp(np.interp(np.log(tf), lt[order], le[order])))
+    out["equal_time"] = dict(fast_seconds=tf, fast_error=out["mixed_surrogate"][Nmax]["rel_err_ref"]["mean"],
+                             plain_error_at_that_time=round(e_at, 5),
+                             plain_time_range_covers=bool(lt.min() <= np.log(tf) <= lt.max()))
     log(f"equal error {out['equal_error']}")
     print(json.dumps({
         "metric": "MLS²MC time-to-posterior at equal posterior-mean error, plain FP64 vs surrogate+FP32",
