@@ -351,7 +351,7 @@ __device__ __forceinline__ int opaque(int c)
 // p = z + beta p_old formed on the fly at the node and its neighbours,
 // stored to Pn with q = A p; returns this thread's share of (p, q).  With X
 // the pass also applies the pending x += xa p_old at its nodes.
-template <int BS, typename T>
+template <int BS, bool NT, typename T>
 __device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* __restrict__ Po, T beta,
                              T* __restrict__ Pn, T* __restrict__ Q, T* __restrict__ X = nullptr, T xa = T(0))
 {
@@ -370,10 +370,17 @@ __device__ double walk_apply(const Lv<T>& F, const T* __restrict__ Z, const T* _
         const T pp = pn(c + s), wyc = F.wy[c];
         const T v = (F.wx[c - 1] + F.wx[c] + wym + wyc) * p0
                   - (F.wx[c - 1] * pn(c - 1) + F.wx[c] * pn(c + 1) + wym * pm + wyc * pp);
-        // p and q are read again only in later passes: streaming stores
-        // keep them from pushing the rows the walks reuse out of the L2
-        __builtin_nontemporal_store(p0, &Pn[c]);
-        __builtin_nontemporal_store(v, &Q[c]);
+        if constexpr (NT) {
+            // on the walked levels p and q are read again only in later
+            // passes: streaming stores keep them from pushing the rows the
+            // walks reuse out of the L2 (on smaller levels they stay in the
+            // caches until then, and plain stores are faster)
+            __builtin_nontemporal_store(p0, &Pn[c]);
+            __builtin_nontemporal_store(v, &Q[c]);
+        } else {
+            Pn[c] = p0;
+            Q[c] = v;
+        }
         if (X) X[c] += xa * Po[c];
         pq += (double)p0 * (double)v;
         pm = p0;
@@ -599,8 +606,8 @@ __device__ __forceinline__ void lds_barrier()
 // on row j every phase works on the thread's column of parity j: the red
 // node of row j, the black node of row j-1 and the red node of row j-2 all
 // sit in it.  The node values of the last four rows are kept in the LDS
-// ring (the thread's own ones too), the weights are read where needed (the
-// rows were read a step or two before, so these reads hit the caches).
+// ring (the thread's own ones too); the weights come from registers on the
+// FP64 solver's finest level and from memory elsewhere (see below).
 template <int BS, typename T, typename W>
 __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, const T* __restrict__ Q, T alpha,
                           T* __restrict__ x, T* __restrict__ X, const T* __restrict__ Pn, T* __restrict__ ring)
@@ -1188,7 +1195,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
         double* Xu = it > 0 ? X : nullptr;
         if (WK >= 1 && F.n >= 64 && BS % F.n == 0) {
-            pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q, Xu, xa);
+            pq = walk_apply<BS, WK == 2>(F, Z, Po, beta, Pn, Q, Xu, xa);
         } else {
             MLS_FOR_INTERIOR(F, {
                 if (Xu) Xu[c] += xa * Po[c];
@@ -1312,7 +1319,7 @@ __device__ void solve_one_mixed(const Map<float>& M, const Job& J, const Common&
         double pq = 0.0;
         auto pn = [&](int q) { return fmaf(beta, Po[q], Z[q]); };
         if (WK >= 1 && F.n >= 64 && BS % F.n == 0) {
-            pq = walk_apply<BS>(F, Z, Po, beta, Pn, Q);
+            pq = walk_apply<BS, WK == 2>(F, Z, Po, beta, Pn, Q);
         } else {
             MLS_FOR_INTERIOR(F, {
                 const float pc = pn(c);
