@@ -607,8 +607,8 @@ __device__ __forceinline__ void lds_barrier()
 // node of row j, the black node of row j-1 and the red node of row j-2 all
 // sit in it.  The node values of the last four rows are kept in the LDS
 // ring (the thread's own ones too); the weights come from registers on the
-// FP64 solver's finest level and from memory elsewhere (see below).
-template <int BS, typename T, typename W>
+// finest level and from memory on a walked coarse level (see below).
+template <int BS, bool FINE, typename T, typename W>
 __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, const T* __restrict__ Q, T alpha,
                           T* __restrict__ x, T* __restrict__ X, const T* __restrict__ Pn, T* __restrict__ ring)
 {
@@ -630,14 +630,15 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
     const gmem<const T> gPn = (gmem<const T>)Pn;
     const gmem<T> gCb = (gmem<T>)C.b;
     T r0[2] = {T(0), T(0)}, r1[2] = {T(0), T(0)}, r2[2] = {T(0), T(0)};  // updated residual, rows j .. j-2
-    // On the FP64 solver's finest level (FP32 weights) the weights of the
-    // thread's columns are read from global memory once per row and carried
-    // through the three steps that use them: wx of columns ca-1 .. ca+1 for
-    // rows j .. j-2, wy of columns ca, ca+1 for rows j .. j-3.  Read again
-    // from memory, those rows fall out of the L2 when every CU of an XCD
-    // walks its own particle.  Elsewhere the registers are dearer than the
+    // On the finest level (FINE; FP32 weights in both solvers) the weights
+    // of the thread's columns are read from global memory once per row and
+    // carried through the three steps that use them: wx of columns
+    // ca-1 .. ca+1 for rows j .. j-2, wy of columns ca, ca+1 for rows
+    // j .. j-3.  Read again from memory, those rows fall out of the L2 when
+    // every CU of an XCD walks its own particle.  On the walked coarse level
+    // (FP64 weights in the FP64 solver) the registers are dearer than the
     // re-reads, and the weights are read where they are used.
-    constexpr bool win = sizeof(W) < sizeof(T);
+    constexpr bool win = FINE;
     W x0[3], x1[3], x2[3], y0[2], y1[2], y2[2], y3[2];
     // wx of row j - r, column ca - 1 + u; wy of row j - r, column ca + u
     auto WX = [&](int j, int r, int u) -> T {
@@ -754,7 +755,7 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
 // interior nodes when want_dot.  In a step on row j both phases work on the
 // thread's column of parity j + 1: the black node of row j and the red node
 // of row j - 1.  New values pass through the LDS ring as in walk_down.
-template <int BS, typename T, typename W>
+template <int BS, bool FINE, typename T, typename W>
 __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, const T* __restrict__ b,
                           const T* __restrict__ xo, T* __restrict__ xn, bool want_dot, T* __restrict__ ring,
                           double* red)
@@ -778,12 +779,14 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
     };
     T b0[2] = {T(0), T(0)}, b1[2] = {T(0), T(0)};  // right-hand side of rows j, j-1
     double dot = 0.0;
-    // As in walk_down, on the FP64 solver's finest level each row's weights
-    // of the thread's columns (wx of columns ca-1 .. ca+1 for rows j, j-1;
-    // wy of columns ca, ca+1 for rows j .. j-2) and the down walk's z of its
-    // own two columns (rows j-1 .. j+1) are read from global memory once and
-    // carried in registers.
-    constexpr bool win = sizeof(W) < sizeof(T);
+    // As in walk_down, on the finest level each row's weights of the
+    // thread's columns (wx of columns ca-1 .. ca+1 for rows j, j-1; wy of
+    // columns ca, ca+1 for rows j .. j-2) are read from global memory once
+    // and carried in registers; in the FP64 solver so is the down walk's z
+    // of the thread's own two columns (rows j-1 .. j+1), which in the mixed
+    // solver would cost the kernel an occupancy step.
+    constexpr bool win = FINE;
+    constexpr bool zwin = FINE && sizeof(W) < sizeof(T);
     W x0[3], x1[3], y0[2], y1[2], y2[2];
     T zm[2], zc[2], zp[2];  // xo of columns ca, ca+1: rows j-1, j, j+1
     auto WX = [&](int j, int r, int u) -> T {  // wx of row j - r, column ca - 1 + u
@@ -795,7 +798,7 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
         else return T(wy[(j - r) * s + ca + u]);
     };
     auto XO = [&](int j, int r, int u) -> T {  // xo of row j + r (r = -1, 0, 1), column ca + u
-        if constexpr (win) return r < 0 ? zm[u] : r == 0 ? zc[u] : zp[u];
+        if constexpr (zwin) return r < 0 ? zm[u] : r == 0 ? zc[u] : zp[u];
         else return xo_[(j + r) * s + ca + u];
     };
     auto load_w = [&](int jj, W* xr, W* yr) {
@@ -815,8 +818,10 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
     if constexpr (win) {
         load_w(j0 - 2, x0, y0);
         y1[0] = y1[1] = W(0);
-        load_z(j0 - 2, zc);
-        load_z(j0 - 1, zp);
+        if constexpr (zwin) {
+            load_z(j0 - 2, zc);
+            load_z(j0 - 1, zp);
+        }
     }
     auto body = [&](auto par, int j) {
         constexpr int k = 1 - decltype(par)::value;  // the active column: ca + k
@@ -826,8 +831,10 @@ __device__ double walk_up(const Lv<T, W>& L, const T* __restrict__ e, int sc, co
             for (int u = 0; u < 3; ++u) x1[u] = x0[u];
             y2[0] = y1[0]; y2[1] = y1[1]; y1[0] = y0[0]; y1[1] = y0[1];
             load_w(j, x0, y0);
-            zm[0] = zc[0]; zm[1] = zc[1]; zc[0] = zp[0]; zc[1] = zp[1];
-            load_z(j + 1, zp);
+            if constexpr (zwin) {
+                zm[0] = zc[0]; zm[1] = zc[1]; zc[0] = zp[0]; zc[1] = zp[1];
+                load_z(j + 1, zp);
+            }
         }
         auto Z = [&](int jj, int i) -> T __attribute__((address_space(3)))& { return zb[(jj & 3) * s + i]; };
         const int i = ca + k;
@@ -1013,11 +1020,11 @@ __device__ double vcycle_walk(const Map<T>& M, const Lv<T, W>& F, T* rhs, const 
         if (walked(L)) V.x = V.kap;
         return V;
     };
-    walk_down<BS>(F, coarse_level(M, l - 1), rhs, Q, alpha, sol, X, Pn, M.ring);
+    walk_down<BS, true>(F, coarse_level(M, l - 1), rhs, Q, alpha, sol, X, Pn, M.ring);
     for (int Lk = l - 1; Lk > Lc; --Lk) {
         const Lv<T> L = coarse_level(M, Lk);
         if (walked(Lk))
-            walk_down<BS>(L, coarse_level(M, Lk - 1), L.b, (const T*)nullptr, T(0), L.x, (T*)nullptr,
+            walk_down<BS, false>(L, coarse_level(M, Lk - 1), L.b, (const T*)nullptr, T(0), L.x, (T*)nullptr,
                           (const T*)nullptr, M.ring);
         else
             down_step<BS>(L, coarse_level(M, Lk - 1), L.b, L.x, 1, false);
@@ -1037,11 +1044,11 @@ __device__ double vcycle_walk(const Map<T>& M, const Lv<T, W>& F, T* rhs, const 
     for (int Lk = Lc + 1; Lk <= l - 1; ++Lk) {
         const Lv<T> L = coarse_level(M, Lk);
         const Lv<T> Cc = result(Lk - 1);
-        if (walked(Lk)) walk_up<BS>(L, Cc.x, Cc.s, L.b, L.x, L.kap, false, M.ring, red);
+        if (walked(Lk)) walk_up<BS, false>(L, Cc.x, Cc.s, L.b, L.x, L.kap, false, M.ring, red);
         else up_step<BS>(L, Cc, L.b, L.x, 1, false, red);
     }
     const Lv<T> Cf = result(l - 1);
-    return walk_up<BS>(F, Cf.x, Cf.s, rhs, sol, zn, want_dot, M.ring, red);
+    return walk_up<BS, true>(F, Cf.x, Cf.s, rhs, sol, zn, want_dot, M.ring, red);
 }
 
 // ------------------------------------------------------- setup & obs --

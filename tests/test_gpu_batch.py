@@ -37,7 +37,9 @@ def test_forward_batch_equals_single_forwards(precision):
         assert rel_err(host(it["phi_out"]), host(c.loglik(Gs, y))) < 1e-10
     # and against the oracle on one item
     Gr = oracle.forward(7, K, 1.0, 0.3, m, host(refs[1][1]))
-    tol = 1e-10 if precision == P.FP64 else 5e-2  # mixed: BF16 field
+    # mixed: the BF16 field's error (1.8e-3 at most per level at K = 100 in the
+    # per-level tests; smaller with K = 20 terms)
+    tol = 1e-10 if precision == P.FP64 else 5e-3
     assert rel_err(host(items[1]["G_out"]), Gr) < tol
 
 
