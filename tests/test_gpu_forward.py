@@ -151,12 +151,14 @@ def test_mixed_forward_field_parity():
         assert e < 1e-6
 
 
-@pytest.mark.parametrize("l,K,N", [(5, 100, 130), (3, 10, 1), (7, 200, 77), (2, 33, 64)])
+@pytest.mark.parametrize("l,K,N", [(5, 100, 130), (3, 10, 1), (7, 200, 77), (2, 33, 64), (4, 256, 65), (3, 300, 70)])
 def test_mixed_bf16_field_error_bound(l, K, N):
     """BF16 KL GEMM with FP32 accumulation: |a_bf16 - a| is bounded by the
     rounding of theta and B to 8-bit mantissas (2^-8 relative each).  The
-    cases cover K padded to 32 and 224, ragged row tiles (N = 1, 77, 130) and
-    a level with fewer elements than one column tile (h = 1/4: 32).  Each
+    cases cover K padded to 32 ... 256 (the column-tile kernel's one to eight
+    32-wide k steps), K = 300 (beyond them: the 64 x 64 tile kernel), ragged
+    row tiles (N = 1, 65, 77, 130) and a level with fewer elements than one
+    column tile (h = 1/4: 32).  Each
     output element depends only on its row of theta, so the rows of a
     sub-batch are bitwise those of the whole batch."""
     device()
