@@ -312,6 +312,21 @@ int mls2mc_gather(mls2mc_ctx* ctx, int64_t N, int64_t ncols, const int32_t* anc,
  * EINVAL while it is set.  For testing the sampler; synchronous.         */
 int mls2mc_set_linear_model(mls2mc_ctx* ctx, const double* A, const double* E);
 
+/* Linear surrogate for the delayed-acceptance first stage (the two-stage
+ * Metropolis-Hastings screen of mls2mc_pcn_step_da): after this call the
+ * surrogate's prediction is G~(theta) = S theta in mls2mc_surrogate_predict,
+ * mls2mc_pcn_step_da and mls2mc_run, in place of the network, and no network
+ * is needed (mls2mc_surrogate_init may be skipped).  In mls2mc_run with
+ * surrogate on, the first stage then screens every pCN move from level
+ * sur_da_min_level on (which may equal l_min), with no collection of
+ * training pairs and no training.  S: host array of N_obs x K doubles
+ * (row-major), copied; NULL restores the network.  With a linear model
+ * (mls2mc_set_linear_model) the whole delayed-acceptance run is then fixed
+ * by the paper's definitions and the random streams, which the tests
+ * compare stage by stage with the oracle's sampler.  For testing;
+ * synchronous.                                                             */
+int mls2mc_set_linear_surrogate(mls2mc_ctx* ctx, const double* S);
+
 #define MLS2MC_KERNEL_PCN 0
 #define MLS2MC_KERNEL_RWM 1
 

@@ -20,5 +20,5 @@ from ._lib import (  # noqa: F401
     mls2mc_forward_batch, mls2mc_run_batch, mls2mc_kl_eigenvalues, KERNEL_PCN, KERNEL_RWM,
     SCHEME_MLB, SCHEME_MLS2MC, COV_MATERN32, COV_SEPEXP, BC_DIRICHLET, BC_FLOW_CELL,
     mls2mc_ctx_n_unknowns, mls2mc_decide, DECIDE_ITU, DECIDE_LU, DECIDE_DONE, DECIDE_NEED_CV,
-    mls2mc_cv_lu, mls2mc_set_linear_model, mls2mc_resample_noalloc,
+    mls2mc_cv_lu, mls2mc_set_linear_model, mls2mc_set_linear_surrogate, mls2mc_resample_noalloc,
 )

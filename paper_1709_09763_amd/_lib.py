@@ -114,6 +114,7 @@ def lib():
         L.mls2mc_resample_noalloc.argtypes = [C.c_int64, _vp, _vp, _vp, _vp]
         L.mls2mc_cv_lu.argtypes = [_vp, C.c_int64, _vp, C.c_double, _vp, _vp]
         L.mls2mc_set_linear_model.argtypes = [_vp, _dp, _dp]
+        L.mls2mc_set_linear_surrogate.argtypes = [_vp, _dp]
         L.mls2mc_gather.argtypes = [_vp, C.c_int64, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp]
         L.mls2mc_pcn_step.argtypes = [_vp, C.POINTER(Stage), C.c_int64, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp, _vp, _vp, _vp]
@@ -283,6 +284,18 @@ def mls2mc_cv_lu(h, d, scale, out2):
     N = d.shape[0]
     _check(lib().mls2mc_cv_lu(h, N, _ptr(d, torch.float64, (N,), "d"), scale,
                               _ptr(out2, torch.float64, (2,), "out2"), _stream()), "mls2mc_cv_lu")
+
+
+def mls2mc_set_linear_surrogate(h, S=None):
+    """S: host float64 array of N_obs x K (None: back to the network)"""
+    import numpy as np
+    if S is None:
+        _check(lib().mls2mc_set_linear_surrogate(h, None), "mls2mc_set_linear_surrogate")
+        return
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    if S.ndim != 2 or S.shape[0] != mls2mc_n_obs(h):
+        raise ValueError(f"S must be N_obs x K, got {S.shape}")
+    _check(lib().mls2mc_set_linear_surrogate(h, S.ctypes.data_as(_dp)), "mls2mc_set_linear_surrogate")
 
 
 def mls2mc_set_linear_model(h, A=None, E=None):
@@ -582,6 +595,12 @@ class Context:
         if A is not None and A.shape[1] != self.K:
             raise ValueError(f"A must have K = {self.K} columns")
         mls2mc_set_linear_model(self.h, A, E)
+
+    def set_linear_surrogate(self, S=None):
+        """the delayed-acceptance first stage uses G~ = S theta (None: back to the network)"""
+        if S is not None and S.shape[1] != self.K:
+            raise ValueError(f"S must have K = {self.K} columns")
+        mls2mc_set_linear_surrogate(self.h, S)
 
     def resample(self, w, u):
         anc = torch.empty(w.shape[0], dtype=torch.int32, device=w.device)

@@ -228,6 +228,7 @@ int mls2mc_destroy(mls2mc_ctx* ctx)
     if (ctx->d_chunk_count) (void)hipFree(ctx->d_chunk_count);
     if (ctx->d_queue) (void)hipFree(ctx->d_queue);
     if (ctx->d_lin_A) (void)hipFree(ctx->d_lin_A);
+    if (ctx->d_sur_S) (void)hipFree(ctx->d_sur_S);
     prof_clear(ctx);
     if (ctx->d_prof_iters) (void)hipFree(ctx->d_prof_iters);
     delete ctx;
@@ -408,6 +409,31 @@ int mls2mc_set_linear_model(mls2mc_ctx* ctx, const double* A, const double* E)
         ctx->d_lin_E = d + n;
     }
     return rc;
+}
+
+int mls2mc_set_linear_surrogate(mls2mc_ctx* ctx, const double* S)
+{
+    MLS_REQUIRE(ctx != nullptr, "null context");
+    MLS_CHECK_HIP(hipDeviceSynchronize());  // work in flight may still read the old table
+    if (ctx->d_sur_S) (void)hipFree(ctx->d_sur_S);
+    ctx->d_sur_S = nullptr;
+    if (!S) return MLS2MC_OK;
+    const size_t n = (size_t)ctx->nobs * ctx->prob.K;
+    for (size_t i = 0; i < n; ++i) MLS_REQUIRE(std::isfinite(S[i]), "set_linear_surrogate: non-finite entry");
+    double* d = nullptr;
+    if (hipMalloc(&d, n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("set_linear_surrogate: device allocation failed");
+        return MLS2MC_ENOMEM;
+    }
+    if (hipMemcpy(d, S, n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d);
+        set_error("set_linear_surrogate: copy to the device failed");
+        return MLS2MC_EDEVICE;
+    }
+    ctx->d_sur_S = d;
+    return MLS2MC_OK;
 }
 
 int mls2mc_resample(mls2mc_ctx* ctx, int64_t N, const double* w, const double* u, int32_t* anc_out,

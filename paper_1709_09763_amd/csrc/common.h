@@ -133,6 +133,7 @@ struct mls2mc_ctx {
     unsigned long long* d_queue = nullptr;  // the solver's particle counter and finished-workgroup count
     double* d_lin_A = nullptr;        // linear test model (N_obs x K each), or null
     double* d_lin_E = nullptr;
+    double* d_sur_S = nullptr;        // linear surrogate G~ = S theta (N_obs x K), or null: the network
     double* da_err = nullptr;         // while mls2mc_run runs with the surrogate: accumulator of the
                                       // surrogate's error against stage-2 solves {sum, max, count}
 };
@@ -234,6 +235,8 @@ int launch_pcn_accept(int64_t N, int K, int nobs, int mode, int rwm, double beta
 int launch_ess_cv(int64_t N, const double* dlo, const double* dhi, double scale, double* out,
                   hipStream_t s);
 int launch_reduce_i32(int64_t N, const int32_t* v, const int8_t* st, int64_t* out2,
+                      hipStream_t s);
+int launch_linear_map(int64_t N, int K, int nobs, const double* S, const double* theta, double* G,
                       hipStream_t s);
 int launch_linear_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, double* G,
                           int8_t* status, int32_t* iters, const double* y, double* phi,

@@ -107,7 +107,12 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     const bool use_sur = cfg->surrogate != 0;
     const int sur_collect = cfg->sur_collect_max_level;
     const int sur_da = cfg->sur_da_min_level;
-    if (use_sur) {
+    const bool sur_linear = use_sur && ctx->d_sur_S != nullptr;  // a given linear surrogate: nothing to train
+    if (sur_linear) {
+        MLS_REQUIRE(sur_da >= ctx->prob.l_min && sur_da <= ctx->prob.l_max,
+                    "run: the linear surrogate needs l_min <= sur_da_min_level <= l_max");
+        MLS_REQUIRE(cfg->kernel == MLS2MC_KERNEL_PCN, "run: delayed acceptance is built for the pCN kernel");
+    } else if (use_sur) {
         MLS_REQUIRE(sur_da > ctx->prob.l_min && sur_da <= ctx->prob.l_max && sur_collect < sur_da,
                     "run: surrogate needs l_min < sur_da_min_level <= l_max and sur_collect_max_level < sur_da_min_level");
         MLS_REQUIRE(cfg->kernel == MLS2MC_KERNEL_PCN, "run: delayed acceptance is built for the pCN kernel");
@@ -144,14 +149,14 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
     res->sur_err_mean = res->sur_err_max = 0.0;
     res->sur_err_count = 0;
     double sur_err_sum = 0.0;
-    bool sur_ready = false;
+    bool sur_ready = sur_linear;
     // the delayed-acceptance steps accumulate the surrogate's error here while the run lasts
     struct ErrSlot {
         mls2mc_ctx* c;
         ~ErrSlot() { c->da_err = nullptr; }
     } err_slot{ctx};
     ctx->da_err = use_sur ? R.sur_err : nullptr;
-    if (use_sur) {
+    if (use_sur && !sur_linear) {
         MLS_TRY(mls2mc_surrogate_init(ctx, cfg->sur_hidden > 0 ? cfg->sur_hidden : 256,
                                       cfg->sur_pairs > 0 ? cfg->sur_pairs : 20480, cfg->seed ^ 0x51u, stream));
     }
@@ -208,7 +213,7 @@ extern "C" int mls2mc_run(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, const d
             }
             MLS_TRY(mls2mc_pcn_step(ctx, &st, J, R.theta, R.Glo, R.Ghi, R.plo, R.phi, y, R.xi, R.upcn,
                                     R.acc, stream));
-            if (use_sur && !bridge && l <= sur_collect) {  // proposals and their solves -> training pairs
+            if (use_sur && !sur_linear && !bridge && l <= sur_collect) {  // proposals and their solves -> training pairs
                 const double* thn = ctx->ws_pcn.as<double>();
                 MLS_TRY(mls2mc_surrogate_add_pairs(ctx, J, thn, thn + (size_t)J * K, stream));
             }

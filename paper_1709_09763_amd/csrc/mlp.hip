@@ -570,10 +570,12 @@ int mls2mc_surrogate_train(mls2mc_ctx* ctx, int epochs, int batch, double lr, ui
 
 int mls2mc_surrogate_predict(mls2mc_ctx* ctx, int64_t N, const double* theta, double* G_out, void* stream)
 {
-    MLS_REQUIRE(ctx && ctx->sur, "surrogate_predict: call mls2mc_surrogate_init first");
+    MLS_REQUIRE(ctx && (ctx->sur || ctx->d_sur_S), "surrogate_predict: call mls2mc_surrogate_init first");
     MLS_REQUIRE(N >= 0, "surrogate_predict: N < 0");
     if (N == 0) return MLS2MC_OK;
     MLS_REQUIRE(theta && G_out, "surrogate_predict: null pointer");
+    if (ctx->d_sur_S)  // the linear surrogate
+        return launch_linear_map(N, ctx->prob.K, ctx->nobs, ctx->d_sur_S, theta, G_out, (hipStream_t)stream);
     Surrogate* S = ctx->sur;
     const hipStream_t s = (hipStream_t)stream;
     const int64_t chunk = 4096;
@@ -622,7 +624,8 @@ int mls2mc_pcn_step_da(mls2mc_ctx* ctx, const mls2mc_stage* st, int64_t N, doubl
                        int64_t* n_solved_lo, int64_t* n_solved_hi, void* stream)
 {
     MLS_REQUIRE(ctx != nullptr && st != nullptr, "pcn_step_da: null argument");
-    MLS_REQUIRE(ctx->sur != nullptr, "pcn_step_da: no surrogate (mls2mc_surrogate_init)");
+    MLS_REQUIRE(ctx->sur != nullptr || ctx->d_sur_S != nullptr,
+                "pcn_step_da: no surrogate (mls2mc_surrogate_init or mls2mc_set_linear_surrogate)");
     MLS_REQUIRE(st->kernel == MLS2MC_KERNEL_PCN, "pcn_step_da: delayed acceptance is built for the pCN kernel");
     MLS_REQUIRE(st->l_lo >= ctx->prob.l_min && st->l_lo <= ctx->prob.l_max, "pcn_step_da: level outside the context");
     const bool bridge = st->l_hi != st->l_lo;

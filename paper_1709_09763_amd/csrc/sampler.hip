@@ -207,6 +207,16 @@ int launch_linear_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta
     return MLS2MC_OK;
 }
 
+// G = S theta for N rows (the linear surrogate; S is N_obs x K)
+int launch_linear_map(int64_t N, int K, int nobs, const double* S, const double* theta, double* G, hipStream_t s)
+{
+    if (N == 0) return MLS2MC_OK;
+    linear_forward_kernel<<<(unsigned)((N + 127) / 128), 128, 0, s>>>(N, nullptr, K, nobs, 0.0, S, S, theta, G,
+                                                                      nullptr, 0.0, nullptr, nullptr, nullptr);
+    MLS_CHECK_HIP(hipGetLastError());
+    return MLS2MC_OK;
+}
+
 // ------------------------------------------------------------- resample --
 // Exact integer CDF (see mls2mc.h).  One workgroup; thread k owns the
 // contiguous chunk [k N / BS, (k+1) N / BS) for the quantised prefix sums.

@@ -143,6 +143,49 @@ def test_linear_run_matches_oracle(cfg):
         assert g["final_level"] == 1  # identical levels: u' stops on the coarsest one
 
 
+@pytest.mark.parametrize("cfg", [
+    dict(name="single level", l_min=3, l_max=3, dep=1.0, scheme=0),
+    dict(name="MLS2MC 4 levels", l_min=2, l_max=5, dep=30.0, scheme=0),
+    dict(name="multilevel bridging", l_min=2, l_max=5, dep=3.0, scheme=1),
+])
+def test_linear_delayed_acceptance_run_matches_oracle(cfg):
+    """Whole delayed-acceptance runs: a linear surrogate G~ = S theta screens
+    every pCN move (tempering and bridging, from the coarsest level on), the
+    linear model judges the survivors.  Stage for stage the same stage types,
+    levels, steps, first-stage passes and acceptances as the oracle's
+    sampler with the same surrogate, the same evidence and particles.  (The
+    oracle evaluates every proposal, the library only the survivors, so
+    their solve counts differ by design.)"""
+    device()
+    case(f"linear delayed-acceptance run {cfg['name']}")
+    s, J = 0.15, 1000
+    A, E, y = _lin_problem(K=2, nobs=4, s=s, seed=3)
+    E = cfg["dep"] * E
+    S = A + 0.3 * inputs.rng(31).standard_normal(A.shape)  # a surrogate that is off by a fair margin
+    c = P.Context(cfg["l_min"], cfg["l_max"], 2, 1.0, 0.3, 2, s)
+    c.set_linear_model(A, E)
+    c.set_linear_surrogate(S)
+    kw = dict(scheme=cfg["scheme"])
+    g = c.run(to_dev(y), J, J_tilde=100, seed=9, surrogate=True, sur_da_min_level=cfg["l_min"], **kw)
+    r = oracle.run_sampler(y, model="linear", l_min=cfg["l_min"], l_max=cfg["l_max"], K=2, nobs=4, sigma_n=s,
+                           J=J, J_tilde=100, seed=9, lin_A=A, lin_E=E, da_S=S, **kw)
+    print(f"  stages {g['n_stages']} / {r['n_stages']}, stage-1 passes {g['stage1_passed']} / "
+          f"{r['stage1_passed']} of {g['da_proposed']}, accepted {g['accepted']} / {r['accepted']}")
+    assert g["n_stages"] == r["n_stages"] and g["final_level"] == r["final_level"]
+    np.testing.assert_array_equal(g["stage_type"], r["stage_type"])
+    np.testing.assert_array_equal(g["stage_level"], r["stage_level"])
+    np.testing.assert_allclose(g["stage_beta"], r["stage_beta"], rtol=1e-12)
+    np.testing.assert_allclose(g["stage_zeta"], r["stage_zeta"], rtol=1e-12, atol=1e-15)
+    assert g["da_proposed"] == g["proposed"] == r["proposed"]  # every move was screened
+    assert g["stage1_passed"] == r["stage1_passed"] and 0 < g["stage1_passed"] < g["da_proposed"]
+    assert g["accepted"] == r["accepted"]
+    assert abs(g["log_Z"] - r["log_Z"]) < 1e-10 * max(1, abs(r["log_Z"]))
+    assert rel_err(host(g["theta"]), r["theta"]) < 1e-12
+    assert g["sur_err_count"] == g["stage1_passed"] and g["sur_err_mean"] > 0
+    c.set_linear_surrogate(None)
+    c.set_linear_model()
+
+
 def _closed_form_check(runs, m, C, logZ, R):
     means = np.array([host(r["theta"]).mean(0) for r in runs])
     vars_ = np.array([host(r["theta"]).var(0) for r in runs])
