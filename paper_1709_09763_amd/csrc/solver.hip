@@ -658,40 +658,20 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
         yr[0] = in ? wy[c] : W(0);
         yr[1] = in ? wy[c + 1] : W(0);
     };
-    // On the finest level the next row's weights, right-hand side and
-    // update direction are loaded one step ahead, so that their round trip
-    // overlaps the step's barrier (same-box A/B: +1.2 % FP64 and +1.7 %
-    // mixed at h = 1/512)
-    W xn[3], yn[2];
-    T bn[2], qn[2], bc[2] = {T(0), T(0)}, qc[2] = {T(0), T(0)};
-    auto load_bq = [&](int jj, T* bb, T* qq) {
-        const bool in = jj >= 1 && jj <= n - 1 && jj <= j1 + 2;
-        const int c = jj * s + ca;
-        bb[0] = in ? gb[c] : T(0);
-        bb[1] = in ? gb[c + 1] : T(0);
-        const bool inq = Q && in && jj < j1;
-        qq[0] = inq ? gQ[c] : T(0);
-        qq[1] = inq ? gQ[c + 1] : T(0);
-    };
     if constexpr (win) {
         load_w(j0 - 4, x0, y0);
 #pragma unroll
         for (int u = 0; u < 3; ++u) x1[u] = x2[u] = W(0);
         y1[0] = y1[1] = y2[0] = y2[1] = y3[0] = y3[1] = W(0);
-        load_w(j0 - 3, xn, yn);
-        load_bq(j0 - 3, bn, qn);
     }
     auto body = [&](auto par, int j) {
         constexpr int k = decltype(par)::value;  // the active column: ca + k
         r2[0] = r1[0]; r2[1] = r1[1]; r1[0] = r0[0]; r1[1] = r0[1]; r0[0] = T(0); r0[1] = T(0);
         if constexpr (win) {
 #pragma unroll
-            for (int u = 0; u < 3; ++u) { x2[u] = x1[u]; x1[u] = x0[u]; x0[u] = xn[u]; }
+            for (int u = 0; u < 3; ++u) { x2[u] = x1[u]; x1[u] = x0[u]; }
             y3[0] = y2[0]; y3[1] = y2[1]; y2[0] = y1[0]; y2[1] = y1[1]; y1[0] = y0[0]; y1[1] = y0[1];
-            y0[0] = yn[0]; y0[1] = yn[1];
-            bc[0] = bn[0]; bc[1] = bn[1]; qc[0] = qn[0]; qc[1] = qn[1];
-            load_w(j + 1, xn, yn);
-            load_bq(j + 1, bn, qn);
+            load_w(j, x0, y0);
         }
         const bool active = ca + k > 0;  // column 0 is the boundary
         auto Z = [&](int jj, int i) -> T __attribute__((address_space(3)))& { return zr[(jj & 3) * s + i]; };
@@ -703,13 +683,8 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
         if (j >= 1 && j <= n - 1 && j <= j1 + 2) {
             const int c = j * s + ca;
             if (Q && j < j1) {
-                if constexpr (win) {
-                    r0[0] = bc[0] - alpha * qc[0];
-                    r0[1] = bc[1] - alpha * qc[1];
-                } else {
-                    r0[0] = gb[c] - alpha * gQ[c];
-                    r0[1] = gb[c + 1] - alpha * gQ[c + 1];
-                }
+                r0[0] = gb[c] - alpha * gQ[c];
+                r0[1] = gb[c + 1] - alpha * gQ[c + 1];
                 if (j >= j0) {
                     if (ca > 0) gb[c] = r0[0];
                     gb[c + 1] = r0[1];
@@ -719,13 +694,8 @@ __device__ void walk_down(const Lv<T, W>& L, const Lv<T>& C, T* __restrict__ b, 
                     }
                 }
             } else {  // no update, or rows above the band (updated there already)
-                if constexpr (win) {
-                    r0[0] = bc[0];
-                    r0[1] = bc[1];
-                } else {
-                    r0[0] = gb[c];
-                    r0[1] = gb[c + 1];
-                }
+                r0[0] = gb[c];
+                r0[1] = gb[c + 1];
             }
             if (active)
                 Z(j, ca + k) = r0[k] / (WX(j, 0, k) + WX(j, 0, k + 1) + WY(j, 1, k) + WY(j, 0, k));
