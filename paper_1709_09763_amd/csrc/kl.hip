@@ -259,7 +259,7 @@ __global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ th
 // Operand lanes: A[i][8*(lane/16) + 0..7] with i = lane%16 (theta rows,
 // rounded to BF16); B^T[j][8*(lane/16) + 0..7] with j = lane%16 (the basis is
 // stored transposed, n_e x Kp, K padded to 32 with zeros).  Output
-// kappa = expf(a) in FP32.  Tile 64 x 64 as above.  The workgroup stages
+// kappa = e^a in FP32 (kappa_of below).  Tile 64 x 64 as above.  The workgroup stages
 // 128-deep k-chunks of its theta rows (rounded once) and basis columns in
 // LDS, so K <= 128 takes a single global round trip.
 constexpr int kBfKC = 128;
@@ -267,6 +267,42 @@ struct GemmBf16Smem {
     __bf16 a[64][kBfKC + 8];  // theta rows x k (row padding against bank conflicts)
     __bf16 b[64][kBfKC + 8];  // basis columns x k
 };
+
+// kappa = e^a in FP32 as 2^(a log2 e): one multiply and one v_exp_f32.
+// Rounding a log2 e to FP32 moves the exponent by at most |a| 2^-23
+// (relative), and v_exp_f32 adds about one unit in the last place, so
+// log kappa is within |a| 2^-23 + 2^-23 of a: under 2e-6 at |a| <= 16,
+// three orders below the BF16 rounding of the field it finishes.
+__device__ __forceinline__ float kappa_of(float a)
+{
+    return __builtin_amdgcn_exp2f(a * 1.44269504088896341f);
+}
+
+// Stores a wave's 16 x 64 block of kappa: lane (r, kq) holds rows
+// p0 + 4 kq + v of columns e0 + 16 c + r.  When the block lies inside the
+// output (every row tile but a ragged last one), the stores go without
+// per-element tests from one row pointer per v, and they are non-temporal:
+// kappa is read once, by the solver's set-up after the launch, and at the
+// large levels it is many times the size of the caches.
+__device__ __forceinline__ void store_kappa_block(const flt4 (&acc)[4], float* __restrict__ out, int64_t p0,
+                                                  int64_t e0, int64_t N, int64_t ne, int r, int kq)
+{
+    if (p0 + 16 <= N && e0 + 64 <= ne) {
+        float* o = out + (p0 + 4 * kq) * ne + e0 + r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v, o += ne)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) __builtin_nontemporal_store(kappa_of(acc[c][v]), o + 16 * c);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = p0 + 4 * kq + v, col = e0 + c * 16 + r;
+            if (row < N && col < ne) out[row * ne + col] = kappa_of(acc[c][v]);
+        }
+}
 
 __device__ __forceinline__ void gemm_bf16_tile(const double* __restrict__ theta,
                                                const __hip_bfloat16* __restrict__ Bt, float* __restrict__ out,
@@ -319,13 +355,7 @@ __device__ __forceinline__ void gemm_bf16_tile(const double* __restrict__ theta,
             }
         }
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t row = p0 + 4 * kq + v, col = e0 + c * 16 + r;
-            if (row < N && col < ne) out[row * ne + col] = expf(acc[c][v]);
-        }
+    store_kappa_block(acc, out, p0, e0, N, ne, r, kq);
 }
 
 __global__ __launch_bounds__(256) void kl_gemm_bf16(const double* __restrict__ theta,
@@ -419,14 +449,7 @@ __global__ __launch_bounds__(256) void kl_gemm_bf16_cols(const __bf16* __restric
                 acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q], b, acc[c], 0, 0, 0);
             }
         }
-        const int64_t p0 = sl * 16;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = p0 + 4 * kq + v, col = e0 + c * 16 + r;
-                if (row < N && col < ne) out[row * ne + col] = expf(acc[c][v]);
-            }
+        store_kappa_block(acc, out, sl * 16, e0, N, ne, r, kq);
     }
 }
 
