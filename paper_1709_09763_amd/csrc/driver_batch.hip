@@ -180,7 +180,7 @@ extern "C" int mls2mc_run_batch(mls2mc_ctx* ctx, const mls2mc_run_config* cfg, i
     for (int i = 0; i < n_inst; ++i) res[i].solves[I[i].l] += I[i].J;
     int64_t graphs = 0;
     int rc = MLS2MC_OK;
-    for (int round = 0; rc == MLS2MC_OK; ++round) {
+    while (rc == MLS2MC_OK) {
         // ---- A: decisions (look-ahead solves fused across instances)
         std::vector<int> check, start_lu;
         for (int i = 0; i < n_inst; ++i) {

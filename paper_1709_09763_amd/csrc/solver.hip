@@ -1146,7 +1146,6 @@ template <int BS, int WK>
 __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
-    const int64_t S = pad_sz(l);
     double *X = fine_array(M, FX), *R = fine_array(M, FR), *Z = fine_array(M, FZ), *Q = fine_array(M, FQ);
     double* Pb[2] = {fine_array(M, FP), fine_array(M, FP2)};
     const Lv<double> F = fine_level(M);  // FP64 weights: stencil apply of CG
