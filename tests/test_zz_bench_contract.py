@@ -52,3 +52,26 @@ def test_default_line_keeps_the_contract(monkeypatch, capsys):
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3 and 0 < rf["frac"] < 1.2
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
+
+
+def test_committed_shapes_and_counter_summary_match_the_solver_source():
+    """The default line takes its solver launch shapes from the committed
+    tuned-shape file and its measured HBM bytes from the committed counter
+    summary, each only when it was made for the current solver source (and,
+    for the bytes, the same launch shape).  A solver edit without a retune
+    and a fresh summary would silently fall back to autotuning and a null
+    `traffic`; this keeps the committed files in step with the source."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sha = bench.solver_sha()
+    for name in ("mi355x_h16-512_K200_J8192.json", "mi355x_h8-64_K50_J1000.json"):
+        rec = json.load(open(os.path.join(root, "paper_1709_09763_amd", "tuned", name)))
+        assert rec["solver_source_sha256_16"] == sha, name
+        assert rec["device_key"] == "gfx950:256cu"
+    rec = json.load(open(os.path.join(root, "paper_1709_09763_amd", "tuned", "mi355x_h16-512_K200_J8192.json")))
+    summary = os.path.join(root, "profiles", "solve_h512_K200_J8192_pmc.md")
+    for form in ("fp64", "mixed"):
+        sh = rec[form]["9"]
+        shape = (sh["grid"], sh["block"], sh["nu"], sh["lds"])
+        t = bench.measured_traffic(summary, shape, form)
+        assert t is not None and 1e12 < t < 3e12, (form, shape)
