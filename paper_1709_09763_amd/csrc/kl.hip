@@ -234,6 +234,17 @@ __device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ theta, 
                 acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.b[ks + kq][c * 16 + r], acc[c], 0, 0, 0);
         }
     }
+    // lane (r, kq) holds rows p0 + kq + 4 v of columns e0 + 16 c + r; a block
+    // inside the output is stored without per-element tests and, as in the
+    // BF16 kernels, non-temporally (the field is read once, after the launch)
+    if (p0 + 16 <= N && e0 + 64 <= ne) {
+        double* o = out + (p0 + kq) * ne + e0 + r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v, o += 4 * ne)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) __builtin_nontemporal_store(EXP ? exp(acc[c][v]) : acc[c][v], o + 16 * c);
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
