@@ -173,43 +173,54 @@ int build_kl_tables(mls2mc_ctx* ctx)
 
 // ----------------------------------------------------------------- GEMM --
 // FP64 on the matrix cores: v_mfma_f64_16x16x4f64.  A workgroup of four
-// waves computes a 64 (particles) x 64 (elements) tile; wave w owns rows
-// 16w..16w+15 and four 16x16 accumulators.  Operand lanes: A[i][k] with
-// i = lane%16, k = lane/16; B[k][j] with j = lane%16, k = lane/16.  Result:
-// lane holds D[lane/16 + 4v][lane%16], v = 0..3 (FP64 accumulator layout).
-// The workgroup stages 16-deep k-chunks of its 64 theta rows and 64 basis
-// columns through LDS (coalesced loads, the next chunk prefetched into
-// registers while the current one feeds the MFMAs), so a global round trip
-// is paid once per 16 k instead of once per MFMA step.
+// waves computes a 64 RT (particles) x 64 (elements) tile; wave w owns rows
+// 16 RT w .. 16 RT (w + 1) - 1 in RT row tiles of 16, each with four 16x16
+// accumulators.  Operand lanes: A[i][k] with i = lane%16, k = lane/16;
+// B[k][j] with j = lane%16, k = lane/16.  Result: lane holds
+// D[lane/16 + 4v][lane%16], v = 0..3 (FP64 accumulator layout).  The
+// workgroup stages 16-deep k-chunks of its theta rows and 64 basis columns
+// through LDS (coalesced loads, the next chunk prefetched into registers
+// while the current one feeds the MFMAs), so a global round trip is paid
+// once per 16 k instead of once per MFMA step.  With RT = 2 every basis
+// operand read from LDS feeds two MFMAs and every staged basis chunk serves
+// 128 particles; the per-element k order is the same for every RT, so the
+// results are bitwise those of RT = 1.
 constexpr int kGemmKC = 16;
-struct GemmF64Smem {
-    double a[64][kGemmKC + 1];  // theta rows x k (padded against bank conflicts)
-    double b[kGemmKC][64 + 1];  // k x basis columns
+template <int RT>
+struct GemmF64SmemT {
+    double a[64 * RT][kGemmKC + 1];  // theta rows x k (padded against bank conflicts)
+    double b[kGemmKC][64 + 1];       // k x basis columns
 };
+using GemmF64Smem = GemmF64SmemT<1>;
 
-template <bool EXP>
+template <bool EXP, int RT = 1>
 __device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ theta, const double* __restrict__ B,
                                               double* __restrict__ out, int64_t N, int K, int64_t ne,
-                                              int64_t bx, int64_t by, GemmF64Smem& sm)
+                                              int64_t bx, int64_t by, GemmF64SmemT<RT>& sm)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, kq = lane >> 4;
     const int64_t e0 = bx * 64;
-    const int64_t pb = by * 64;
-    const int64_t p0 = pb + wv * 16;
-    dbl4 acc[4];
+    const int64_t pb = by * 64 * RT;
+    dbl4 acc[RT][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // each thread moves 4 theta and 4 basis values per chunk
-    double ra[4], rb[4];
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[rt][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // each thread moves 4 RT theta and 4 basis values per chunk
+    double ra[4 * RT], rb[4];
     auto fetch = [&](int kc) {
+#pragma unroll
+        for (int t = 0; t < 4 * RT; ++t) {
+            const int idx = tid + 256 * t;
+            const int row = idx >> 4, kk = idx & 15;          // theta: 64 RT rows x 16 k
+            const int k = kc + kk;
+            ra[t] = (pb + row < N && k < K) ? theta[(pb + row) * K + k] : 0.0;
+        }
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const int idx = tid + 256 * t;
-            const int row = idx >> 4, kk = idx & 15;          // theta: 64 rows x 16 k
-            const int k = kc + kk;
-            ra[t] = (pb + row < N && k < K) ? theta[(pb + row) * K + k] : 0.0;
             const int kb = idx >> 6, col = idx & 63;         // basis: 16 k x 64 columns
             const int k2 = kc + kb;
             rb[t] = (k2 < K && e0 + col < ne) ? B[(int64_t)k2 * ne + e0 + col] : 0.0;
@@ -219,51 +230,72 @@ __device__ __forceinline__ void gemm_f64_tile(const double* __restrict__ theta, 
     for (int kc = 0; kc < K; kc += kGemmKC) {
         __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < 4 * RT; ++t) {
             const int idx = tid + 256 * t;
             sm.a[idx >> 4][idx & 15] = ra[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int idx = tid + 256 * t;
             sm.b[idx >> 6][idx & 63] = rb[t];
         }
         __syncthreads();
         if (kc + kGemmKC < K) fetch(kc + kGemmKC);
 #pragma unroll
         for (int ks = 0; ks < kGemmKC; ks += 4) {
-            const double a = sm.a[wv * 16 + r][ks + kq];
+            double a[RT];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sm.b[ks + kq][c * 16 + r], acc[c], 0, 0, 0);
+            for (int rt = 0; rt < RT; ++rt) a[rt] = sm.a[wv * 16 * RT + 16 * rt + r][ks + kq];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double b = sm.b[ks + kq][c * 16 + r];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt], b, acc[rt][c], 0, 0, 0);
+            }
         }
     }
-    // lane (r, kq) holds rows p0 + kq + 4 v of columns e0 + 16 c + r; a block
-    // inside the output is stored without per-element tests and, as in the
-    // BF16 kernels, non-temporally (the field is read once, after the launch)
-    if (p0 + 16 <= N && e0 + 64 <= ne) {
-        double* o = out + (p0 + kq) * ne + e0 + r;
 #pragma unroll
-        for (int v = 0; v < 4; ++v, o += 4 * ne)
+    for (int rt = 0; rt < RT; ++rt) {
+        const int64_t p0 = pb + wv * 16 * RT + 16 * rt;
+        // lane (r, kq) holds rows p0 + kq + 4 v of columns e0 + 16 c + r; a
+        // block inside the output is stored without per-element tests and, as
+        // in the BF16 kernels, non-temporally (the field is read once, after
+        // the launch)
+        if (p0 + 16 <= N && e0 + 64 <= ne) {
+            double* o = out + (p0 + kq) * ne + e0 + r;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) __builtin_nontemporal_store(EXP ? exp(acc[c][v]) : acc[c][v], o + 16 * c);
-        return;
-    }
+            for (int v = 0; v < 4; ++v, o += 4 * ne)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t row = p0 + kq + 4 * v, col = e0 + c * 16 + r;
-            if (row < N && col < ne) out[row * ne + col] = EXP ? exp(acc[c][v]) : acc[c][v];
+                for (int c = 0; c < 4; ++c)
+                    __builtin_nontemporal_store(EXP ? exp(acc[rt][c][v]) : acc[rt][c][v], o + 16 * c);
+            continue;
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = p0 + kq + 4 * v, col = e0 + c * 16 + r;
+                if (row < N && col < ne) out[row * ne + col] = EXP ? exp(acc[rt][c][v]) : acc[rt][c][v];
+            }
+    }
 }
 
-template <bool EXP>
-__global__ __launch_bounds__(256) void kl_gemm_f64(const double* __restrict__ theta,
+// Three waves per SIMD (at most 168 registers): the 128-particle tile then
+// keeps its accumulators in VGPRs without spilling, and a third wave hides
+// the epilogue's FP64 exp behind the other waves' MFMAs (same-box A/B at
+// h = 1/512, K = 200, N = 2048: 9.9 ms with the compiler's two waves,
+// 9.1 ms with three)
+template <bool EXP, int RT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void kl_gemm_f64(const double* __restrict__ theta,
                                                    const double* __restrict__ B,
                                                    double* __restrict__ out, int64_t N, int K,
                                                    int64_t ne, const int64_t* __restrict__ N_dev)
 {
-    __shared__ GemmF64Smem sm;
+    __shared__ GemmF64SmemT<RT> sm;
     if (N_dev) N = min(N, *N_dev);
-    if ((int64_t)blockIdx.y * 64 >= N) return;
-    gemm_f64_tile<EXP>(theta, B, out, N, K, ne, blockIdx.x, blockIdx.y, sm);
+    if ((int64_t)blockIdx.y * 64 * RT >= N) return;
+    gemm_f64_tile<EXP, RT>(theta, B, out, N, K, ne, blockIdx.x, blockIdx.y, sm);
 }
 
 // BF16 on the matrix cores with FP32 accumulation: v_mfma_f32_16x16x32_bf16.
@@ -505,12 +537,21 @@ int launch_kl_field(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, void
     const int K = ctx->prob.K;
     MLS_REQUIRE((N + 63) / 64 <= 65535, "kl_field: N too large for one launch");
     dim3 grid((unsigned)((ne + 63) / 64), (unsigned)((N + 63) / 64));
+    // FP64: 128-particle tiles once there are more than 64 particles
+    dim3 grid2((unsigned)((ne + 63) / 64), (unsigned)((N + 127) / 128));
     ProfRec rec;
     if (ctx->prof_on) MLS_TRY(prof_begin(ctx, MLS2MC_PROF_GEMM, l, N, s, &rec));
-    if (kind == MLS2MC_FIELD_LOG_F64) {
-        kl_gemm_f64<false><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne, N_dev);
-    } else if (kind == MLS2MC_FIELD_KAPPA_F64) {
-        kl_gemm_f64<true><<<grid, 256, 0, s>>>(theta, ctx->d_B[l], (double*)out, N, K, ne, N_dev);
+    if (kind == MLS2MC_FIELD_LOG_F64 || kind == MLS2MC_FIELD_KAPPA_F64) {
+        const double* Bl = ctx->d_B[l];
+        double* o = (double*)out;
+        const bool e = kind == MLS2MC_FIELD_KAPPA_F64;
+        if (N <= 64) {
+            if (e) kl_gemm_f64<true, 1><<<grid, 256, 0, s>>>(theta, Bl, o, N, K, ne, N_dev);
+            else kl_gemm_f64<false, 1><<<grid, 256, 0, s>>>(theta, Bl, o, N, K, ne, N_dev);
+        } else {
+            if (e) kl_gemm_f64<true, 2><<<grid2, 256, 0, s>>>(theta, Bl, o, N, K, ne, N_dev);
+            else kl_gemm_f64<false, 2><<<grid2, 256, 0, s>>>(theta, Bl, o, N, K, ne, N_dev);
+        }
     } else if (kind == MLS2MC_FIELD_KAPPA_F32) {
         MLS_REQUIRE(ctx->d_B16[l] != nullptr, "kl_field: BF16 basis needs precision MIXED");
         const int Kp = (K + 31) / 32 * 32;
