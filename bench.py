@@ -32,15 +32,19 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# algorithmic bytes per fine-level unknown per PCG iteration of the FP64
+# algorithmic bytes per fine-level unknown per PCG iteration of the
 # multigrid-PCG: PCG vector work + V(1,1) cycle, each array read once and
-# written once per sweep, coarse levels included (293 B); each further
-# smoothing step per side adds two sweeps reading x, b and the two weight
-# arrays and writing x, over all levels (2 x 5 x 8 x 4/3 = 106.7 B).
-# Half of both with FP32 inner arrays.
+# written once per sweep, coarse levels included (293 B with the iterate
+# x); each further smoothing step per side adds two sweeps reading x, b and
+# the two weight arrays and writing x, over all levels (2 x 5 x 8 x 4/3 =
+# 106.7 B).  The FP64 forward gathers the observations from the search
+# directions and never stores x, so its model drops x's read and write
+# (16 B: 277 B).  The mixed form keeps its iterate; half of 293 B with its
+# FP32 inner arrays.
 def b_iter(nu, fp32=False):
-    b = 293.0 + 106.7 * (max(1, nu) - 1)
-    return b / 2 if fp32 else b
+    if fp32:
+        return (293.0 + 106.7 * (max(1, nu) - 1)) / 2
+    return 277.0 + 106.7 * (max(1, nu) - 1)
 
 
 B_ITER_FP64 = b_iter(1)

@@ -1100,22 +1100,43 @@ struct Common {
     int nu;
 };
 
-template <int BS, typename T>
+// J.G[o] += alpha (observation o of p): the observations of the iterate
+// gathered step by step (thread o owns observation o, as in
+// observe_and_store)
+template <int BS>
+__device__ void observe_step(const Job& J, const Common& C, const double* P, double alpha)
+{
+    for (int o = threadIdx.x; o < C.nobs; o += BS) {
+        double g = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g += J.obs_w[3 * o + k] * P[J.obs_idx[3 * o + k]];
+        J.G[o] += alpha * g;
+    }
+}
+
+// Observations, potential, status.  FROM_X: the observations are taken
+// from the solution X; otherwise J.G already holds them (observe_step) and
+// X is not read.
+template <int BS, bool FROM_X = true, typename T>
 __device__ void observe_and_store(const Job& J, const Common& C, const T* X, int n, int8_t st, int it,
                                   double* red)
 {
     double ph = 0.0;
     for (int o = threadIdx.x; o < C.nobs; o += BS) {
         double g = 0.0;
+        if constexpr (FROM_X) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) g += J.obs_w[3 * o + k] * (double)X[J.obs_idx[3 * o + k]];
-        J.G[o] = g;
+            for (int k = 0; k < 3; ++k) g += J.obs_w[3 * o + k] * (double)X[J.obs_idx[3 * o + k]];
+            J.G[o] = g;
+        } else {
+            g = J.G[o];
+        }
         if (J.y) {
             const double r = (J.y[o] - g) * C.inv_sigma;
             ph += r * r;
         }
     }
-    if (J.p_out) {
+    if (FROM_X && J.p_out) {
         const int64_t M = (int64_t)(n - 1) * (n - 1);
         for (int64_t t = threadIdx.x; t < M; t += BS) {
             const int j = 1 + (int)(t / (n - 1)), i = 1 + (int)(t % (n - 1));
@@ -1142,7 +1163,7 @@ __device__ inline Lv<T> fine_level(const Map<T>& M)
 }
 
 // ---------------------------------------------------------- FP64 solve --
-template <int BS, int WK>
+template <int BS, int WK, bool KEEP_X>
 __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& C, double* red)
 {
     const int l = J.l;
@@ -1169,7 +1190,19 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
     setup_hierarchy<BS>(M, F, kap, FV.wx, FV.wy, walks);
     if (l == 2) build_coarse_inverse<BS>(FV, M.cinv);
     else if (l >= 3) build_coarse_inverse<BS>(coarse_level(M, 2), M.cinv);
-    MLS_FOR_INTERIOR(F, { X[c] = 0.0; R[c] = h2; })
+    // The forward map needs the solution only at the observation points
+    // unless the whole field is asked for (p_out; KEEP_X).  G = Obs x is
+    // linear in x = sum_k alpha_k p_k, so without p_out each step adds
+    // alpha_k Obs p_k to G as soon as alpha_k is known, and x is never
+    // stored: the stencil pass then neither reads nor writes it (16 B less
+    // per unknown and iteration).
+    constexpr bool keep_x = KEEP_X;
+    MLS_FOR_INTERIOR(F, {
+        if (keep_x) X[c] = 0.0;
+        R[c] = h2;
+    })
+    if (!keep_x)
+        for (int o = threadIdx.x; o < C.nobs; o += BS) J.G[o] = 0.0;
     __syncthreads();
     if (walks) {
         vcycle_walk<BS>(M, FV, R, (const double*)nullptr, 0.0, (double*)nullptr, (const double*)nullptr, Z, Q,
@@ -1199,7 +1232,7 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         // stored at those nodes), so the pass needs no barrier in between
         double pq = 0.0;
         auto pn = [&](int q) { return fma(beta, Po[q], Z[q]); };
-        double* Xu = it > 0 ? X : nullptr;
+        double* Xu = keep_x && it > 0 ? X : nullptr;
         if (WK >= 1 && F.n >= 64 && BS % F.n == 0) {
             pq = walk_apply<BS, WK == 2>(F, Z, Po, beta, Pn, Q, Xu, xa);
         } else {
@@ -1218,6 +1251,9 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         const double alpha = rz / pq;
         xa = alpha;
         Pl = Pn;
+        // Pn is complete (the reduction's barriers) and no pass writes it
+        // before the next stencil pass
+        if (!keep_x) observe_step<BS>(J, C, Pn, alpha);
         double rzn;
         if (walks) {  // the r update rides on the down walk
             rzn = vcycle_walk<BS>(M, FV, R, Q, alpha, (double*)nullptr, (const double*)nullptr, Z, Q, true, red);
@@ -1239,11 +1275,11 @@ __device__ void solve_one_f64(const Map<double>& M, const Job& J, const Common& 
         rz = rzn;
         Po = Pn;
     }
-    if (Pl) {  // the last pending x += alpha p
+    if (Pl && keep_x) {  // the last pending x += alpha p
         MLS_FOR_INTERIOR(F, { X[c] += xa * Pl[c]; })
         __syncthreads();
     }
-    observe_and_store<BS>(J, C, X, F.n, st, it, red);
+    observe_and_store<BS, keep_x>(J, C, X, F.n, st, it, red);
 }
 
 // --------------------------------------------------------- mixed solve --
@@ -1415,7 +1451,11 @@ extern __shared__ __align__(16) char mls_lds[];
 // spilling.
 #define MLS_SOLVER_ATTR __attribute__((amdgpu_waves_per_eu(WK == 2 ? (MIXED ? 4 : 3) : (MIXED ? 1 : (WK ? 4 : 6)))))
 
-template <int BS, bool MIXED, int WK>
+// PX: the launch asks for the solution field (p_out), so the FP64 solve
+// keeps its iterate; without it the FP64 solve gathers only the
+// observations (separate instances: one kernel holding both variants
+// spills heavily).  The mixed solve always keeps its FP64 iterate.
+template <int BS, bool MIXED, int WK, bool PX>
 __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P)
 {
     __shared__ double red[BS / 64];
@@ -1455,7 +1495,7 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_kernel(SolveParams P
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
             double* ring = (WK == 2 && P.ring_off >= 0) ? (double*)mls_lds + P.ring_off : nullptr;
-            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C, red);
+            solve_one_f64<BS, WK, PX>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C, red);
         }
     }
     // every workgroup has drawn past the end; the last one to finish resets
@@ -1521,7 +1561,8 @@ __global__ __launch_bounds__(BS) MLS_SOLVER_ATTR void solve_list_kernel(ListPara
             double* slot = (double*)P.ws + (int64_t)blockIdx.x * P.slot_elems;
             double* cinv = P.cinv_lds ? (double*)mls_lds + P.lds_elems : slot + hier_elems(l, false);
             double* ring = (WK == 2 && P.ring_off >= 0) ? (double*)mls_lds + P.ring_off : nullptr;
-            solve_one_f64<BS, WK>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C, red);
+            solve_one_f64<BS, WK, false>(make_map(slot, (double*)mls_lds, l, P.lds_elems, cinv, ring), J, P.C,
+                                         red);  // work items carry no p_out
         }
     }
 }
@@ -1547,13 +1588,13 @@ static Common make_common(const mls2mc_ctx* ctx, int l)
 }
 
 // solve_kernel instances: WK selects the column walk of the CG stencil pass
-#define MLS_SWITCH_SOLVE(bs, MIXED, WK, grid, lds, stream, params)                               \
+#define MLS_SWITCH_SOLVE(bs, MIXED, WK, PX, grid, lds, stream, params)                           \
     switch (bs) {                                                                                \
-        case 64: solve_kernel<64, MIXED, WK><<<grid, 64, lds, stream>>>(params); break;           \
-        case 128: solve_kernel<128, MIXED, WK><<<grid, 128, lds, stream>>>(params); break;        \
-        case 256: solve_kernel<256, MIXED, WK><<<grid, 256, lds, stream>>>(params); break;        \
-        case 512: solve_kernel<512, MIXED, WK><<<grid, 512, lds, stream>>>(params); break;        \
-        case 1024: solve_kernel<1024, MIXED, WK><<<grid, 1024, lds, stream>>>(params); break;     \
+        case 64: solve_kernel<64, MIXED, WK, PX><<<grid, 64, lds, stream>>>(params); break;       \
+        case 128: solve_kernel<128, MIXED, WK, PX><<<grid, 128, lds, stream>>>(params); break;    \
+        case 256: solve_kernel<256, MIXED, WK, PX><<<grid, 256, lds, stream>>>(params); break;    \
+        case 512: solve_kernel<512, MIXED, WK, PX><<<grid, 512, lds, stream>>>(params); break;    \
+        case 1024: solve_kernel<1024, MIXED, WK, PX><<<grid, 1024, lds, stream>>>(params); break; \
         default: MLS_REQUIRE(false, "solver: unsupported block size");                           \
     }
 
@@ -1643,15 +1684,19 @@ int launch_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     // stencil pass walks columns (measured faster from there; the smaller
     // levels are latency bound)
     const bool walk = l >= 6 && bs % (1 << l) == 0;
+    const bool px = P.p_out != nullptr;
     if (fused) {
-        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 2, g, lds, s, P) }
-        else { MLS_SWITCH_SOLVE(bs, false, 2, g, lds, s, P) }
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 2, true, g, lds, s, P) }
+        else if (px) { MLS_SWITCH_SOLVE(bs, false, 2, true, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, 2, false, g, lds, s, P) }
     } else if (walk) {
-        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 1, g, lds, s, P) }
-        else { MLS_SWITCH_SOLVE(bs, false, 1, g, lds, s, P) }
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 1, true, g, lds, s, P) }
+        else if (px) { MLS_SWITCH_SOLVE(bs, false, 1, true, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, 1, false, g, lds, s, P) }
     } else {
-        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 0, g, lds, s, P) }
-        else { MLS_SWITCH_SOLVE(bs, false, 0, g, lds, s, P) }
+        if (mixed) { MLS_SWITCH_SOLVE(bs, true, 0, true, g, lds, s, P) }
+        else if (px) { MLS_SWITCH_SOLVE(bs, false, 0, true, g, lds, s, P) }
+        else { MLS_SWITCH_SOLVE(bs, false, 0, false, g, lds, s, P) }
     }
     MLS_CHECK_HIP(hipGetLastError());
     if (ctx->prof_on) {
