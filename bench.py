@@ -150,7 +150,8 @@ def solve_bytes(l, nobs, particles, iters, b_iter):
 def flow_solve_bytes(l, nobs, particles, iters, nu):
     """streaming model of the flow-cell solver's fused passes, per fine
     unknown and PCG iteration: p = z + beta p_old with q = A p 48 B (FP64
-    weights), the x/r update with the first red sweep 64 B, and on the fine
+    weights), the r update with the first red sweep 48 B (the forward keeps
+    no iterate: its observations are gathered step by step), and on the fine
     level, whose V-cycle reads FP32 weights, 120 + 128 (nu - 1) B (black
     sweep 32, restriction of the red residuals 24, black and red sweeps 64)
     plus the coarse correction: a prolongation pass of 18 B below h = 1/128,
@@ -161,7 +162,7 @@ def flow_solve_bytes(l, nobs, particles, iters, nu):
     n = 1 << l
     M = (n - 1) * (n + 1)
     correction = 18 if l < 7 else 2
-    b_iter = 48 + 64 + 120 + correction + 128 * (nu - 1) + (170 + 160 * (nu - 1)) / 3.0
+    b_iter = 48 + 48 + 120 + correction + 128 * (nu - 1) + (170 + 160 * (nu - 1)) / 3.0
     fsz = (n + 1) * (n + 3)
     slot = 9 * fsz + 4 * fsz / 3.0 + 2 * n * n / 3.0
     return particles * (8 * 2 * n * n + 8 * slot + 32 * nobs) + iters * b_iter * M

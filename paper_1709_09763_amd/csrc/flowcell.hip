@@ -440,7 +440,13 @@ __device__ double flow_walk_apply(const FLv& F, const double* __restrict__ Z, co
     return pq;
 }
 
-template <int BS, bool WK>
+// PX: the launch returns the pressure field (p_out), so the iterate U is
+// kept.  Without it the observations are gathered step by step: G = Obs U
+// with U = the lifted boundary values + sum_k alpha_k p_k, so G starts at
+// the observations of the lift and each step adds alpha_k Obs p_k, and the
+// update pass neither reads nor writes U (16 B less per unknown and
+// iteration).  Separate instances keep each variant's registers.
+template <int BS, bool WK, bool PX>
 __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
 {
     __shared__ double red[BS / 64];
@@ -470,13 +476,23 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
             if (L >= 2) flow_coarsen<BS>(C.kc, flevel(S, l, L - 1).kc, C.n / 2);
             __syncthreads();
         }
-        // lifted right-hand side; z starts with the V-cycle's first red sweep
+        // lifted right-hand side; z starts with the V-cycle's first red sweep;
+        // the Dirichlet column i = n of U holds 1 (no step changes it)
         FLOW_FOR_UNK(n, {
             const double r = i == n - 1 ? F.wx[c] : 0.0;
             R[c] = r;
             Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F32, c);
         })
+        for (int j = threadIdx.x; j <= n; j += BS) U[(j + 1) * s + n] = 1.0;
         __syncthreads();
+        double* Gq = P.G + q * P.nobs;
+        if (!PX)  // the observations of the lift; thread o owns observation o
+            for (int o = threadIdx.x; o < P.nobs; o += BS) {
+                double g = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) g += P.obs_w[3 * o + k] * U[P.obs_idx[3 * o + k]];
+                Gq[o] = g;
+            }
         // PCG
         double rz = flow_vcycle<BS>(S, l, P.nu, red);
         const double rz0 = rz;
@@ -507,8 +523,15 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
             }
             pq = block_sum<BS>(pq, red);
             const double alpha = rz / pq;
+            if (!PX)  // Pn is complete (the reduction's barriers)
+                for (int o = threadIdx.x; o < P.nobs; o += BS) {
+                    double g = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) g += P.obs_w[3 * o + k] * Pn[P.obs_idx[3 * o + k]];
+                    Gq[o] += alpha * g;
+                }
             FLOW_FOR_UNK(n, {
-                U[c] += alpha * Pn[c];
+                if (PX) U[c] += alpha * Pn[c];
                 const double r = R[c] - alpha * Q[c];
                 R[c] = r;
                 Z[c] = ((i + j) & 1) ? 0.0 : r / fdiag(F32, c);
@@ -523,21 +546,24 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
             Po = Pn;
             Pn = t;
         }
-        // the Dirichlet column i = n holds 1; observe and store
-        for (int j = threadIdx.x; j <= n; j += BS) U[(j + 1) * s + n] = 1.0;
+        // observe and store
         __syncthreads();
         double ph = 0.0;
         for (int o = threadIdx.x; o < P.nobs; o += BS) {
             double g = 0.0;
+            if (PX) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) g += P.obs_w[3 * o + k] * U[P.obs_idx[3 * o + k]];
-            P.G[q * P.nobs + o] = g;
+                for (int k = 0; k < 3; ++k) g += P.obs_w[3 * o + k] * U[P.obs_idx[3 * o + k]];
+                Gq[o] = g;
+            } else {
+                g = Gq[o];
+            }
             if (P.y) {
                 const double r = (P.y[o] - g) * P.inv_sigma;
                 ph += r * r;
             }
         }
-        if (P.p_out) {
+        if (PX && P.p_out) {
             double* po = P.p_out + q * (int64_t)(n - 1) * (n + 1);
             FLOW_FOR_UNK(n, { po[t_] = U[c]; })
         }
@@ -554,6 +580,25 @@ __global__ __launch_bounds__(BS) void flow_solve_kernel(FlowParams P)
 }  // namespace
 
 int64_t flow_unknowns(int l) { return ((int64_t(1) << l) - 1) * ((int64_t(1) << l) + 1); }
+
+#define FLOW_SWITCH(bs, walk, PX, grid, lds, stream, params)                                       \
+    switch (bs) {                                                                                \
+        case 64: flow_solve_kernel<64, false, PX><<<grid, 64, lds, stream>>>(params); break;      \
+        case 128: flow_solve_kernel<128, false, PX><<<grid, 128, lds, stream>>>(params); break;   \
+        case 256:                                                                                \
+            if (walk) flow_solve_kernel<256, true, PX><<<grid, 256, lds, stream>>>(params);       \
+            else flow_solve_kernel<256, false, PX><<<grid, 256, lds, stream>>>(params);           \
+            break;                                                                               \
+        case 512:                                                                                \
+            if (walk) flow_solve_kernel<512, true, PX><<<grid, 512, lds, stream>>>(params);       \
+            else flow_solve_kernel<512, false, PX><<<grid, 512, lds, stream>>>(params);           \
+            break;                                                                               \
+        case 1024:                                                                               \
+            if (walk) flow_solve_kernel<1024, true, PX><<<grid, 1024, lds, stream>>>(params);     \
+            else flow_solve_kernel<1024, false, PX><<<grid, 1024, lds, stream>>>(params);         \
+            break;                                                                               \
+        default: MLS_REQUIRE(false, "flow cell: unsupported block size");                        \
+    }
 
 int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
 {
@@ -596,22 +641,10 @@ int launch_flow_solve(mls2mc_ctx* ctx, const SolveArgs& a, hipStream_t s)
     // width divides the block (separate instances, so the others keep their
     // registers)
     const bool walk = l >= 6 && bs % (1 << l) == 0;
-    switch (bs) {
-        case 64: flow_solve_kernel<64, false><<<g, 64, lds, s>>>(P); break;
-        case 128: flow_solve_kernel<128, false><<<g, 128, lds, s>>>(P); break;
-        case 256:
-            if (walk) flow_solve_kernel<256, true><<<g, 256, lds, s>>>(P);
-            else flow_solve_kernel<256, false><<<g, 256, lds, s>>>(P);
-            break;
-        case 512:
-            if (walk) flow_solve_kernel<512, true><<<g, 512, lds, s>>>(P);
-            else flow_solve_kernel<512, false><<<g, 512, lds, s>>>(P);
-            break;
-        case 1024:
-            if (walk) flow_solve_kernel<1024, true><<<g, 1024, lds, s>>>(P);
-            else flow_solve_kernel<1024, false><<<g, 1024, lds, s>>>(P);
-            break;
-        default: MLS_REQUIRE(false, "flow cell: unsupported block size");
+    if (P.p_out) {
+        FLOW_SWITCH(bs, walk, true, g, lds, s, P)
+    } else {
+        FLOW_SWITCH(bs, walk, false, g, lds, s, P)
     }
     MLS_CHECK_HIP(hipGetLastError());
     if (ctx->prof_on) {

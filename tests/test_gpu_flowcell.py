@@ -239,3 +239,23 @@ def test_flowcell_run_matches_oracle_stage_by_stage(cfg):
     assert rel_err(th.mean(0), r["theta"].mean(0)) < 1e-8
     assert rel_err(th.var(0), r["theta"].var(0)) < 1e-8
     assert g["not_converged"] == 0
+
+
+@pytest.mark.parametrize("l", [3, 6, 8])
+def test_flowcell_observations_without_the_field(l):
+    """Without p_out the forward gathers G step by step from the search
+    directions (no iterate stored); with p_out it keeps the iterate.  Both
+    give the same G up to rounding, and the field-free one matches the
+    oracle on sampled particles."""
+    device()
+    m, N = 7, 40
+    case(f"flowcell G with and without the field l={l} N={N}")
+    ctx = _ctx(l, l, m=m)
+    kap = inputs.kappa_batch(310 + l, N, 2 * 4 ** l, spread=1.0)
+    G0, _, st0, it0 = ctx.forward_field(l, to_dev(kap), want_p=False)
+    G1, p1, st1, it1 = ctx.forward_field(l, to_dev(kap), want_p=True)
+    assert (host(st0) == 0).all() and (host(st1) == 0).all()
+    np.testing.assert_array_equal(host(it0), host(it1))
+    assert rel_err(host(G0), host(G1)) < 1e-13
+    idx = [0, N - 1]
+    assert rel_err(host(G0)[idx], fc.forward_kappa(l, m, kap[idx])) < 1e-10

@@ -324,3 +324,23 @@ def test_walked_levels_after_smaller_levels_in_one_context(prec):
         np.testing.assert_array_equal(outs[lv], host(G))
         fresh.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("l", [3, 6, 8])
+def test_observations_without_the_field(l):
+    """The FP64 forward without p_out gathers G = Obs x step by step from the
+    search directions and never stores x; with p_out it keeps x.  Same
+    iteration counts, the same G up to rounding, and the field-free G
+    matches the oracle on sampled particles."""
+    device()
+    m, N = 7, 40
+    case(f"forward_field G with and without the field l={l} N={N}")
+    ctx = P.Context(l, l, 4, 1.0, 0.3, m, 0.01)
+    kap = inputs.kappa_batch(320 + l, N, oracle.n_elem(l), spread=1.0)
+    G0, _, st0, it0 = ctx.forward_field(l, to_dev(kap), want_p=False)
+    G1, p1, st1, it1 = ctx.forward_field(l, to_dev(kap), want_p=True)
+    assert (host(st0) == 0).all() and (host(st1) == 0).all()
+    np.testing.assert_array_equal(host(it0), host(it1))
+    assert rel_err(host(G0), host(G1)) < 1e-13
+    idx = [0, N - 1]
+    assert rel_err(host(G0)[idx], oracle.forward_kappa(l, m, kap[idx])) < 1e-10

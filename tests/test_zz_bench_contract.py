@@ -17,19 +17,19 @@ def test_more_than_one_gpu_is_refused(monkeypatch, capsys):
 
 
 def test_flow_solver_byte_model_counts_the_fused_passes():
-    # V(1,1): 48 + 64 + 138 (fine level, FP32 V-cycle weights) + 170 / 3
+    # V(1,1): 48 + 48 + 138 (fine level, FP32 V-cycle weights) + 170 / 3
     # (coarse levels, FP64) B per unknown and iteration, nothing else when
     # the per-solve terms are left out (particles = 0)
     l, iters = 6, 10
     M = (2 ** l - 1) * (2 ** l + 1)
-    assert bench.flow_solve_bytes(l, 25, 0, iters, 1) == pytest.approx(iters * M * (112 + 138 + 170 / 3))
+    assert bench.flow_solve_bytes(l, 25, 0, iters, 1) == pytest.approx(iters * M * (96 + 138 + 170 / 3))
     assert bench.flow_solve_bytes(l, 25, 0, iters, 2) - bench.flow_solve_bytes(l, 25, 0, iters, 1) == \
         pytest.approx(iters * M * (128 + 160 / 3))
     # from h = 1/128 on the prolongation pass (18 B) becomes 2 B of coarse
     # values read inside the first black sweep
     l = 8
     M = (2 ** l - 1) * (2 ** l + 1)
-    assert bench.flow_solve_bytes(l, 49, 0, iters, 1) == pytest.approx(iters * M * (112 + 122 + 170 / 3))
+    assert bench.flow_solve_bytes(l, 49, 0, iters, 1) == pytest.approx(iters * M * (96 + 122 + 170 / 3))
 
 
 @pytest.mark.gpu
