@@ -75,3 +75,9 @@ def test_committed_shapes_and_counter_summary_match_the_solver_source():
         shape = (sh["grid"], sh["block"], sh["nu"], sh["lds"])
         t = bench.measured_traffic(summary, shape, form)
         assert t is not None and 1e12 < t < 3e12, (form, shape)
+    # and the h = 1/64 stage workload's summary for its committed h = 1/64 shape
+    rec = json.load(open(os.path.join(root, "paper_1709_09763_amd", "tuned", "mi355x_h8-64_K50_J1000.json")))
+    sh = rec["fp64"]["6"]
+    t = bench.measured_traffic(os.path.join(root, "profiles", "solve_h64_K50_J1000_pmc.md"),
+                               (sh["grid"], sh["block"], sh["nu"], sh["lds"]))
+    assert t is not None and 1e9 < t < 3e10
