@@ -173,7 +173,10 @@ int mls2mc_forward(mls2mc_ctx* ctx, int l, int64_t N, const double* theta, doubl
 /* Forward response from a given coefficient batch (skips the KL field):
  * kappa: N x n_e(l) double, one positive value per element; G_out as above;
  * p_out (N x M(l) double, may be NULL) receives the nodal solution at the
- * unknowns, M(l) = mls2mc_ctx_n_unknowns(ctx, l).                          */
+ * unknowns, M(l) = mls2mc_ctx_n_unknowns(ctx, l).  Without p_out the FP64
+ * solvers never store the solution (G is gathered from the CG search
+ * directions), so a call with p_out streams one more vector per iteration;
+ * G agrees between the two to rounding (same iterations).                  */
 int mls2mc_forward_field(mls2mc_ctx* ctx, int l, int64_t N, const double* kappa,
                          double* G_out, double* p_out, int8_t* status_out,
                          int32_t* iters_out, void* stream);
