@@ -241,15 +241,15 @@ def test_flowcell_run_matches_oracle_stage_by_stage(cfg):
     assert g["not_converged"] == 0
 
 
-@pytest.mark.parametrize("l", [3, 6, 8])
-def test_flowcell_observations_without_the_field(l):
+@pytest.mark.parametrize("l,m", [(3, 7), (6, 7), (8, 7), (5, 32)])
+def test_flowcell_observations_without_the_field(l, m):
     """Without p_out the forward gathers G step by step from the search
     directions (no iterate stored); with p_out it keeps the iterate.  Both
     give the same G up to rounding, and the field-free one matches the
     oracle on sampled particles."""
     device()
-    m, N = 7, 40
-    case(f"flowcell G with and without the field l={l} N={N}")
+    N = 40  # m = 32: 1024 observations, more than the threads of a workgroup
+    case(f"flowcell G with and without the field l={l} m={m} N={N}")
     ctx = _ctx(l, l, m=m)
     kap = inputs.kappa_batch(310 + l, N, 2 * 4 ** l, spread=1.0)
     G0, _, st0, it0 = ctx.forward_field(l, to_dev(kap), want_p=False)

@@ -326,15 +326,15 @@ def test_walked_levels_after_smaller_levels_in_one_context(prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("l", [3, 6, 8])
-def test_observations_without_the_field(l):
+@pytest.mark.parametrize("l,m", [(3, 7), (6, 7), (8, 7), (5, 32)])
+def test_observations_without_the_field(l, m):
     """The FP64 forward without p_out gathers G = Obs x step by step from the
     search directions and never stores x; with p_out it keeps x.  Same
     iteration counts, the same G up to rounding, and the field-free G
     matches the oracle on sampled particles."""
     device()
-    m, N = 7, 40
-    case(f"forward_field G with and without the field l={l} N={N}")
+    N = 40  # m = 32: 1024 observations, more than the threads of a workgroup
+    case(f"forward_field G with and without the field l={l} m={m} N={N}")
     ctx = P.Context(l, l, 4, 1.0, 0.3, m, 0.01)
     kap = inputs.kappa_batch(320 + l, N, oracle.n_elem(l), spread=1.0)
     G0, _, st0, it0 = ctx.forward_field(l, to_dev(kap), want_p=False)
