@@ -81,3 +81,35 @@ def test_committed_shapes_and_counter_summary_match_the_solver_source():
     t = bench.measured_traffic(os.path.join(root, "profiles", "solve_h64_K50_J1000_pmc.md"),
                                (sh["grid"], sh["block"], sh["nu"], sh["lds"]))
     assert t is not None and 1e9 < t < 3e10
+
+
+def test_measured_traffic_is_null_once_source_or_shape_differ(tmp_path):
+    """`traffic` on the line must come from counters of the same solver
+    source and launch shape: a summary with another source hash, or a
+    lookup with another shape or form, yields None."""
+    good = tmp_path / "good.md"
+    good.write_text(f"solver_source_sha256_16: {bench.solver_sha()}\nlaunch_shape: 256,1024,1,0\n"
+                    "traffic_bytes_per_launch: 123456789\nlaunch_shape_mixed: 512,512,1,0\n"
+                    "traffic_bytes_per_launch_mixed: 987654321\n")
+    assert bench.measured_traffic(str(good), (256, 1024, 1, 0)) == 123456789.0
+    assert bench.measured_traffic(str(good), (512, 512, 1, 0), "mixed") == 987654321.0
+    assert bench.measured_traffic(str(good), (512, 1024, 1, 0)) is None
+    assert bench.measured_traffic(str(good), (256, 1024, 1, 0), "mixed") is None
+    stale = tmp_path / "stale.md"
+    stale.write_text(good.read_text().replace(bench.solver_sha(), "0000000000000000"))
+    assert bench.measured_traffic(str(stale), (256, 1024, 1, 0)) is None
+    assert bench.measured_traffic(str(tmp_path / "missing.md"), (256, 1024, 1, 0)) is None
+
+
+def test_byte_models_per_unknown_and_iteration():
+    """The streaming models the roofline divides by: FP64 forward without its
+    iterate 277 B at V(1,1), the mixed form half of 293 B, each further
+    smoothing step 106.7 B (halved for mixed)."""
+    assert bench.b_iter(1) == pytest.approx(277.0)
+    assert bench.b_iter(2) - bench.b_iter(1) == pytest.approx(106.7)
+    assert bench.b_iter(1, True) == pytest.approx(146.5)
+    assert bench.b_iter(2, True) - bench.b_iter(1, True) == pytest.approx(53.35)
+    # per solve: kappa read, fine and coarse weights written, observations
+    n, nobs = 64, 25
+    assert bench.solve_bytes(6, nobs, 1, 0, 0) == pytest.approx(8 * 2 * n * n + (4 / 3) * 2 * 2 * n * (n - 1) * 8
+                                                              + 32 * nobs)
